@@ -1,0 +1,919 @@
+// Gradient-SDF reference implementation ("the oracle") -- TEST INFRASTRUCTURE.
+//
+// A plain, slow, single-threaded FP64 implementation of the per-frame depth
+// tracking and fusion method of Gradient-SDF (Sommer et al., CVPR 2022).  It
+// exists only so that tests, the smoke check and the CPU-baseline leg of the
+// benchmark can compare the GPU library against an obviously correct
+// reading of the paper.  The product path never links, loads or calls it.
+// It shares no code with the GPU library.
+//
+// Build: g++ -O2 -std=c++17 -ffp-contract=off -fno-fast-math -shared -fPIC
+// (-ffp-contract=off keeps the binary32 "decision arithmetic" below free of
+// fused multiply-adds, so every float operation is one IEEE rounding.)
+//
+// What follows the paper where:
+//   * SDF running weighted average ............ Sec. 3.1, Eq. (1)-(2)
+//   * gradient accumulation g <- g + w n ...... Sec. 3.2, Eq. (3)
+//   * regular grid v_j = v_s m_j .............. Sec. 3.1
+//   * 8^3 voxel blocks in a hash map ........... Sec. 3.1 (blocks), Sec. 5.1
+//   * tracking energy, weighted least squares .. Sec. 4.1, Eq. (5)
+//   * first-order Taylor distance, gradient,
+//     nearest voxel by rounding ................ Sec. 4.1, Eq. (14)-(16)
+//   * Gauss-Newton with a Cholesky solve ....... Sec. 5.1
+//   * per-pixel ray-band integration, linear
+//     weight, FALS normals, 75 deg filter ...... Sec. 5.3 (Setup)
+//
+// Readings where the paper is silent (each is listed in the design notes):
+//   * sign: psi > 0 inside objects, < 0 in free space (Sec. 3.1); the
+//     stored gradient points into the object, away from the camera.
+//   * new distance estimate d(v) = n_w . (v - p), the point-to-plane
+//     distance to the observed point p with the pixel's normal, clamped to
+//     [-T, T]; linear weight w(d) = 1 (d <= eps), (T-d)/(T-eps) (eps<d<T),
+//     0 (d >= T), eps = voxel size.
+//   * voxels along the ray within truncation: the binary32 "decision
+//     arithmetic" samples z_k = (D - T) + k (v_s/2), k = 0..2T/(v_s/2); the
+//     voxel list is the sample voxels with consecutive repeats removed.
+//   * normals: least-squares plane fit 1/z = a . [x/z, y/z, 1] on a 5x5
+//     window (the FALS idea: the 3x3 matrix depends only on pixel geometry),
+//     n = a/|a|; needs all 25 depths valid and |D_i - D_c| <= T.
+//   * nearest voxel j* = floor(p / v_s + 1/2) per axis.
+//   * tracking weight w_k: Huber IRLS weight min(1, delta/|r|).
+//   * solve (H + mu I) dxi = -b with mu = damping * tr(H)/6; pose update
+//     T <- exp(dxi^) T (left, world frame), dxi = (rho, phi).
+//   * depth pyramid: 2x2 mean when all four are valid and max-min <= T.
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <unordered_map>
+#include <vector>
+
+namespace {
+
+constexpr int kB = 8;               // voxels per block edge
+constexpr int kBV = kB * kB * kB;   // voxels per block
+
+struct Voxel {
+    double psi = 0.0;               // running weighted mean, Eq. (1)
+    double W = 0.0;                 // accumulated weight, Eq. (2)
+    double g[3] = {0.0, 0.0, 0.0};  // accumulated weighted normals, Eq. (3)
+};
+
+struct Block {
+    Voxel v[kBV];
+};
+
+struct I3 {
+    int x, y, z;
+};
+
+int floordiv8(int m) {
+    // floor(m / 8) for any sign
+    return (int)std::floor((double)m / 8.0);
+}
+
+int64_t pack_key(int bx, int by, int bz) {
+    const int64_t o = 1 << 20;
+    return ((int64_t)(bx + o) << 42) | ((int64_t)(by + o) << 21) | (int64_t)(bz + o);
+}
+
+void unpack_key(int64_t k, int* bx, int* by, int* bz) {
+    const int64_t o = 1 << 20, mask = (1 << 21) - 1;
+    *bx = (int)(((k >> 42) & mask) - o);
+    *by = (int)(((k >> 21) & mask) - o);
+    *bz = (int)((k & mask) - o);
+}
+
+int local_index(int lx, int ly, int lz) { return lx + kB * ly + kB * kB * lz; }
+
+}  // namespace
+
+extern "C" {
+
+struct OrcCam {
+    double fx, fy, cx, cy;
+    int32_t width, height;
+    double zmin, zmax;
+};
+
+struct OrcMap {
+    double vs;          // voxel size
+    double T;           // truncation distance
+    int bounded;
+    int bmin[3], bmax[3];   // half-open block range when bounded
+    std::unordered_map<int64_t, std::unique_ptr<Block>> blocks;
+};
+
+}  // extern "C"
+
+namespace {
+
+Block* find_block(const OrcMap* M, int bx, int by, int bz) {
+    auto it = M->blocks.find(pack_key(bx, by, bz));
+    return it == M->blocks.end() ? nullptr : it->second.get();
+}
+
+Voxel* find_voxel(const OrcMap* M, const I3& m) {
+    int bx = floordiv8(m.x), by = floordiv8(m.y), bz = floordiv8(m.z);
+    Block* b = find_block(M, bx, by, bz);
+    if (!b) return nullptr;
+    return &b->v[local_index(m.x - 8 * bx, m.y - 8 * by, m.z - 8 * bz)];
+}
+
+bool in_bounds(const OrcMap* M, int bx, int by, int bz) {
+    if (!M->bounded) return true;
+    return bx >= M->bmin[0] && bx < M->bmax[0] && by >= M->bmin[1] && by < M->bmax[1] &&
+           bz >= M->bmin[2] && bz < M->bmax[2];
+}
+
+// ---------------------------------------------------------------------------
+// Pixel validity (depth cut-off, Sec. 5.3) -- exact binary32 comparisons.
+// ---------------------------------------------------------------------------
+bool depth_valid(float D, const OrcCam& c) {
+    return std::isfinite(D) && D > 0.0f && D >= (float)c.zmin && D <= (float)c.zmax;
+}
+
+// ---------------------------------------------------------------------------
+// Decision arithmetic: which voxels a pixel's ray band touches (binary32).
+// ---------------------------------------------------------------------------
+struct Decision {
+    float ifx, ify, cxf, cyf, invvs, Tf, Df;
+    float R[9], t[3];
+    int nsamples;
+};
+
+Decision make_decision(const OrcMap* M, const OrcCam& c, const double* T) {
+    Decision d;
+    d.ifx = (float)(1.0 / c.fx);
+    d.ify = (float)(1.0 / c.fy);
+    d.cxf = (float)c.cx;
+    d.cyf = (float)c.cy;
+    d.invvs = (float)(1.0 / M->vs);
+    d.Tf = (float)M->T;
+    d.Df = (float)(M->vs / 2.0);
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) d.R[3 * i + j] = (float)T[4 * i + j];
+        d.t[i] = (float)T[4 * i + 3];
+    }
+    d.nsamples = (int)std::floor(2.0 * M->T / (M->vs / 2.0) + 0.5) + 1;
+    return d;
+}
+
+// Voxels sampled along the depth band [D - T, D + T] of pixel (u, v), with
+// consecutive repeats removed.
+std::vector<I3> band_voxels(const Decision& d, int u, int v, float D) {
+    std::vector<I3> out;
+    float xr = ((float)u - d.cxf) * d.ifx;
+    float yr = ((float)v - d.cyf) * d.ify;
+    for (int k = 0; k < d.nsamples; ++k) {
+        float z = (D - d.Tf) + (float)k * d.Df;
+        if (!(z > 0.0f)) continue;
+        float X = z * xr;
+        float Y = z * yr;
+        int m[3];
+        for (int i = 0; i < 3; ++i) {
+            float a = d.R[3 * i + 0] * X;
+            float b = d.R[3 * i + 1] * Y;
+            float e = d.R[3 * i + 2] * z;
+            float q = ((a + b) + e) + d.t[i];
+            float s = q * d.invvs;
+            m[i] = (int)std::floor(s + 0.5f);
+        }
+        if (out.empty() || out.back().x != m[0] || out.back().y != m[1] || out.back().z != m[2])
+            out.push_back({m[0], m[1], m[2]});
+    }
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// Small dense linear algebra in FP64.
+// ---------------------------------------------------------------------------
+// Gaussian elimination with partial pivoting for an n x n system (n <= 6).
+bool solve_dense(int n, const double* A_in, const double* b_in, double* x) {
+    double A[36], b[6];
+    std::memcpy(A, A_in, sizeof(double) * n * n);
+    std::memcpy(b, b_in, sizeof(double) * n);
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(A[r * n + c]) > std::fabs(A[p * n + c])) p = r;
+        if (A[p * n + c] == 0.0) return false;
+        if (p != c) {
+            for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[p * n + k]);
+            std::swap(b[c], b[p]);
+        }
+        for (int r = c + 1; r < n; ++r) {
+            double f = A[r * n + c] / A[c * n + c];
+            for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double s = b[r];
+        for (int k = r + 1; k < n; ++k) s -= A[r * n + k] * x[k];
+        x[r] = s / A[r * n + r];
+    }
+    return true;
+}
+
+// Cholesky factorisation A = L L^T and solve A x = b (Sec. 5.1: the GN
+// system is solved by Cholesky decomposition).
+bool cholesky_solve6(const double* A, const double* b, double* x) {
+    double L[36] = {0};
+    for (int j = 0; j < 6; ++j) {
+        double s = A[j * 6 + j];
+        for (int k = 0; k < j; ++k) s -= L[j * 6 + k] * L[j * 6 + k];
+        if (!(s > 0.0)) return false;
+        L[j * 6 + j] = std::sqrt(s);
+        for (int i = j + 1; i < 6; ++i) {
+            double t = A[i * 6 + j];
+            for (int k = 0; k < j; ++k) t -= L[i * 6 + k] * L[j * 6 + k];
+            L[i * 6 + j] = t / L[j * 6 + j];
+        }
+    }
+    double y[6];
+    for (int i = 0; i < 6; ++i) {
+        double s = b[i];
+        for (int k = 0; k < i; ++k) s -= L[i * 6 + k] * y[k];
+        y[i] = s / L[i * 6 + i];
+    }
+    for (int i = 5; i >= 0; --i) {
+        double s = y[i];
+        for (int k = i + 1; k < 6; ++k) s -= L[k * 6 + i] * x[k];
+        x[i] = s / L[i * 6 + i];
+    }
+    return true;
+}
+
+void hat(const double* w, double* K) {
+    K[0] = 0;     K[1] = -w[2]; K[2] = w[1];
+    K[3] = w[2];  K[4] = 0;     K[5] = -w[0];
+    K[6] = -w[1]; K[7] = w[0];  K[8] = 0;
+}
+
+void matmul3(const double* A, const double* B, double* C) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0;
+            for (int k = 0; k < 3; ++k) s += A[3 * i + k] * B[3 * k + j];
+            C[3 * i + j] = s;
+        }
+}
+
+// Exponential map of se(3), xi = (rho, phi): R = I + A K + B K^2,
+// V = I + B K + C K^2, t = V rho, with K = [phi]x (textbook closed form).
+void se3_exp(const double* xi, double* T) {
+    const double* rho = xi;
+    const double* phi = xi + 3;
+    double th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
+    double th = std::sqrt(th2);
+    double A, B, C;
+    if (th < 1e-4) {
+        A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+        B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+        C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+    } else {
+        A = std::sin(th) / th;
+        B = (1.0 - std::cos(th)) / th2;
+        C = (th - std::sin(th)) / (th2 * th);
+    }
+    double K[9], K2[9];
+    hat(phi, K);
+    matmul3(K, K, K2);
+    double R[9], V[9];
+    for (int i = 0; i < 9; ++i) {
+        double I = (i % 4 == 0) ? 1.0 : 0.0;
+        R[i] = I + A * K[i] + B * K2[i];
+        V[i] = I + B * K[i] + C * K2[i];
+    }
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) T[4 * i + j] = R[3 * i + j];
+        T[4 * i + 3] = V[3 * i + 0] * rho[0] + V[3 * i + 1] * rho[1] + V[3 * i + 2] * rho[2];
+    }
+}
+
+// T <- A * T for 3x4 rigid transforms.
+void compose_left(const double* A, double* T) {
+    double out[12];
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 4; ++j) {
+            double s = 0;
+            for (int k = 0; k < 3; ++k) s += A[4 * i + k] * T[4 * k + j];
+            out[4 * i + j] = s + (j == 3 ? A[4 * i + 3] : 0.0);
+        }
+    }
+    std::memcpy(T, out, sizeof(out));
+}
+
+// Left Jacobian of SE(3) as the series sum_{n>=0} ad(xi)^n / (n+1)!, with
+// ad(xi) = [[phi^, rho^], [0, phi^]] -- the definition, summed until the
+// terms vanish in double precision.
+void se3_left_jacobian(const double* xi, double* Jl) {
+    double ad[36] = {0};
+    double P[9], Rh[9];
+    hat(xi + 3, P);
+    hat(xi, Rh);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            ad[6 * i + j] = P[3 * i + j];
+            ad[6 * i + j + 3] = Rh[3 * i + j];
+            ad[6 * (i + 3) + j + 3] = P[3 * i + j];
+        }
+    double term[36] = {0};
+    for (int i = 0; i < 6; ++i) term[7 * i] = 1.0;
+    std::memcpy(Jl, term, sizeof(term));
+    for (int n = 1; n < 80; ++n) {
+        double nt[36];
+        for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 6; ++j) {
+                double s = 0;
+                for (int k = 0; k < 6; ++k) s += term[6 * i + k] * ad[6 * k + j];
+                nt[6 * i + j] = s / (double)(n + 1);
+            }
+        double mx = 0;
+        for (int i = 0; i < 36; ++i) {
+            term[i] = nt[i];
+            Jl[i] += nt[i];
+            mx = std::max(mx, std::fabs(nt[i]));
+        }
+        if (mx < 1e-300) break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Normals: least-squares plane fit on the 5x5 window (FALS idea).
+// ---------------------------------------------------------------------------
+struct Normal {
+    bool valid;
+    double n[3];     // camera frame, unit, n . x > 0
+    double cosang;   // |n . x| / |x|
+};
+
+Normal fals_normal(const float* depth, const OrcCam& c, float Tf, int u, int v) {
+    Normal r{false, {0, 0, 0}, 0};
+    const int hw = 2;
+    if (u < hw || v < hw || u >= c.width - hw || v >= c.height - hw) return r;
+    float Dc = depth[(size_t)v * c.width + u];
+    if (!depth_valid(Dc, c)) return r;
+    double A[9] = {0}, b[3] = {0};
+    for (int dv = -hw; dv <= hw; ++dv)
+        for (int du = -hw; du <= hw; ++du) {
+            float Di = depth[(size_t)(v + dv) * c.width + (u + du)];
+            if (!depth_valid(Di, c)) return r;
+            if (!(std::fabs(Di - Dc) <= Tf)) return r;   // binary32, exact here
+            double ray[3] = {((double)(u + du) - c.cx) / c.fx, ((double)(v + dv) - c.cy) / c.fy, 1.0};
+            for (int i = 0; i < 3; ++i) {
+                for (int j = 0; j < 3; ++j) A[3 * i + j] += ray[i] * ray[j];
+                b[i] += ray[i] / (double)Di;
+            }
+        }
+    double a[3];
+    if (!solve_dense(3, A, b, a)) return r;
+    double na = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    if (!(na > 0)) return r;
+    double ray[3] = {((double)u - c.cx) / c.fx, ((double)v - c.cy) / c.fy, 1.0};
+    double dot = 0, nr = 0;
+    for (int i = 0; i < 3; ++i) {
+        r.n[i] = a[i] / na;
+        dot += r.n[i] * ray[i];
+        nr += ray[i] * ray[i];
+    }
+    if (dot < 0) {   // orient away from the camera
+        for (int i = 0; i < 3; ++i) r.n[i] = -r.n[i];
+        dot = -dot;
+    }
+    r.cosang = dot / std::sqrt(nr);
+    r.valid = true;
+    return r;
+}
+
+double w_linear(double d, double eps, double T) {
+    if (d <= eps) return 1.0;
+    if (d >= T) return 0.0;
+    return (T - d) / (T - eps);
+}
+
+double huber_rho(double r, double delta) {
+    double a = std::fabs(r);
+    return a <= delta ? 0.5 * r * r : delta * a - 0.5 * delta * delta;
+}
+
+double huber_weight(double r, double delta) {
+    double a = std::fabs(r);
+    return a <= delta ? 1.0 : delta / a;
+}
+
+void transform(const double* T, const double* x, double* q) {
+    for (int i = 0; i < 3; ++i)
+        q[i] = T[4 * i] * x[0] + T[4 * i + 1] * x[1] + T[4 * i + 2] * x[2] + T[4 * i + 3];
+}
+
+I3 nearest_voxel(const double* q, double vs) {
+    return {(int)std::floor(q[0] / vs + 0.5), (int)std::floor(q[1] / vs + 0.5),
+            (int)std::floor(q[2] / vs + 0.5)};
+}
+
+// Taylor distance at q from the nearest voxel (Eq. (14)-(16)).  Returns false
+// when the voxel is not allocated or carries no observation.
+bool taylor(const OrcMap* M, const double* q, double* r, double* gh, I3* mstar, Voxel** vox) {
+    I3 m = nearest_voxel(q, M->vs);
+    Voxel* V = find_voxel(M, m);
+    if (!V || !(V->W > 0.0)) return false;
+    double ng = std::sqrt(V->g[0] * V->g[0] + V->g[1] * V->g[1] + V->g[2] * V->g[2]);
+    if (!(ng > 0.0)) return false;
+    double d = V->psi;
+    for (int i = 0; i < 3; ++i) gh[i] = V->g[i] / ng;
+    double vj[3] = {M->vs * m.x, M->vs * m.y, M->vs * m.z};
+    for (int i = 0; i < 3; ++i) d += gh[i] * (q[i] - vj[i]);
+    *r = d;
+    if (mstar) *mstar = m;
+    if (vox) *vox = V;
+    return true;
+}
+
+// Normal equations of the Huber-weighted tracking energy at pose T for one
+// depth image (values in double).  out29 = 21 upper-triangular H entries
+// (row-major), 6 of b, energy, count.
+void normal_equations(const OrcMap* M, const double* depth, const OrcCam& c, const double* T,
+                      double delta, double* out29) {
+    double H[36] = {0}, b[6] = {0}, E = 0, n = 0;
+    for (int v = 0; v < c.height; ++v)
+        for (int u = 0; u < c.width; ++u) {
+            double D = depth[(size_t)v * c.width + u];
+            if (!(std::isfinite(D) && D > 0 && (float)D >= (float)c.zmin && (float)D <= (float)c.zmax))
+                continue;
+            double x[3] = {D * ((double)u - c.cx) / c.fx, D * ((double)v - c.cy) / c.fy, D};
+            double q[3], r, gh[3];
+            transform(T, x, q);
+            if (!taylor(M, q, &r, gh, nullptr, nullptr)) continue;
+            double J[6] = {gh[0], gh[1], gh[2],
+                           q[1] * gh[2] - q[2] * gh[1],
+                           q[2] * gh[0] - q[0] * gh[2],
+                           q[0] * gh[1] - q[1] * gh[0]};
+            double w = huber_weight(r, delta);
+            for (int i = 0; i < 6; ++i) {
+                for (int j = 0; j < 6; ++j) H[6 * i + j] += w * J[i] * J[j];
+                b[i] += w * J[i] * r;
+            }
+            E += huber_rho(r, delta);
+            n += 1;
+        }
+    int k = 0;
+    for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j) out29[k++] = H[6 * i + j];
+    for (int i = 0; i < 6; ++i) out29[21 + i] = b[i];
+    out29[27] = E;
+    out29[28] = n;
+}
+
+// One damped Gauss-Newton step from the packed normal equations.  Returns
+// false (and leaves T unchanged) when the Cholesky factorisation fails.
+bool gn_step(const double* ne, double damping, double* T, double* dxi_out) {
+    double H[36];
+    int k = 0;
+    for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j) {
+            H[6 * i + j] = ne[k];
+            H[6 * j + i] = ne[k];
+            ++k;
+        }
+    double tr = 0;
+    for (int i = 0; i < 6; ++i) tr += H[7 * i];
+    double mu = damping * tr / 6.0;
+    for (int i = 0; i < 6; ++i) H[7 * i] += mu;
+    double rhs[6], dxi[6];
+    for (int i = 0; i < 6; ++i) rhs[i] = -ne[21 + i];
+    if (!cholesky_solve6(H, rhs, dxi)) return false;
+    double E[12];
+    se3_exp(dxi, E);
+    compose_left(E, T);
+    if (dxi_out) std::memcpy(dxi_out, dxi, sizeof(dxi));
+    return true;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C interface (called from Python through ctypes)
+// ===========================================================================
+extern "C" {
+
+OrcMap* orc_map_new(double voxel_size, double truncation, int bounded, const int32_t* bmin,
+                    const int32_t* bmax) {
+    OrcMap* M = new OrcMap();
+    M->vs = voxel_size;
+    M->T = truncation;
+    M->bounded = bounded;
+    for (int i = 0; i < 3; ++i) {
+        M->bmin[i] = bounded ? bmin[i] : 0;
+        M->bmax[i] = bounded ? bmax[i] : 0;
+    }
+    return M;
+}
+
+void orc_map_free(OrcMap* M) { delete M; }
+
+int64_t orc_num_blocks(const OrcMap* M) { return (int64_t)M->blocks.size(); }
+
+OrcMap* orc_map_clone(const OrcMap* M) {
+    OrcMap* C = orc_map_new(M->vs, M->T, M->bounded, M->bmin, M->bmax);
+    for (auto& kv : M->blocks) C->blocks[kv.first] = std::make_unique<Block>(*kv.second);
+    return C;
+}
+
+// Sorted (x, y, z) block keys.
+void orc_export_keys(const OrcMap* M, int32_t* out) {
+    std::vector<std::array<int, 3>> keys;
+    keys.reserve(M->blocks.size());
+    for (auto& kv : M->blocks) {
+        int x, y, z;
+        unpack_key(kv.first, &x, &y, &z);
+        keys.push_back({x, y, z});
+    }
+    std::sort(keys.begin(), keys.end());
+    for (size_t i = 0; i < keys.size(); ++i)
+        for (int j = 0; j < 3; ++j) out[3 * i + j] = keys[i][j];
+}
+
+// Voxel values of the given blocks, voxel order lx + 8 ly + 64 lz.  Missing
+// blocks read as zeros and set found[i] = 0.
+void orc_export_voxels(const OrcMap* M, const int32_t* keys, int64_t n, double* psi, double* g,
+                       double* W, int32_t* found) {
+    for (int64_t i = 0; i < n; ++i) {
+        Block* b = find_block(M, keys[3 * i], keys[3 * i + 1], keys[3 * i + 2]);
+        if (found) found[i] = b ? 1 : 0;
+        for (int j = 0; j < kBV; ++j) {
+            const Voxel* V = b ? &b->v[j] : nullptr;
+            psi[i * kBV + j] = V ? V->psi : 0.0;
+            W[i * kBV + j] = V ? V->W : 0.0;
+            for (int k = 0; k < 3; ++k) g[(i * kBV + j) * 3 + k] = V ? V->g[k] : 0.0;
+        }
+    }
+}
+
+// Set voxel values of the given blocks (creating blocks as needed).
+void orc_import_voxels(OrcMap* M, const int32_t* keys, int64_t n, const double* psi,
+                       const double* g, const double* W) {
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t key = pack_key(keys[3 * i], keys[3 * i + 1], keys[3 * i + 2]);
+        auto& slot = M->blocks[key];
+        if (!slot) slot = std::make_unique<Block>();
+        for (int j = 0; j < kBV; ++j) {
+            Voxel& V = slot->v[j];
+            V.psi = psi[i * kBV + j];
+            V.W = W[i * kBV + j];
+            for (int k = 0; k < 3; ++k) V.g[k] = g[(i * kBV + j) * 3 + k];
+        }
+    }
+}
+
+// Voxel list of one pixel's band (decision arithmetic); returns the count.
+int orc_band_voxels(const OrcMap* M, const OrcCam* cam, const double* T, int u, int v, float D,
+                    int32_t* out, int cap) {
+    Decision d = make_decision(M, *cam, T);
+    std::vector<I3> vox = band_voxels(d, u, v, D);
+    int n = (int)vox.size();
+    for (int i = 0; i < n && i < cap; ++i) {
+        out[3 * i] = vox[i].x;
+        out[3 * i + 1] = vox[i].y;
+        out[3 * i + 2] = vox[i].z;
+    }
+    return n;
+}
+
+// Allocation (Sec. 5.3 / Sec. 3.1): every block holding a band voxel of a
+// valid pixel.  Returns the number of blocks created.
+int64_t orc_allocate(OrcMap* M, const float* depth, const OrcCam* cam, const double* T) {
+    Decision d = make_decision(M, *cam, T);
+    int64_t created = 0;
+    for (int v = 0; v < cam->height; ++v)
+        for (int u = 0; u < cam->width; ++u) {
+            float D = depth[(size_t)v * cam->width + u];
+            if (!depth_valid(D, *cam)) continue;
+            for (const I3& m : band_voxels(d, u, v, D)) {
+                int bx = floordiv8(m.x), by = floordiv8(m.y), bz = floordiv8(m.z);
+                if (!in_bounds(M, bx, by, bz)) continue;
+                auto& slot = M->blocks[pack_key(bx, by, bz)];
+                if (!slot) {
+                    slot = std::make_unique<Block>();
+                    ++created;
+                }
+            }
+        }
+    return created;
+}
+
+// Normals of a depth image: n (H*W*3, camera frame), valid flag and the
+// cosine between normal and viewing ray.
+void orc_normals(const float* depth, const OrcCam* cam, double truncation, double* n_out,
+                 int32_t* valid_out, double* cos_out) {
+    float Tf = (float)truncation;
+    for (int v = 0; v < cam->height; ++v)
+        for (int u = 0; u < cam->width; ++u) {
+            size_t i = (size_t)v * cam->width + u;
+            Normal nr = fals_normal(depth, *cam, Tf, u, v);
+            valid_out[i] = nr.valid ? 1 : 0;
+            cos_out[i] = nr.cosang;
+            for (int k = 0; k < 3; ++k) n_out[3 * i + k] = nr.n[k];
+        }
+}
+
+// Fusion (Eq. (1)-(3)), observation by observation in pixel order.
+// eps: linear-weight plateau; cos_min: cosine of the maximum viewing angle.
+// marginal_out (optional, H*W): 1 where the angle test is within margin of
+// its threshold.  Returns the number of voxel updates with w > 0.
+int64_t orc_integrate(OrcMap* M, const float* depth, const OrcCam* cam, const double* T,
+                      double eps, double cos_min, double margin, int32_t* marginal_out) {
+    Decision d = make_decision(M, *cam, T);
+    float Tf = (float)M->T;
+    const double* Rm = T;
+    int64_t updates = 0;
+    for (int v = 0; v < cam->height; ++v)
+        for (int u = 0; u < cam->width; ++u) {
+            size_t pix = (size_t)v * cam->width + u;
+            if (marginal_out) marginal_out[pix] = 0;
+            float Df = depth[pix];
+            if (!depth_valid(Df, *cam)) continue;
+            Normal nr = fals_normal(depth, *cam, Tf, u, v);
+            if (!nr.valid) continue;
+            if (marginal_out && std::fabs(nr.cosang - cos_min) < margin) marginal_out[pix] = 1;
+            if (!(nr.cosang >= cos_min)) continue;
+            double D = Df;
+            double x[3] = {D * ((double)u - cam->cx) / cam->fx, D * ((double)v - cam->cy) / cam->fy, D};
+            double p[3], nw[3];
+            transform(T, x, p);
+            for (int i = 0; i < 3; ++i)
+                nw[i] = Rm[4 * i] * nr.n[0] + Rm[4 * i + 1] * nr.n[1] + Rm[4 * i + 2] * nr.n[2];
+            for (const I3& m : band_voxels(d, u, v, Df)) {
+                Voxel* V = find_voxel(M, m);
+                if (!V) continue;
+                double vj[3] = {M->vs * m.x, M->vs * m.y, M->vs * m.z};
+                double dist = nw[0] * (vj[0] - p[0]) + nw[1] * (vj[1] - p[1]) + nw[2] * (vj[2] - p[2]);
+                dist = std::min(M->T, std::max(-M->T, dist));
+                double w = w_linear(dist, eps, M->T);
+                if (!(w > 0.0)) continue;
+                V->psi = (V->W * V->psi + w * dist) / (V->W + w);   // Eq. (1)
+                V->W = V->W + w;                                      // Eq. (2)
+                for (int k = 0; k < 3; ++k) V->g[k] += w * nw[k];     // Eq. (3)
+                ++updates;
+            }
+        }
+    return updates;
+}
+
+// Depth pyramid level (binary32): mean of each 2x2 block when all four are
+// valid and their spread is within the truncation, else 0.
+void orc_pyramid_down(const float* src, const OrcCam* cam, double truncation, float* dst) {
+    int w2 = cam->width / 2, h2 = cam->height / 2;
+    float Tf = (float)truncation;
+    for (int v = 0; v < h2; ++v)
+        for (int u = 0; u < w2; ++u) {
+            float a = src[(size_t)(2 * v) * cam->width + 2 * u];
+            float b = src[(size_t)(2 * v) * cam->width + 2 * u + 1];
+            float c = src[(size_t)(2 * v + 1) * cam->width + 2 * u];
+            float e = src[(size_t)(2 * v + 1) * cam->width + 2 * u + 1];
+            bool ok = depth_valid(a, *cam) && depth_valid(b, *cam) && depth_valid(c, *cam) &&
+                      depth_valid(e, *cam);
+            float mx = std::max(std::max(a, b), std::max(c, e));
+            float mn = std::min(std::min(a, b), std::min(c, e));
+            ok = ok && (mx - mn <= Tf);
+            dst[(size_t)v * w2 + u] = ok ? ((a + b) + (c + e)) * 0.25f : 0.0f;
+        }
+}
+
+void orc_normal_equations(const OrcMap* M, const double* depth, const OrcCam* cam,
+                          const double* T, double delta, double* out29) {
+    normal_equations(M, depth, *cam, T, delta, out29);
+}
+
+// Fixed-iteration damped Gauss-Newton on one image (values in double).
+// stats (optional, iters x 2): energy and count at each linearisation.
+// Returns the number of failed (skipped) solves.
+int orc_gn_level(const OrcMap* M, const double* depth, const OrcCam* cam, int iters,
+                 double delta, double damping, double* T, double* stats) {
+    int failed = 0;
+    for (int it = 0; it < iters; ++it) {
+        double ne[29];
+        normal_equations(M, depth, *cam, T, delta, ne);
+        if (stats) {
+            stats[2 * it] = ne[27];
+            stats[2 * it + 1] = ne[28];
+        }
+        if (!gn_step(ne, damping, T, nullptr)) ++failed;
+    }
+    return failed;
+}
+
+// Coarse-to-fine tracking: pyramid (binary32), then iters[l] GN steps per
+// level from the coarsest to the finest.
+int orc_track(const OrcMap* M, const float* depth, const OrcCam* cam, int levels,
+              const int32_t* iters, double delta, double damping, double* T, double* stats) {
+    std::vector<std::vector<float>> pyr(levels);
+    std::vector<OrcCam> cams(levels);
+    pyr[0].assign(depth, depth + (size_t)cam->width * cam->height);
+    cams[0] = *cam;
+    for (int l = 1; l < levels; ++l) {
+        const OrcCam& pc = cams[l - 1];
+        OrcCam c = pc;
+        c.width = pc.width / 2;
+        c.height = pc.height / 2;
+        c.fx = pc.fx / 2;
+        c.fy = pc.fy / 2;
+        c.cx = (pc.cx + 0.5) / 2 - 0.5;
+        c.cy = (pc.cy + 0.5) / 2 - 0.5;
+        pyr[l].resize((size_t)c.width * c.height);
+        orc_pyramid_down(pyr[l - 1].data(), &pc, M->T, pyr[l].data());
+        cams[l] = c;
+    }
+    int failed = 0, s = 0;
+    for (int l = levels - 1; l >= 0; --l) {
+        std::vector<double> dd(pyr[l].begin(), pyr[l].end());
+        failed += orc_gn_level(M, dd.data(), &cams[l], iters[l], delta, damping, T,
+                               stats ? stats + 2 * s : nullptr);
+        s += iters[l];
+    }
+    return failed;
+}
+
+// ---- small numerical kernels exposed for pin tests ----
+int orc_cholesky_solve6(const double* A, const double* b, double* x) {
+    return cholesky_solve6(A, b, x) ? 1 : 0;
+}
+void orc_se3_exp(const double* xi, double* T) { se3_exp(xi, T); }
+void orc_se3_left_jacobian(const double* xi, double* Jl) { se3_left_jacobian(xi, Jl); }
+int orc_gn_step(const double* ne, double damping, double* T, double* dxi) {
+    return gn_step(ne, damping, T, dxi) ? 1 : 0;
+}
+double orc_huber_rho(double r, double delta) { return huber_rho(r, delta); }
+double orc_huber_weight(double r, double delta) { return huber_weight(r, delta); }
+double orc_w_linear(double d, double eps, double T) { return w_linear(d, eps, T); }
+void orc_nearest_voxel(const double* q, double vs, int32_t* m) {
+    I3 r = nearest_voxel(q, vs);
+    m[0] = r.x;
+    m[1] = r.y;
+    m[2] = r.z;
+}
+int orc_floordiv8(int m) { return floordiv8(m); }
+
+// Taylor residual and its gradient direction at world point q (nan if none).
+int orc_taylor(const OrcMap* M, const double* q, double* r, double* gh, int32_t* m) {
+    I3 ms;
+    if (!taylor(M, q, r, gh, &ms, nullptr)) return 0;
+    m[0] = ms.x;
+    m[1] = ms.y;
+    m[2] = ms.z;
+    return 1;
+}
+
+// ---------------------------------------------------------------------------
+// Differentiable loss over keyframes.
+//   L = sum_i sum_k rho_delta(r_ik),  T_i = exp(xi_i^) T0_i.
+// Gradients: dL/dpsi_j = sum rho'(r); dL/dg_j = sum rho'(r) (I - gh gh^T)(q - v_j)/|g_j|;
+// dL/dxi_i = Jl(xi_i)^T sum_k rho'(r_ik) [gh; q x gh].
+// The voxel parameters are the map's psi and g (W only marks observed).
+// assoc (K*H*W*3, optional): nearest-voxel association; freeze = 1 reads it,
+// freeze = 0 writes it (pixels without a usable voxel get INT32_MIN).
+// dpsi / dg (optional) are returned per block in key order of `keys`.
+// ---------------------------------------------------------------------------
+double orc_loss_grad(const OrcMap* M, int K, const double* depth, const OrcCam* cam,
+                     const double* T0, const double* xi, double delta, int32_t* assoc,
+                     int freeze, const int32_t* keys, int64_t nkeys, double* dpsi, double* dg,
+                     double* dxi) {
+    std::unordered_map<int64_t, int64_t> kidx;
+    if (keys)
+        for (int64_t i = 0; i < nkeys; ++i)
+            kidx[pack_key(keys[3 * i], keys[3 * i + 1], keys[3 * i + 2])] = i;
+    if (dpsi) std::fill(dpsi, dpsi + nkeys * kBV, 0.0);
+    if (dg) std::fill(dg, dg + nkeys * kBV * 3, 0.0);
+    double L = 0;
+    const size_t npx = (size_t)cam->width * cam->height;
+    for (int i = 0; i < K; ++i) {
+        double E[12], T[12];
+        se3_exp(xi + 6 * i, E);
+        std::memcpy(T, T0 + 12 * i, sizeof(T));
+        compose_left(E, T);
+        double gl[6] = {0};
+        for (int v = 0; v < cam->height; ++v)
+            for (int u = 0; u < cam->width; ++u) {
+                size_t pix = (size_t)v * cam->width + u;
+                double D = depth[i * npx + pix];
+                int32_t* as = assoc ? assoc + 3 * (i * npx + pix) : nullptr;
+                if (!(std::isfinite(D) && D > 0 && (float)D >= (float)cam->zmin &&
+                      (float)D <= (float)cam->zmax)) {
+                    if (as && !freeze) as[0] = as[1] = as[2] = INT32_MIN;
+                    continue;
+                }
+                double x[3] = {D * ((double)u - cam->cx) / cam->fx, D * ((double)v - cam->cy) / cam->fy, D};
+                double q[3];
+                transform(T, x, q);
+                I3 m;
+                if (as && freeze) {
+                    if (as[0] == INT32_MIN) continue;
+                    m = {as[0], as[1], as[2]};
+                } else {
+                    m = nearest_voxel(q, M->vs);
+                }
+                Voxel* V = find_voxel(M, m);
+                double ng = V ? std::sqrt(V->g[0] * V->g[0] + V->g[1] * V->g[1] + V->g[2] * V->g[2]) : 0;
+                if (!V || !(V->W > 0.0) || !(ng > 0.0)) {
+                    if (as && !freeze) as[0] = as[1] = as[2] = INT32_MIN;
+                    continue;
+                }
+                if (as && !freeze) {
+                    as[0] = m.x;
+                    as[1] = m.y;
+                    as[2] = m.z;
+                }
+                double gh[3] = {V->g[0] / ng, V->g[1] / ng, V->g[2] / ng};
+                double dq[3] = {q[0] - M->vs * m.x, q[1] - M->vs * m.y, q[2] - M->vs * m.z};
+                double r = V->psi + gh[0] * dq[0] + gh[1] * dq[1] + gh[2] * dq[2];
+                L += huber_rho(r, delta);
+                double rp = huber_weight(r, delta) * r;   // rho'(r)
+                double J[6] = {gh[0], gh[1], gh[2], q[1] * gh[2] - q[2] * gh[1],
+                               q[2] * gh[0] - q[0] * gh[2], q[0] * gh[1] - q[1] * gh[0]};
+                for (int k = 0; k < 6; ++k) gl[k] += rp * J[k];
+                if (keys && (dpsi || dg)) {
+                    int bx = floordiv8(m.x), by = floordiv8(m.y), bz = floordiv8(m.z);
+                    auto it = kidx.find(pack_key(bx, by, bz));
+                    if (it != kidx.end()) {
+                        int64_t j = it->second * kBV + local_index(m.x - 8 * bx, m.y - 8 * by, m.z - 8 * bz);
+                        if (dpsi) dpsi[j] += rp;
+                        if (dg) {
+                            double gd = gh[0] * dq[0] + gh[1] * dq[1] + gh[2] * dq[2];
+                            for (int k = 0; k < 3; ++k) dg[3 * j + k] += rp * (dq[k] - gh[k] * gd) / ng;
+                        }
+                    }
+                }
+            }
+        if (dxi) {
+            double Jl[36];
+            se3_left_jacobian(xi + 6 * i, Jl);
+            for (int a = 0; a < 6; ++a) {
+                double s = 0;
+                for (int k = 0; k < 6; ++k) s += Jl[6 * k + a] * gl[k];
+                dxi[6 * i + a] = s;
+            }
+        }
+    }
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// Test helper: ray-cast the map's own Taylor surface, i.e. the first root
+// along each ray of r(p) = psi_j* + gh_j* . (p - v_j*) with j* the nearest
+// voxel of p.  Inside one nearest-voxel cell r is linear along the ray, so
+// roots are exact.  Pixels without a root inside a cell get depth 0.
+// ---------------------------------------------------------------------------
+void orc_render_taylor(const OrcMap* M, const OrcCam* cam, const double* T, double smin,
+                       double smax, double* depth_out) {
+    const double vs = M->vs;
+    for (int v = 0; v < cam->height; ++v)
+        for (int u = 0; u < cam->width; ++u) {
+            double ray[3] = {((double)u - cam->cx) / cam->fx, ((double)v - cam->cy) / cam->fy, 1.0};
+            double o[3] = {T[3], T[7], T[11]}, d[3];
+            for (int i = 0; i < 3; ++i) d[i] = T[4 * i] * ray[0] + T[4 * i + 1] * ray[1] + T[4 * i + 2] * ray[2];
+            double s = smin, hit = 0.0;
+            bool seen_neg = false;
+            for (int step = 0; step < 100000 && s < smax; ++step) {
+                double p[3] = {o[0] + s * d[0], o[1] + s * d[1], o[2] + s * d[2]};
+                I3 m = nearest_voxel(p, vs);
+                int mm[3] = {m.x, m.y, m.z};
+                double sexit = smax;
+                for (int k = 0; k < 3; ++k) {
+                    if (d[k] > 0) sexit = std::min(sexit, ((mm[k] + 0.5) * vs - o[k]) / d[k]);
+                    else if (d[k] < 0) sexit = std::min(sexit, ((mm[k] - 0.5) * vs - o[k]) / d[k]);
+                }
+                Voxel* V = find_voxel(M, m);
+                double ng = V ? std::sqrt(V->g[0] * V->g[0] + V->g[1] * V->g[1] + V->g[2] * V->g[2]) : 0;
+                if (V && V->W > 0 && ng > 0) {
+                    double gh[3] = {V->g[0] / ng, V->g[1] / ng, V->g[2] / ng};
+                    // r(s) = a + b s
+                    double a = V->psi, b = 0;
+                    for (int k = 0; k < 3; ++k) {
+                        a += gh[k] * (o[k] - vs * mm[k]);
+                        b += gh[k] * d[k];
+                    }
+                    double r_in = a + b * s;
+                    if (r_in < 0) seen_neg = true;
+                    if (seen_neg && b > 0) {
+                        double sr = -a / b;
+                        double margin = 1e-9 * vs;
+                        if (sr > s + margin && sr < sexit - margin) {
+                            double pr[3] = {o[0] + sr * d[0], o[1] + sr * d[1], o[2] + sr * d[2]};
+                            I3 mc = nearest_voxel(pr, vs);
+                            if (mc.x == m.x && mc.y == m.y && mc.z == m.z) hit = sr;
+                            break;
+                        }
+                    }
+                    if (r_in >= 0 && seen_neg) break;   // jumped over the surface
+                }
+                s = sexit + 1e-12;
+            }
+            depth_out[(size_t)v * cam->width + u] = hit;
+        }
+}
+
+}  // extern "C"

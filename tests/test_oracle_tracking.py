@@ -1,0 +1,285 @@
+"""Oracle pins for tracking (Eq. (5), (14)-(16)), the Cholesky solve and the
+SE(3) update (Sec. 5.1), the depth pyramid, and the adjoint of the keyframe
+Huber loss.  References are textbook routines (scipy), finite differences,
+invariances and an exactly solvable rendering."""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+from paper_2111_13652_amd import synth
+from tests import scenes
+
+
+def _hat(w):
+    return np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]])
+
+
+def _twist(xi):
+    A = np.zeros((4, 4))
+    A[:3, :3] = _hat(xi[3:])
+    A[:3, 3] = xi[:3]
+    return A
+
+
+def _expm_pose(xi):
+    return sla.expm(_twist(xi))[:3]
+
+
+def _compose(A, T):
+    return np.concatenate([A[:, :3] @ T[:, :3], (A[:, :3] @ T[:, 3] + A[:, 3])[:, None]], 1)
+
+
+def test_cholesky_matches_scipy():
+    rng = np.random.default_rng(0)
+    for _ in range(50):
+        B = rng.standard_normal((6, 6))
+        A = B @ B.T + 0.1 * np.eye(6)
+        b = rng.standard_normal(6)
+        x = oracle.cholesky_solve6(A, b)
+        np.testing.assert_allclose(x, sla.cho_solve(sla.cho_factor(A), b), rtol=1e-10, atol=1e-12)
+    # not positive definite -> failure
+    assert oracle.cholesky_solve6(-np.eye(6), np.ones(6)) is None
+
+
+@pytest.mark.parametrize("scale", [1e-9, 1e-5, 1e-2, 0.5, 2.0])
+def test_se3_exp_matches_matrix_exponential(scale):
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        xi = rng.standard_normal(6) * scale
+        np.testing.assert_allclose(oracle.se3_exp(xi), _expm_pose(xi), atol=1e-13)
+
+
+def test_se3_left_jacobian_by_finite_differences():
+    # exp(xi + d) = exp(Jl(xi) d) exp(xi) + O(d^2)
+    rng = np.random.default_rng(2)
+    for _ in range(5):
+        xi = rng.standard_normal(6) * 0.4
+        Jl = oracle.se3_left_jacobian(xi)
+        E0 = np.vstack([_expm_pose(xi), [0, 0, 0, 1]])
+        h = 1e-6
+        for k in range(6):
+            e = np.zeros(6)
+            e[k] = h
+            Ep = np.vstack([_expm_pose(xi + e), [0, 0, 0, 1]])
+            Em = np.vstack([_expm_pose(xi - e), [0, 0, 0, 1]])
+            Lp = sla.logm(Ep @ np.linalg.inv(E0)).real
+            Lm = sla.logm(Em @ np.linalg.inv(E0)).real
+            col = np.concatenate([(Lp - Lm)[:3, 3], [(Lp - Lm)[2, 1], (Lp - Lm)[0, 2], (Lp - Lm)[1, 0]]]) / (2 * h)
+            np.testing.assert_allclose(Jl[:, k], col, atol=1e-7)
+    np.testing.assert_allclose(oracle.se3_left_jacobian(np.zeros(6)), np.eye(6), atol=0)
+
+
+def test_gn_step_solves_damped_system_and_left_multiplies():
+    rng = np.random.default_rng(3)
+    B = rng.standard_normal((6, 6))
+    H = B @ B.T + np.eye(6)
+    b = rng.standard_normal(6) * 0.01
+    ne = np.concatenate([H[np.triu_indices(6)], b, [1.0, 10.0]])
+    T = synth.look_at([1, 2, 1], [2, 3, 1])
+    damping = 1e-3
+    Tn, dxi = oracle.gn_step(ne, damping, T)
+    mu = damping * np.trace(H) / 6
+    np.testing.assert_allclose(dxi, np.linalg.solve(H + mu * np.eye(6), -b), rtol=1e-10)
+    np.testing.assert_allclose(Tn, _compose(_expm_pose(dxi), T), atol=1e-14)
+
+
+def _room_map(vs=0.02, T=0.1, frames=(0,), cam=None):
+    st = scenes.room_frames(cam or scenes.SMALL_CAM, max(frames) + 1)
+    M = oracle.OracleMap(vs, T)
+    for f in frames:
+        M.allocate(st.depth[f], st.cam, st.poses[f])
+        M.integrate(st.depth[f], st.cam, st.poses[f])
+    return M, st
+
+
+def test_single_pixel_normal_equations_match_finite_difference_jacobian():
+    M, st = _room_map()
+    cam = st.cam
+    T = st.poses[0]
+    rng = np.random.default_rng(4)
+    delta = 0.01
+    checked = 0
+    for _ in range(200):
+        u, v = int(rng.integers(5, cam.width - 5)), int(rng.integers(5, cam.height - 5))
+        D = float(st.depth[0][v, u]) + rng.uniform(-0.02, 0.02)
+        img = np.zeros((cam.height, cam.width))
+        img[v, u] = D
+        ne = M.normal_equations(img, cam, T, delta)
+        if ne[28] == 0:
+            continue
+        x = D * np.array([(u - cam.cx) / cam.fx, (v - cam.cy) / cam.fy, 1.0])
+        q0 = T[:, :3] @ x + T[:, 3]
+        base = M.taylor(q0)
+        r0, _, m0 = base
+        h = 1e-6
+        J = np.zeros(6)
+        ok = True
+        for k in range(6):
+            e = np.zeros(6)
+            e[k] = h
+            vals = []
+            for s in (1, -1):
+                E = _expm_pose(s * e)
+                res = M.taylor(E[:, :3] @ q0 + E[:, 3])
+                if res is None or not np.array_equal(res[2], m0):
+                    ok = False
+                    break
+                vals.append(res[0])
+            if not ok:
+                break
+            J[k] = (vals[0] - vals[1]) / (2 * h)
+        if not ok:
+            continue
+        w = min(1.0, delta / abs(r0)) if r0 != 0 else 1.0
+        Hh, bb, E, n = oracle.unpack_upper(ne)
+        np.testing.assert_allclose(Hh, w * np.outer(J, J), atol=1e-8)
+        np.testing.assert_allclose(bb, w * J * r0, atol=1e-9)
+        rho = 0.5 * r0 ** 2 if abs(r0) <= delta else delta * abs(r0) - 0.5 * delta ** 2
+        assert E == pytest.approx(rho, abs=1e-15) and n == 1
+        checked += 1
+    assert checked > 50
+
+
+def test_sign_flip_leaves_normal_equations_bit_identical():
+    M, st = _room_map()
+    keys = M.keys()
+    psi, g, W, _ = M.voxels(keys)
+    F = oracle.OracleMap(M.voxel_size, M.truncation)
+    F.set_voxels(keys, -psi, -g, W)
+    depth = st.depth[0].astype(np.float64)
+    T = st.poses[0]
+    a = M.normal_equations(depth, st.cam, T, 0.01)
+    b = F.normal_equations(depth, st.cam, T, 0.01)
+    assert a[28] > 1000
+    np.testing.assert_array_equal(a, b)
+
+
+def test_pyramid_level_geometry():
+    cam = scenes.SMALL_CAM
+    n_cam = np.array([0.4, -0.2, 1.0])
+    n_cam /= np.linalg.norm(n_cam)
+    depth = scenes.depth_image(scenes.plane_depth(cam, n_cam, 1.5), cam)
+    lvl = oracle.pyramid_down(depth, cam, 0.05)
+    # the level-1 pixel (u, v) sees the ray of level-0 position (2u+1/2, 2v+1/2),
+    # i.e. intrinsics f/2 and (c + 1/2)/2 - 1/2
+    cam1 = synth.Camera(cam.fx / 2, cam.fy / 2, (cam.cx + 0.5) / 2 - 0.5, (cam.cy + 0.5) / 2 - 0.5,
+                        cam.width // 2, cam.height // 2, cam.zmin, cam.zmax)
+    exact = scenes.plane_depth(cam1, n_cam, 1.5)
+    ok = lvl > 0
+    assert ok.mean() > 0.95
+    # the 2x2 mean of a smooth depth differs from the centre ray's depth only
+    # by its curvature: far below the slope times half a pixel (~1e-2 m)
+    assert np.abs(lvl[ok] - exact[ok]).max() < 1e-4
+    # constant images stay constant and exactly representable
+    const = np.full((cam.height, cam.width), 1.25, np.float32)
+    assert np.all(oracle.pyramid_down(const, cam, 0.05) == np.float32(1.25))
+    # a step larger than T invalidates the 2x2 blocks it crosses
+    step = const.copy()
+    step[:, 81:] = 1.5
+    l2 = oracle.pyramid_down(step, cam, 0.05)
+    assert np.all(l2[:, 40] == 0) and np.all(l2[:, 39] > 0) and np.all(l2[:, 41] > 0)
+
+
+def test_exact_pose_recovery_on_model_consistent_render():
+    """Rendering the map's own Taylor surface from a perturbed pose gives
+    residuals that vanish at that pose: GN must reach it (Eq. (5), (14))."""
+    cam = synth.Camera(131.0, 131.0, 79.5, 59.5, 160, 120, 0.4, 4.0)
+    sc = scenes.box_room_scene()
+    T0 = scenes.box_room_pose()
+    M = oracle.OracleMap(0.02, 0.1)
+    for k in range(3):
+        Tk = synth.perturb_pose(T0, 100 + k, 1.0, 0.01)
+        d = synth.to_depth_image(synth.render_depth(sc, cam, Tk), cam)
+        M.allocate(d, cam, Tk)
+        M.integrate(d, cam, Tk)
+    T1 = synth.perturb_pose(T0, 11, 2.0, 0.02)
+    depth = M.render_taylor(cam, T1, 0.3, 6.0)
+    assert (depth > 0).mean() > 0.5
+    Tn, stats, failed = M.gn_level(depth, cam, T0, 20, 0.01, 1e-6)
+    assert failed == 0
+    Rr = Tn[:, :3] @ T1[:, :3].T
+    ang = np.linalg.norm([Rr[2, 1] - Rr[1, 2], Rr[0, 2] - Rr[2, 0], Rr[1, 0] - Rr[0, 1]]) / 2
+    assert ang < 1e-9
+    assert np.linalg.norm(Tn[:, 3] - T1[:, 3]) < 1e-9
+    assert stats[-1, 0] < 1e-20
+
+
+def test_sphere_observable_centre_is_recovered():
+    cfg = synth.CONFIG_SPHERE
+    cam = cfg["cam"]
+    sc = synth.sphere_scene()
+    T0 = scenes.IDENTITY
+    d0 = synth.to_depth_image(synth.render_depth(sc, cam, T0), cam)
+    M = oracle.OracleMap(0.02, 0.10, bounds=([-4, -4, 5], [4, 4, 13]))
+    M.allocate(d0, cam, T0)
+    M.integrate(d0, cam, T0)
+    T1 = synth.perturb_pose(T0, 0, 2.0, 0.02)
+    d1 = synth.to_depth_image(synth.render_depth(sc, cam, T1), cam)
+    Tn, stats, failed = M.track(d1, cam, T0, 1, [10], 0.01)
+    c = np.array([0.0, 0.0, 1.5])
+    cc = lambda T: T[:, :3].T @ (c - T[:, 3])
+    # rotation about the centre is unobservable; the centre in the camera frame
+    # is; the fused map's discretisation bias stays well below a voxel
+    assert np.linalg.norm(cc(Tn) - cc(T1)) < 0.05 * 0.02
+    assert np.linalg.norm(cc(T0) - cc(T1)) > 0.02
+    assert stats[-1, 0] < stats[0, 0]
+
+
+def test_adjoint_matches_finite_differences_and_gauss_newton_gradient():
+    M, st = _room_map(frames=(0, 1))
+    cam = st.cam
+    K = 2
+    depths = st.depth[:K].astype(np.float64)
+    T0 = st.poses[:K]
+    delta = 0.01
+    xi0 = np.zeros((K, 6))
+    # at xi = 0 the pose gradient equals the GN right-hand side b (w r = rho')
+    L, dpsi, dg, dxi = M.loss_grad(depths, cam, T0, xi0, delta)
+    for i in range(K):
+        ne = M.normal_equations(depths[i], cam, T0[i], delta)
+        np.testing.assert_allclose(dxi[i], ne[21:27], rtol=1e-12, atol=1e-15)
+    assert L == pytest.approx(sum(M.normal_equations(depths[i], cam, T0[i], delta)[27] for i in range(K)),
+                              rel=1e-12)
+    # central differences with the association frozen at xi
+    rng = np.random.default_rng(6)
+    xi = rng.standard_normal((K, 6)) * 1e-3
+    assoc = np.zeros((K, cam.height, cam.width, 3), np.int32)
+    L, dpsi, dg, dxi = M.loss_grad(depths, cam, T0, xi, delta, assoc=assoc, freeze=False)
+    # the Huber loss is only C1 (its second derivative jumps at |r| = delta), so
+    # central differences converge as O(h) across the kink: take a small h in FP64
+    h = 1e-6
+    for i in range(K):
+        for k in range(6):
+            e = np.zeros((K, 6))
+            e[i, k] = h
+            Lp = M.loss_grad(depths, cam, T0, xi + e, delta, assoc=assoc, freeze=True,
+                             want_voxel_grads=False)[0]
+            Lm = M.loss_grad(depths, cam, T0, xi - e, delta, assoc=assoc, freeze=True,
+                             want_voxel_grads=False)[0]
+            fd = (Lp - Lm) / (2 * h)
+            assert dxi[i, k] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+    keys = M.keys()
+    psi, g, W, _ = M.voxels(keys)
+    nz = np.argwhere(np.abs(dpsi) > 1e-3)
+    for bi, j in nz[rng.choice(len(nz), 6, replace=False)]:
+        for comp in range(4):
+            pp, gp = psi.copy(), g.copy()
+            pm, gm = psi.copy(), g.copy()
+            if comp == 0:
+                pp[bi, j] += h
+                pm[bi, j] -= h
+                ana = dpsi[bi, j]
+            else:
+                gp[bi, j, comp - 1] += h
+                gm[bi, j, comp - 1] -= h
+                ana = dg[bi, j, comp - 1]
+            A = oracle.OracleMap(M.voxel_size, M.truncation)
+            A.set_voxels(keys, pp, gp, W)
+            B = oracle.OracleMap(M.voxel_size, M.truncation)
+            B.set_voxels(keys, pm, gm, W)
+            Lp = A.loss_grad(depths, cam, T0, xi, delta, assoc=assoc, freeze=True, want_voxel_grads=False)[0]
+            Lm = B.loss_grad(depths, cam, T0, xi, delta, assoc=assoc, freeze=True, want_voxel_grads=False)[0]
+            assert ana == pytest.approx((Lp - Lm) / (2 * h), rel=1e-6, abs=1e-8)

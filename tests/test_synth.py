@@ -1,0 +1,97 @@
+"""Pins for the seeded input generator: exact ray casts, SDFs, noise model,
+trajectory bounds.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2111_13652_amd import synth
+
+
+def _hits(scene, cam, T, z):
+    rays = cam.rays()
+    R, t = T[:, :3], T[:, 3]
+    return (rays * z[..., None]) @ R.T + t
+
+
+def test_sphere_sdf_closed_form_and_unit_gradient():
+    sc = synth.sphere_scene((0.1, -0.2, 1.5), 0.5)
+    rng = np.random.default_rng(0)
+    p = rng.uniform(-1, 2, size=(2000, 3))
+    # closed form R - |p - c| (positive inside, Sec. 3.1 sign convention)
+    np.testing.assert_allclose(sc.sdf(p), 0.5 - np.linalg.norm(p - [0.1, -0.2, 1.5], axis=1), atol=1e-15)
+    h = 1e-6
+    g = np.stack([(sc.sdf(p + h * e) - sc.sdf(p - h * e)) / (2 * h) for e in np.eye(3)], -1)
+    np.testing.assert_allclose(np.linalg.norm(g, axis=1), 1.0, atol=1e-6)
+
+
+def test_room_sdf_unit_gradient_away_from_kinks():
+    poses = synth.smooth_trajectory(2, 10)
+    sc = synth.room_scene(1, poses[:, :, 3])
+    rng = np.random.default_rng(1)
+    p = rng.uniform([0.2, 0.2, 0.2], [3.8, 3.8, 2.8], size=(3000, 3))
+    h = 1e-7
+    g = np.stack([(sc.sdf(p + h * e) - sc.sdf(p - h * e)) / (2 * h) for e in np.eye(3)], -1)
+    gn = np.linalg.norm(g, axis=1)
+    # a max of distance functions has |grad| = 1 almost everywhere (inside a box's
+    # interior it is also 1); allow the measure-zero kinks
+    assert np.mean(np.abs(gn - 1.0) < 1e-5) > 0.99
+
+
+@pytest.mark.parametrize("which", ["sphere", "room"])
+def test_ray_cast_hits_lie_on_surface(which):
+    if which == "sphere":
+        cam = synth.CONFIG_SPHERE["cam"]
+        sc = synth.sphere_scene()
+        T = np.hstack([np.eye(3), np.zeros((3, 1))])
+    else:
+        cam = synth.Camera(525.0 / 4, 525.0 / 4, 79.5, 59.5, 160, 120, 0.4, 4.0)
+        poses = synth.smooth_trajectory(2, 5)
+        sc = synth.room_scene(1, poses[:, :, 3])
+        T = poses[3]
+    z = synth.render_depth(sc, cam, T)
+    ok = np.isfinite(z)
+    assert ok.sum() > 1000
+    p = _hits(sc, cam, T, np.where(ok, z, 0.0))[ok]
+    assert np.max(np.abs(sc.sdf(p))) < 1e-12
+    # a ray segment just in front of the hit is in free space
+    p_front = _hits(sc, cam, T, np.where(ok, z * (1 - 1e-3), 0.0))[ok]
+    assert np.all(sc.sdf(p_front) < 0)
+
+
+def test_sphere_config_valid_pixel_count():
+    cam = synth.CONFIG_SPHERE["cam"]
+    d = synth.to_depth_image(synth.render_depth(synth.sphere_scene(), cam,
+                                                np.hstack([np.eye(3), np.zeros((3, 1))])), cam)
+    # image radius of the sphere: f * R / sqrt(c^2 - R^2) = 131 * 0.5 / sqrt(2)
+    r_img = 131.0 * 0.5 / math.sqrt(1.5 ** 2 - 0.5 ** 2)
+    assert abs(r_img - 46.3) < 0.05
+    assert abs((d > 0).sum() - math.pi * r_img ** 2) < 0.01 * math.pi * r_img ** 2
+
+
+def test_noise_model_and_range():
+    z = np.full(200000, 2.0)
+    zn = synth.add_depth_noise(z, np.random.Generator(np.random.PCG64(3)))
+    sig = 0.0012 + 0.0019 * (2.0 - 0.4) ** 2
+    assert abs(np.std(zn - z) / sig - 1) < 0.01
+    cam = synth.CONFIG_ROOM["cam"]
+    img = synth.to_depth_image(np.array([[0.39, 0.4, 2.0, 4.0, 4.01, np.inf]]), cam)
+    assert list(img[0] > 0) == [False, True, True, True, False, False]
+
+
+def test_trajectory_step_bounds_and_determinism():
+    P = synth.smooth_trajectory(2, 60)
+    step = np.linalg.norm(np.diff(P[:, :, 3], axis=0), axis=1)
+    ang = [synth._rot_angle(P[i, :, :3], P[i + 1, :, :3]) for i in range(len(P) - 1)]
+    assert step.max() <= 0.02 + 1e-12 and math.degrees(max(ang)) <= 1.0 + 1e-9
+    for R in P[:, :, :3]:
+        np.testing.assert_allclose(R.T @ R, np.eye(3), atol=1e-12)
+        assert abs(np.linalg.det(R) - 1) < 1e-12
+    np.testing.assert_array_equal(P, synth.smooth_trajectory(2, 60))
+
+
+def test_perturbation_is_exact():
+    T0 = synth.look_at([1, 1, 1], [2, 3, 1.2])
+    T1 = synth.perturb_pose(T0, 7, 2.0, 0.02)
+    assert abs(math.degrees(synth._rot_angle(T0[:, :3], T1[:, :3])) - 2.0) < 1e-9
+    assert abs(np.linalg.norm(T1[:, 3] - T0[:, 3]) - 0.02) < 1e-12
