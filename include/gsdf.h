@@ -1,0 +1,228 @@
+/*
+ * gsdf.h -- C ABI of the MI355X (gfx950) Gradient-SDF tracking and fusion
+ * library (libgsdf.so).
+ *
+ * The method is Gradient-SDF (Sommer, Sang, Schubert, Cremers, CVPR 2022):
+ * a voxel SDF whose voxels also store an accumulated SDF gradient, fused
+ * from depth images (Sec. 3.1 Eq. (1)-(2), Sec. 3.2 Eq. (3)) and used to
+ * track the camera with one voxel lookup per pixel through a first-order
+ * Taylor expansion (Sec. 4.1 Eq. (5), (14)-(16)), solved by Gauss-Newton
+ * with a Cholesky decomposition (Sec. 5.1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every pointer argument named *_dev, and every buffer of gsdf_map, is
+ *    DEVICE memory allocated by the caller (the library never allocates or
+ *    frees device memory).  Struct arguments (gsdf_camera, *_params,
+ *    gsdf_map itself) are HOST memory read during the call only.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls only
+ *    enqueue work; none synchronises the stream.  Device buffers must stay
+ *    valid until the stream reaches the work.
+ *  - Return value: GSDF_OK, or a negative gsdf_status detected on the host
+ *    (null pointer, bad size, mismatched storage, launch failure); on such
+ *    an error nothing is enqueued.
+ *  - Conditions found on the device are OR-ed into *status_dev as the bit
+ *    (1u << -code) and are sticky until the caller clears the word.
+ *  - Poses are camera-to-world (R, t) as 12 float64, row-major 3x4, kept on
+ *    the device: a camera point x maps to R x + t (Eq. (5)).
+ *  - Depth images are float32 z-depth in metres, row-major height x width,
+ *    with the pixel centre of column u at x = u; a pixel is valid when its
+ *    depth is finite and zmin <= D <= zmax (binary32 comparisons).
+ *  - Sign: psi > 0 inside objects and < 0 in free space (Sec. 3.1); the
+ *    stored gradient points into the object.
+ *  - A map is used by one stream at a time.
+ */
+#ifndef GSDF_H
+#define GSDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GSDF_OK = 0,
+    GSDF_EINVAL = -1,     /* bad argument (host)                                   */
+    GSDF_ECAPACITY = -2,  /* hash table or block pool full (device): the block is  */
+                          /* not allocated and later steps skip its voxels         */
+    GSDF_EHIP = -3,       /* a HIP call failed (host)                               */
+    GSDF_ENOTPD = -4,     /* a Gauss-Newton system was not positive definite        */
+                          /* (device): that iteration's pose update is skipped      */
+    GSDF_ELOST = -5       /* tracking used fewer than min_inlier_frac of the valid  */
+                          /* pixels at the finest level (device)                    */
+} gsdf_status;
+
+typedef enum {
+    GSDF_FP32 = 0,  /* voxel = float4 {sum w d, g_x, g_y, g_z} (16 B) + W   */
+    GSDF_BF16 = 1,  /* voxel = 4 x bf16 {psi/T, gbar_x, gbar_y, gbar_z} + W */
+    GSDF_FP16 = 2   /* voxel = 4 x fp16 {psi/T, gbar_x, gbar_y, gbar_z} + W */
+} gsdf_storage;
+
+/* Map geometry and capacity.  The grid is v_j = voxel_size * m_j (Sec. 3.1),
+ * stored sparsely as 8^3-voxel blocks found through a hash table. */
+typedef struct gsdf_map_desc {
+    double voxel_size;    /* metres (float32 band constants are rounded from it) */
+    double truncation;    /* T, metres: SDF values are clamped to [-T, T]        */
+    int32_t storage;      /* gsdf_storage                                        */
+    int32_t reserved0;
+    int64_t hash_slots;   /* power of two, >= 2 * max_blocks recommended         */
+    int64_t max_blocks;   /* block pool capacity, <= 2^24                        */
+    int32_t bounded;      /* 1: only blocks b with bmin <= b < bmax are allocated */
+    int32_t bmin[3];
+    int32_t bmax[3];
+    int32_t reserved1;
+} gsdf_map_desc;
+
+/* The four caller-allocated device buffers of a map (sizes from
+ * gsdf_map_buffer_sizes).  Layout inside them is private to the library. */
+typedef struct gsdf_map {
+    void* hash;     /* hash table                                             */
+    void* vox;      /* voxel records, max_blocks * 512                          */
+    void* weight;   /* float32 accumulated weight W per voxel, max_blocks * 512 */
+    void* aux;      /* block keys, counters, per-frame accumulators and lists   */
+    gsdf_map_desc desc;
+} gsdf_map;
+
+/* Pinhole camera (Sec. 4.1 back-projection x = D [(u-cx)/fx, (v-cy)/fy, 1]). */
+typedef struct gsdf_camera {
+    double fx, fy, cx, cy;
+    int32_t width, height;
+    float zmin, zmax;     /* valid depth range, metres */
+} gsdf_camera;
+
+/* Fusion parameters (Sec. 5.3 setup). */
+typedef struct gsdf_fuse_params {
+    float eps_weight;     /* linear weight: w(d) = 1 for d <= eps, (T-d)/(T-eps)  */
+                          /* for eps < d < T, 0 for d >= T                        */
+    float cos_max_angle;  /* integrate pixels whose normal/ray angle cosine is at */
+                          /* least this (cos 75 deg in the paper)                 */
+} gsdf_fuse_params;
+
+/* Tracking parameters (Sec. 4.1, Sec. 5.1). */
+typedef struct gsdf_track_params {
+    int32_t levels;          /* pyramid levels, 1..4                              */
+    int32_t iters[4];        /* Gauss-Newton iterations per level, iters[0] is    */
+                             /* the finest level; levels run coarse to fine       */
+    float huber_delta;       /* Huber threshold delta (metres)                    */
+    double damping;          /* mu = damping * trace(H) / 6 added to H's diagonal */
+    float min_inlier_frac;   /* GSDF_ELOST below this fraction at the finest level */
+    int32_t reserved;
+} gsdf_track_params;
+
+/* ---------------------------------------------------------------------- */
+/* Map buffers                                                             */
+/* ---------------------------------------------------------------------- */
+
+/* Byte sizes of the four map buffers for `desc` (host only, no GPU work).
+ * sizes_out[0..3] = hash, vox, weight, aux.  Returns GSDF_EINVAL for a
+ * hash_slots that is not a power of two, a non-positive capacity, a
+ * voxel_size <= 0 or truncation < voxel_size. */
+int gsdf_map_buffer_sizes(const gsdf_map_desc* desc, size_t sizes_out[4]);
+
+/* Clear a map to empty (all hash slots free, all voxels zero). */
+int gsdf_map_reset(gsdf_map* map, void* stream);
+
+/* Number of allocated blocks, written to *n_dev (int32, device). */
+int gsdf_map_num_blocks(const gsdf_map* map, int32_t* n_dev, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* The per-frame hot path                                                  */
+/* ---------------------------------------------------------------------- */
+
+/* allocate_blocks (Sec. 5.3 setup: fusion is driven by depth pixels, each
+ * touching the voxels its viewing ray crosses inside the truncation band;
+ * 8^3 blocks as in Sec. 3.1): insert into the map every block that holds a
+ * voxel of a valid pixel's ray band.  The band is sampled at z_k = (D - T) + k v_s/2,
+ * k = 0 .. 4T/v_s, each sample is mapped to its voxel floor(q / v_s + 1/2)
+ * and the voxel to its block floor(m / 8), all in binary32 with a fixed
+ * operation order, so the allocated key set is reproducible bit for bit.
+ * T_wc_dev: 12 float64 (device).  A full table or pool sets GSDF_ECAPACITY. */
+int gsdf_allocate_blocks(gsdf_map* map, const float* depth_dev, const gsdf_camera* cam,
+                         const double* T_wc_dev, int32_t* status_dev, void* stream);
+
+/* integrate_frame (Eq. (1)-(3)): for every valid pixel whose 5x5 normal fit
+ * succeeds and whose normal/ray angle passes the filter, every voxel of its
+ * ray band (as in gsdf_allocate_blocks) in an allocated block receives
+ * d = clamp(n_w . (v - p), -T, T) with weight w(d); per voxel,
+ * psi <- (W psi + sum w d) / (W + sum w), g <- g + sum w n_w, W <- W + sum w.
+ * Blocks must have been allocated for this frame first. */
+int gsdf_integrate_frame(gsdf_map* map, const float* depth_dev, const gsdf_camera* cam,
+                         const double* T_wc_dev, const gsdf_fuse_params* params,
+                         int32_t* status_dev, void* stream);
+
+/* Scratch bytes gsdf_track_frame / gsdf_normal_equations need for `cam`. */
+size_t gsdf_track_scratch_bytes(const gsdf_camera* cam, int32_t levels);
+
+/* track_frame (Sec. 4.1 Eq. (5), (14)-(16); Sec. 5.1): coarse-to-fine
+ * Gauss-Newton on E = sum_k rho_delta(r_k), r_k = psi_j + g^_j . (T x_k - v_j)
+ * with j the voxel nearest to T x_k, Jacobian [g^ ; (T x) x g^] for a left
+ * perturbation in the world frame, and a damped 6x6 Cholesky solve in
+ * float64 on the device; T <- exp(dxi) T.  T_wc_inout_dev (device, 12 f64)
+ * holds the initial pose and receives the estimate.  stats_dev (device,
+ * optional) receives 2 floats per iteration in execution order: the energy
+ * and the number of pixels used at that linearisation.  scratch_dev must
+ * hold gsdf_track_scratch_bytes(cam, levels) bytes. */
+int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, const gsdf_camera* cam,
+                     const gsdf_track_params* params, double* T_wc_inout_dev, float* stats_dev,
+                     void* scratch_dev, size_t scratch_bytes, int32_t* status_dev, void* stream);
+
+/* One linearisation of the tracking energy at T_wc_dev on the full-resolution
+ * image (Eq. (5), (14)-(16)): out29_dev (device, 29 float64) = the 21 upper-
+ * triangular entries of H = sum w J J^T (row-major), the 6 of b = sum w J r,
+ * the energy sum rho_delta(r) and the number of pixels used. */
+int gsdf_normal_equations(const gsdf_map* map, const float* depth_dev, const gsdf_camera* cam,
+                          const double* T_wc_dev, float huber_delta, double* out29_dev,
+                          void* scratch_dev, size_t scratch_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Inspection, import (used for parity checks and checkpoints)             */
+/* ---------------------------------------------------------------------- */
+
+/* Block keys in pool order: keys_out_dev (device, max_blocks x 3 int32) and
+ * their count in *n_dev (int32, device). */
+int gsdf_export_keys(const gsdf_map* map, int32_t* keys_out_dev, int32_t* n_dev, void* stream);
+
+/* Voxel values of pool slots [0, n_blocks): psi (n x 512), g (n x 512 x 3:
+ * the accumulated gradient of Eq. (3) for FP32 storage, the weighted-mean
+ * gradient g/W for BF16/FP16), W (n x 512), all float32, device.  Voxel order
+ * within a block is lx + 8 ly + 64 lz. */
+int gsdf_export_voxels(const gsdf_map* map, int32_t n_blocks, float* psi_dev, float* g_dev,
+                       float* w_dev, void* stream);
+
+/* Insert n blocks with the given keys (device, n x 3 int32) and set their
+ * voxels from psi/g/W (device float32, layouts as gsdf_export_voxels). */
+int gsdf_import_blocks(gsdf_map* map, const int32_t* keys_dev, int32_t n, const float* psi_dev,
+                       const float* g_dev, const float* w_dev, int32_t* status_dev, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Timing of individual kernels (host bookkeeping with HIP events)        */
+/* ---------------------------------------------------------------------- */
+
+/* Kernel identifiers for gsdf_timing_read. */
+enum {
+    GSDF_K_ALLOCATE = 0,
+    GSDF_K_INTEGRATE = 1,
+    GSDF_K_TRACK = 2,
+    GSDF_K_PYRAMID = 3,
+    GSDF_K_FINALIZE = 4,
+    GSDF_K_BACKWARD = 5,
+    GSDF_K_COUNT = 16
+};
+
+/* Enable (1) or disable (0) event timing around every kernel launch and
+ * clear the accumulated totals. */
+int gsdf_timing_enable(int32_t on);
+
+/* Total milliseconds and launch count recorded for one kernel id since the
+ * last enable; synchronises the recorded events. */
+int gsdf_timing_read(int32_t kernel_id, double* total_ms, int64_t* launches);
+
+const char* gsdf_status_string(int32_t code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSDF_H */

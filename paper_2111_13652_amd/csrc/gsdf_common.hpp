@@ -1,0 +1,319 @@
+// Device-side building blocks shared by the gfx950 kernels of libgsdf:
+// map layout, block keys, the hash table, and the binary32 ray-band rule.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+
+#include "../../include/gsdf.h"
+
+namespace gsdf {
+
+constexpr int kBlockEdge = 8;
+constexpr int kBlockVoxels = 512;
+
+// ---------------------------------------------------------------------------
+// Status bits (1 << -code), OR-ed into the caller's status word.
+// ---------------------------------------------------------------------------
+__device__ inline void raise_status(int32_t* status, int code) {
+    if (status) atomicOr(status, 1 << (-code));
+}
+
+// ---------------------------------------------------------------------------
+// Block keys: three 21-bit biased coordinates packed into 63 bits.  The
+// all-ones word never encodes a valid key and marks an empty hash slot.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kEmptyKey = ~0ull;
+constexpr int kKeyBias = 1 << 20;
+constexpr int kKeyMin = -kKeyBias;          // inclusive
+constexpr int kKeyMax = kKeyBias - 2;       // inclusive
+
+__host__ __device__ inline bool key_in_range(int bx, int by, int bz) {
+    return bx >= kKeyMin && bx <= kKeyMax && by >= kKeyMin && by <= kKeyMax && bz >= kKeyMin &&
+           bz <= kKeyMax;
+}
+
+__host__ __device__ inline uint64_t pack_key(int bx, int by, int bz) {
+    return ((uint64_t)(uint32_t)(bx + kKeyBias) << 42) | ((uint64_t)(uint32_t)(by + kKeyBias) << 21) |
+           (uint64_t)(uint32_t)(bz + kKeyBias);
+}
+
+__host__ __device__ inline void unpack_key(uint64_t k, int* bx, int* by, int* bz) {
+    const uint64_t m = (1ull << 21) - 1;
+    *bx = (int)((k >> 42) & m) - kKeyBias;
+    *by = (int)((k >> 21) & m) - kKeyBias;
+    *bz = (int)(k & m) - kKeyBias;
+}
+
+// 64-bit finaliser (Murmur3 fmix64): scatters neighbouring blocks over the table.
+__host__ __device__ inline uint64_t mix64(uint64_t k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}
+
+// One hash-table entry, 16 bytes: read with a single dwordx4 load.
+struct alignas(16) HashEntry {
+    uint64_t key;
+    int32_t slot;   // pool slot, or -1 while unassigned / when the pool is full
+    int32_t pad;
+};
+
+// Voxel index inside a block: Morton order of (lx, ly, lz), so every 2x2x2
+// sub-cube (8 voxels) is contiguous.
+__host__ __device__ inline int morton9(int lx, int ly, int lz) {
+    int r = 0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        r |= ((lx >> b) & 1) << (3 * b);
+        r |= ((ly >> b) & 1) << (3 * b + 1);
+        r |= ((lz >> b) & 1) << (3 * b + 2);
+    }
+    return r;
+}
+
+__host__ __device__ inline void demorton9(int r, int* lx, int* ly, int* lz) {
+    int x = 0, y = 0, z = 0;
+    for (int b = 0; b < 3; ++b) {
+        x |= ((r >> (3 * b)) & 1) << b;
+        y |= ((r >> (3 * b + 1)) & 1) << b;
+        z |= ((r >> (3 * b + 2)) & 1) << b;
+    }
+    *lx = x;
+    *ly = y;
+    *lz = z;
+}
+
+// 16-bit storage formats: bf16 (round to nearest even) and IEEE fp16.
+__device__ inline float unpack16(unsigned short s, int storage) {
+    if (storage == GSDF_BF16) return __uint_as_float((uint32_t)s << 16);
+    __half h;
+    *reinterpret_cast<unsigned short*>(&h) = s;
+    return __half2float(h);
+}
+
+__device__ inline unsigned short pack16(float f, int storage) {
+    if (storage == GSDF_BF16) {
+        uint32_t u = __float_as_uint(f);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40);  // NaN
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return (unsigned short)(u >> 16);
+    }
+    __half h = __float2half_rn(f);
+    return *reinterpret_cast<unsigned short*>(&h);
+}
+
+// Aux buffer layout (offsets in bytes from map.aux).
+struct AuxLayout {
+    size_t block_keys;   // uint64 per pool slot
+    size_t counters;     // 64 int32
+    size_t touched_flag; // int32 per pool slot (per-frame touched marker)
+    size_t touched_list; // int32 per pool slot
+    size_t accum;        // float per voxel x 5 (reduced-precision storage only)
+    size_t total;
+};
+
+enum Counter { kNumBlocks = 0, kNumTouched = 1 };
+
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+__host__ __device__ inline AuxLayout aux_layout(const gsdf_map_desc& d) {
+    AuxLayout a;
+    size_t nb = (size_t)d.max_blocks;
+    size_t o = 0;
+    a.block_keys = o;   o = align256(o + nb * 8);
+    a.counters = o;     o = align256(o + 64 * 4);
+    a.touched_flag = o; o = align256(o + nb * 4);
+    a.touched_list = o; o = align256(o + nb * 4);
+    a.accum = o;
+    if (d.storage != GSDF_FP32) o = align256(o + nb * kBlockVoxels * 5 * 4);
+    a.total = o;
+    return a;
+}
+
+// Device view of a map, passed to kernels by value.
+struct MapView {
+    HashEntry* hash;
+    uint64_t mask;          // hash_slots - 1
+    void* vox;
+    float* weight;
+    uint64_t* block_keys;
+    int32_t* counters;
+    int32_t* touched_flag;
+    int32_t* touched_list;
+    float* accum;
+    int32_t max_blocks;
+    int32_t bounded;
+    int32_t bmin[3], bmax[3];
+    float voxel_size;
+    float truncation;
+    double voxel_size_d;
+    double truncation_d;
+};
+
+inline MapView make_view(const gsdf_map& m) {
+    MapView v;
+    AuxLayout a = aux_layout(m.desc);
+    char* aux = (char*)m.aux;
+    v.hash = (HashEntry*)m.hash;
+    v.mask = (uint64_t)m.desc.hash_slots - 1;
+    v.vox = m.vox;
+    v.weight = (float*)m.weight;
+    v.block_keys = (uint64_t*)(aux + a.block_keys);
+    v.counters = (int32_t*)(aux + a.counters);
+    v.touched_flag = (int32_t*)(aux + a.touched_flag);
+    v.touched_list = (int32_t*)(aux + a.touched_list);
+    v.accum = m.desc.storage != GSDF_FP32 ? (float*)(aux + a.accum) : nullptr;
+    v.max_blocks = (int32_t)m.desc.max_blocks;
+    v.bounded = m.desc.bounded;
+    for (int i = 0; i < 3; ++i) {
+        v.bmin[i] = m.desc.bmin[i];
+        v.bmax[i] = m.desc.bmax[i];
+    }
+    v.voxel_size = (float)m.desc.voxel_size;
+    v.truncation = (float)m.desc.truncation;
+    v.voxel_size_d = m.desc.voxel_size;
+    v.truncation_d = m.desc.truncation;
+    return v;
+}
+
+__device__ inline bool block_allowed(const MapView& M, int bx, int by, int bz) {
+    if (!key_in_range(bx, by, bz)) return false;
+    if (!M.bounded) return true;
+    return bx >= M.bmin[0] && bx < M.bmax[0] && by >= M.bmin[1] && by < M.bmax[1] &&
+           bz >= M.bmin[2] && bz < M.bmax[2];
+}
+
+// Pool slot of block (bx,by,bz), or -1.  Linear probing; an empty slot ends
+// the search.  Only valid after the kernel that inserted the key finished.
+__device__ inline int32_t hash_find(const MapView& M, int bx, int by, int bz) {
+    if (!key_in_range(bx, by, bz)) return -1;
+    const uint64_t key = pack_key(bx, by, bz);
+    uint64_t h = mix64(key) & M.mask;
+    for (uint64_t probe = 0; probe <= M.mask; ++probe) {
+        const uint4 e = *reinterpret_cast<const uint4*>(&M.hash[h]);
+        const uint64_t k = (uint64_t)e.x | ((uint64_t)e.y << 32);
+        if (k == key) return (int32_t)e.z;
+        if (k == kEmptyKey) return -1;
+        h = (h + 1) & M.mask;
+    }
+    return -1;
+}
+
+// Insert a block key if absent.  The winner of the compare-and-swap takes a
+// pool slot from the block counter.  Returns the number of blocks created
+// by this call (0 or 1).
+__device__ inline int hash_insert(const MapView& M, int bx, int by, int bz, int32_t* status) {
+    const uint64_t key = pack_key(bx, by, bz);
+    uint64_t h = mix64(key) & M.mask;
+    for (uint64_t probe = 0; probe <= M.mask; ++probe) {
+        unsigned long long* kp = reinterpret_cast<unsigned long long*>(&M.hash[h].key);
+        uint64_t k = *kp;
+        if (k == key) return 0;
+        if (k == kEmptyKey) {
+            uint64_t old = atomicCAS(kp, (unsigned long long)kEmptyKey, (unsigned long long)key);
+            if (old == kEmptyKey) {
+                int32_t slot = atomicAdd(&M.counters[kNumBlocks], 1);
+                if (slot < M.max_blocks) {
+                    M.hash[h].slot = slot;
+                    M.block_keys[slot] = key;
+                    return 1;
+                }
+                raise_status(status, GSDF_ECAPACITY);
+                return 0;
+            }
+            if (old == key) return 0;
+        }
+        h = (h + 1) & M.mask;
+    }
+    raise_status(status, GSDF_ECAPACITY);
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// The ray band of a pixel, decided in binary32 with a fixed operation order
+// (no contraction): sample z_k = (D - T) + k (v_s / 2), camera point
+// (z xr, z yr, z), world q_i = ((R_i0 X + R_i1 Y) + R_i2 z) + t_i, voxel
+// floor(q v_s^-1 + 1/2).  Constants are float32 roundings of the float64
+// camera, pose and map parameters.
+// ---------------------------------------------------------------------------
+struct BandRule {
+    float ifx, ify, cxf, cyf, invvs, Tf, Df;
+    float R[9], t[3];
+    int nsamples;
+};
+
+__device__ inline BandRule make_band_rule(const double* T, float ifx, float ify, float cxf,
+                                          float cyf, float invvs, float Tf, float Df, int nsamples) {
+    BandRule b;
+    b.ifx = ifx;
+    b.ify = ify;
+    b.cxf = cxf;
+    b.cyf = cyf;
+    b.invvs = invvs;
+    b.Tf = Tf;
+    b.Df = Df;
+    b.nsamples = nsamples;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) b.R[3 * i + j] = (float)T[4 * i + j];
+        b.t[i] = (float)T[4 * i + 3];
+    }
+    return b;
+}
+
+// Voxel coordinate of band sample k of pixel (u, v) with depth D.
+// Returns false for samples at or behind the camera (z <= 0).
+__device__ inline bool band_sample(const BandRule& b, float xr, float yr, float D, int k, int* m) {
+    const float z = __fadd_rn(__fsub_rn(D, b.Tf), __fmul_rn((float)k, b.Df));
+    if (!(z > 0.0f)) return false;
+    const float X = __fmul_rn(z, xr);
+    const float Y = __fmul_rn(z, yr);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float a = __fmul_rn(b.R[3 * i + 0], X);
+        const float c = __fmul_rn(b.R[3 * i + 1], Y);
+        const float e = __fmul_rn(b.R[3 * i + 2], z);
+        const float q = __fadd_rn(__fadd_rn(__fadd_rn(a, c), e), b.t[i]);
+        m[i] = (int)floorf(__fadd_rn(__fmul_rn(q, b.invvs), 0.5f));
+    }
+    return true;
+}
+
+__device__ inline float pixel_xr(const BandRule& b, int u) { return __fmul_rn(__fsub_rn((float)u, b.cxf), b.ifx); }
+__device__ inline float pixel_yr(const BandRule& b, int v) { return __fmul_rn(__fsub_rn((float)v, b.cyf), b.ify); }
+
+// Floor division by 8 (arithmetic shift on two's complement).
+__device__ inline int block_of(int m) { return m >> 3; }
+
+__device__ inline bool depth_ok(float D, float zmin, float zmax) {
+    return D > 0.0f && D >= zmin && D <= zmax && D <= 3.0e38f;
+}
+
+// Host-side float32 constants of the band rule.
+struct BandConsts {
+    float ifx, ify, cxf, cyf, invvs, Tf, Df;
+    int nsamples;
+};
+
+inline BandConsts band_consts(const gsdf_camera& c, double voxel_size, double truncation) {
+    BandConsts k;
+    k.ifx = (float)(1.0 / c.fx);
+    k.ify = (float)(1.0 / c.fy);
+    k.cxf = (float)c.cx;
+    k.cyf = (float)c.cy;
+    k.invvs = (float)(1.0 / voxel_size);
+    k.Tf = (float)truncation;
+    k.Df = (float)(voxel_size / 2.0);
+    k.nsamples = (int)std::floor(2.0 * truncation / (voxel_size / 2.0) + 0.5) + 1;
+    return k;
+}
+
+}  // namespace gsdf

@@ -1,0 +1,56 @@
+// Host-side helpers of libgsdf: argument checks, launch bracketing with the
+// optional event timer, and camera/pose constants.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "gsdf_common.hpp"
+
+namespace gsdf {
+
+// ---- optional per-kernel event timing (see gsdf_timing_enable) ----
+bool timing_on();
+void timing_begin(int kernel_id, hipStream_t s);
+void timing_end(int kernel_id, hipStream_t s);
+
+struct TimedLaunch {
+    int id;
+    hipStream_t s;
+    bool on;
+    TimedLaunch(int kernel_id, hipStream_t stream) : id(kernel_id), s(stream), on(timing_on()) {
+        if (on) timing_begin(id, s);
+    }
+    ~TimedLaunch() {
+        if (on) timing_end(id, s);
+    }
+};
+
+inline bool valid_desc(const gsdf_map_desc& d) {
+    if (!(d.voxel_size > 0.0) || !(d.truncation >= d.voxel_size)) return false;
+    if (d.max_blocks <= 0 || d.max_blocks > (1 << 24)) return false;
+    if (d.hash_slots <= 0 || (d.hash_slots & (d.hash_slots - 1)) != 0) return false;
+    if (d.hash_slots < d.max_blocks) return false;
+    if (d.storage < GSDF_FP32 || d.storage > GSDF_FP16) return false;
+    return true;
+}
+
+inline bool valid_map(const gsdf_map* m) {
+    return m && m->hash && m->vox && m->weight && m->aux && valid_desc(m->desc);
+}
+
+inline bool valid_cam(const gsdf_camera* c) {
+    return c && c->width > 0 && c->height > 0 && c->width <= 16384 && c->height <= 16384 &&
+           c->fx > 0 && c->fy > 0 && std::isfinite(c->cx) && std::isfinite(c->cy);
+}
+
+inline int launch_status() {
+    return hipGetLastError() == hipSuccess ? GSDF_OK : GSDF_EHIP;
+}
+
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+}  // namespace gsdf

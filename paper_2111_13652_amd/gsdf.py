@@ -1,0 +1,211 @@
+"""Python front end of libgsdf: torch owns the device buffers, the library
+does every step of the path.  Argument marshalling only.
+
+    m = GsdfMap(voxel_size=0.01, truncation=0.05, max_blocks=40000)
+    m.allocate(depth, cam, pose); m.integrate(depth, cam, pose)
+    m.track(depth2, cam, pose2, levels=3, iters=(4, 5, 10))   # pose2 updated in place
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+
+STORAGE = {"fp32": _lib.FP32, "bf16": _lib.BF16, "fp16": _lib.FP16}
+COS_75 = math.cos(math.radians(75.0))
+
+
+def _stream() -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def camera(cam) -> _lib.Camera:
+    """A ``_lib.Camera`` from any object with fx, fy, cx, cy, width, height,
+    zmin, zmax attributes."""
+    return _lib.Camera(float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy), int(cam.width),
+                       int(cam.height), float(cam.zmin), float(min(cam.zmax, 3.0e38)))
+
+
+def _need(t: torch.Tensor, dtype, shape=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous {dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class GsdfMap:
+    """A sparse 8^3-block Gradient-SDF map living in device memory."""
+
+    def __init__(self, voxel_size: float, truncation: float, max_blocks: int,
+                 hash_slots: Optional[int] = None, storage: str = "fp32", bounds=None,
+                 device: str = "cuda"):
+        lib = _lib.load()
+        if hash_slots is None:
+            hash_slots = 1 << max(4, int(math.ceil(math.log2(4 * max_blocks))))
+        d = _lib.MapDesc()
+        d.voxel_size = float(voxel_size)
+        d.truncation = float(truncation)
+        d.storage = STORAGE[storage]
+        d.hash_slots = int(hash_slots)
+        d.max_blocks = int(max_blocks)
+        if bounds is not None:
+            d.bounded = 1
+            for i in range(3):
+                d.bmin[i] = int(bounds[0][i])
+                d.bmax[i] = int(bounds[1][i])
+        sizes = (C.c_size_t * 4)()
+        _lib.check(lib.gsdf_map_buffer_sizes(C.byref(d), C.byref(sizes)), "map_buffer_sizes")
+        self.device = torch.device(device)
+        self.buffers = [torch.empty(int(s), dtype=torch.uint8, device=self.device) for s in sizes]
+        self._map = _lib.Map(self.buffers[0].data_ptr(), self.buffers[1].data_ptr(),
+                             self.buffers[2].data_ptr(), self.buffers[3].data_ptr(), d)
+        self.voxel_size = float(voxel_size)
+        self.truncation = float(truncation)
+        self.max_blocks = int(max_blocks)
+        self.storage = storage
+        self.status = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self._scratch = {}
+        self.reset()
+
+    # ---- buffers ----
+    @property
+    def weight(self) -> torch.Tensor:
+        """Per-voxel accumulated weight W (max_blocks*512 float32, pool order)."""
+        return self.buffers[2].view(torch.float32)
+
+    def reset(self) -> None:
+        _lib.check(_lib.load().gsdf_map_reset(C.byref(self._map), _stream()), "map_reset")
+        self.status.zero_()
+
+    def _scratch_for(self, cam: _lib.Camera, levels: int) -> torch.Tensor:
+        key = (cam.width, cam.height, levels)
+        if key not in self._scratch:
+            n = _lib.load().gsdf_track_scratch_bytes(C.byref(cam), levels)
+            if n == 0:
+                raise ValueError("invalid camera / levels for tracking")
+            self._scratch[key] = torch.empty(int(n), dtype=torch.uint8, device=self.device)
+        return self._scratch[key]
+
+    # ---- the hot path ----
+    def allocate(self, depth: torch.Tensor, cam, pose: torch.Tensor) -> None:
+        c = camera(cam)
+        _need(depth, torch.float32, (c.height, c.width), "depth")
+        _need(pose, torch.float64, (3, 4), "pose")
+        _lib.check(_lib.load().gsdf_allocate_blocks(C.byref(self._map), _ptr(depth), C.byref(c),
+                                                     _ptr(pose), _ptr(self.status), _stream()),
+                   "allocate_blocks")
+
+    def integrate(self, depth: torch.Tensor, cam, pose: torch.Tensor, eps: Optional[float] = None,
+                  cos_max_angle: float = COS_75) -> None:
+        c = camera(cam)
+        _need(depth, torch.float32, (c.height, c.width), "depth")
+        _need(pose, torch.float64, (3, 4), "pose")
+        p = _lib.FuseParams(float(self.voxel_size if eps is None else eps), float(cos_max_angle))
+        _lib.check(_lib.load().gsdf_integrate_frame(C.byref(self._map), _ptr(depth), C.byref(c),
+                                                     _ptr(pose), C.byref(p), _ptr(self.status),
+                                                     _stream()), "integrate_frame")
+
+    def fuse(self, depth: torch.Tensor, cam, pose: torch.Tensor, **kw) -> None:
+        self.allocate(depth, cam, pose)
+        self.integrate(depth, cam, pose, **kw)
+
+    def track(self, depth: torch.Tensor, cam, pose: torch.Tensor, levels: int = 3,
+              iters: Sequence[int] = (4, 5, 10), delta: float = 0.01, damping: float = 1e-6,
+              min_inlier_frac: float = 0.1, stats: Optional[torch.Tensor] = None) -> None:
+        """Coarse-to-fine tracking; ``pose`` (3x4 float64, device) is updated
+        in place.  ``iters[l]`` iterations at level l (0 = finest)."""
+        c = camera(cam)
+        _need(depth, torch.float32, (c.height, c.width), "depth")
+        _need(pose, torch.float64, (3, 4), "pose")
+        it = list(iters) + [0] * (4 - len(iters))
+        if stats is not None:
+            _need(stats, torch.float32, None, "stats")
+            if stats.numel() < 2 * sum(it[:levels]):
+                raise ValueError("stats too small")
+        p = _lib.TrackParams(int(levels), (C.c_int32 * 4)(*it[:4]), float(delta), float(damping),
+                             float(min_inlier_frac), 0)
+        scratch = self._scratch_for(c, levels)
+        _lib.check(_lib.load().gsdf_track_frame(C.byref(self._map), _ptr(depth), C.byref(c),
+                                                 C.byref(p), _ptr(pose), _ptr(stats), _ptr(scratch),
+                                                 scratch.numel(), _ptr(self.status), _stream()),
+                   "track_frame")
+
+    def normal_equations(self, depth: torch.Tensor, cam, pose: torch.Tensor, delta: float) -> torch.Tensor:
+        c = camera(cam)
+        _need(depth, torch.float32, (c.height, c.width), "depth")
+        _need(pose, torch.float64, (3, 4), "pose")
+        out = torch.zeros(29, dtype=torch.float64, device=self.device)
+        scratch = self._scratch_for(c, 1)
+        _lib.check(_lib.load().gsdf_normal_equations(C.byref(self._map), _ptr(depth), C.byref(c),
+                                                      _ptr(pose), float(delta), _ptr(out),
+                                                      _ptr(scratch), scratch.numel(), _stream()),
+                   "normal_equations")
+        return out
+
+    # ---- inspection ----
+    def num_blocks(self) -> int:
+        n = torch.zeros(1, dtype=torch.int32, device=self.device)
+        _lib.check(_lib.load().gsdf_map_num_blocks(C.byref(self._map), _ptr(n), _stream()), "num_blocks")
+        return int(n.item())
+
+    def keys(self) -> np.ndarray:
+        """Block keys (n, 3) int32 in pool order."""
+        out = torch.zeros((self.max_blocks, 3), dtype=torch.int32, device=self.device)
+        n = torch.zeros(1, dtype=torch.int32, device=self.device)
+        _lib.check(_lib.load().gsdf_export_keys(C.byref(self._map), _ptr(out), _ptr(n), _stream()),
+                   "export_keys")
+        return out[: int(n.item())].cpu().numpy()
+
+    def voxels(self, n_blocks: Optional[int] = None):
+        """(psi, g, W) as numpy arrays (n, 512), (n, 512, 3), (n, 512) in pool
+        order; voxel order lx + 8 ly + 64 lz."""
+        n = self.num_blocks() if n_blocks is None else int(n_blocks)
+        psi = torch.zeros((max(n, 1), 512), dtype=torch.float32, device=self.device)
+        g = torch.zeros((max(n, 1), 512, 3), dtype=torch.float32, device=self.device)
+        w = torch.zeros((max(n, 1), 512), dtype=torch.float32, device=self.device)
+        _lib.check(_lib.load().gsdf_export_voxels(C.byref(self._map), n, _ptr(psi), _ptr(g), _ptr(w),
+                                                   _stream()), "export_voxels")
+        return psi[:n].cpu().numpy(), g[:n].cpu().numpy(), w[:n].cpu().numpy()
+
+    def import_blocks(self, keys, psi, g, W) -> None:
+        k = torch.as_tensor(np.ascontiguousarray(keys, np.int32), device=self.device)
+        p = torch.as_tensor(np.ascontiguousarray(psi, np.float32), device=self.device)
+        gg = torch.as_tensor(np.ascontiguousarray(g, np.float32), device=self.device)
+        w = torch.as_tensor(np.ascontiguousarray(W, np.float32), device=self.device)
+        _lib.check(_lib.load().gsdf_import_blocks(C.byref(self._map), _ptr(k), int(len(k)), _ptr(p),
+                                                   _ptr(gg), _ptr(w), _ptr(self.status), _stream()),
+                   "import_blocks")
+
+    def status_flags(self):
+        return _lib.status_bits(int(self.status.item()))
+
+
+def run_stream(m: GsdfMap, depth: torch.Tensor, cam, pose0: torch.Tensor, levels: int = 3,
+               iters: Sequence[int] = (4, 5, 10), delta: float = 0.01, damping: float = 1e-6,
+               poses_out: Optional[torch.Tensor] = None, start: int = 0, stop: Optional[int] = None):
+    """The per-frame loop on the device: frame ``start`` is fused at
+    ``pose0``; every later frame is tracked from the previous estimate and
+    then fused at the new estimate.  ``depth`` is (F, H, W) float32 on the
+    device; returns the (F, 3, 4) float64 device tensor of estimates."""
+    F = depth.shape[0]
+    stop = F if stop is None else stop
+    if poses_out is None:
+        poses_out = torch.zeros((F, 3, 4), dtype=torch.float64, device=depth.device)
+    poses_out[start].copy_(pose0)
+    m.fuse(depth[start], cam, poses_out[start])
+    for f in range(start + 1, stop):
+        poses_out[f].copy_(poses_out[f - 1])
+        m.track(depth[f], cam, poses_out[f], levels=levels, iters=iters, delta=delta, damping=damping)
+        m.fuse(depth[f], cam, poses_out[f])
+    return poses_out
