@@ -269,26 +269,44 @@ __device__ inline BandRule make_band_rule(const double* T, float ifx, float ify,
     return b;
 }
 
+// Single-rounding binary32 operations.  HIP's __fmul_rn / __fadd_rn are
+// plain operators that the compiler may fuse into FMAs; the decision
+// arithmetic below must round after every operation, so contraction is
+// switched off in these helpers (HIP honours the pragma).
+__device__ inline float mul_rn(float a, float b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+__device__ inline float add_rn(float a, float b) {
+#pragma clang fp contract(off)
+    return a + b;
+}
+__device__ inline float sub_rn(float a, float b) {
+#pragma clang fp contract(off)
+    return a - b;
+}
+
 // Voxel coordinate of band sample k of pixel (u, v) with depth D.
 // Returns false for samples at or behind the camera (z <= 0).
 __device__ inline bool band_sample(const BandRule& b, float xr, float yr, float D, int k, int* m) {
-    const float z = __fadd_rn(__fsub_rn(D, b.Tf), __fmul_rn((float)k, b.Df));
+#pragma clang fp contract(off)
+    const float z = add_rn(sub_rn(D, b.Tf), mul_rn((float)k, b.Df));
     if (!(z > 0.0f)) return false;
-    const float X = __fmul_rn(z, xr);
-    const float Y = __fmul_rn(z, yr);
+    const float X = mul_rn(z, xr);
+    const float Y = mul_rn(z, yr);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        const float a = __fmul_rn(b.R[3 * i + 0], X);
-        const float c = __fmul_rn(b.R[3 * i + 1], Y);
-        const float e = __fmul_rn(b.R[3 * i + 2], z);
-        const float q = __fadd_rn(__fadd_rn(__fadd_rn(a, c), e), b.t[i]);
-        m[i] = (int)floorf(__fadd_rn(__fmul_rn(q, b.invvs), 0.5f));
+        const float a = mul_rn(b.R[3 * i + 0], X);
+        const float c = mul_rn(b.R[3 * i + 1], Y);
+        const float e = mul_rn(b.R[3 * i + 2], z);
+        const float q = add_rn(add_rn(add_rn(a, c), e), b.t[i]);
+        m[i] = (int)floorf(add_rn(mul_rn(q, b.invvs), 0.5f));
     }
     return true;
 }
 
-__device__ inline float pixel_xr(const BandRule& b, int u) { return __fmul_rn(__fsub_rn((float)u, b.cxf), b.ifx); }
-__device__ inline float pixel_yr(const BandRule& b, int v) { return __fmul_rn(__fsub_rn((float)v, b.cyf), b.ify); }
+__device__ inline float pixel_xr(const BandRule& b, int u) { return mul_rn(sub_rn((float)u, b.cxf), b.ifx); }
+__device__ inline float pixel_yr(const BandRule& b, int v) { return mul_rn(sub_rn((float)v, b.cyf), b.ify); }
 
 // Floor division by 8 (arithmetic shift on two's complement).
 __device__ inline int block_of(int m) { return m >> 3; }

@@ -6,10 +6,12 @@
 // Each Gauss-Newton iteration is one launch.  Every thread walks a strided
 // set of pixels, accumulating the 21 upper entries of H = sum w J J^T, the
 // 6 of b = sum w J r, the energy, the count of pixels used and the count of
-// valid pixels in registers; waves reduce with cross-lane shuffles, the 4
-// waves of a work-group through LDS, and the last work-group to finish (a
-// device-scope ticket) sums all work-group partials in float64, solves,
-// updates the pose in place and records the statistics.
+// valid pixels in float32 registers; from there on every sum is float64:
+// waves reduce with cross-lane shuffles, the 4 waves of a work-group through
+// LDS, and the last work-group to finish (a device-scope ticket) adds all
+// work-group partials, solves, updates the pose in place and records the
+// statistics.  Float64 partial sums keep the rounding noise of b far below
+// what a rank-deficient H (a lone sphere) would amplify through the damping.
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
@@ -19,7 +21,7 @@
 namespace gsdf {
 
 constexpr int kNE = 30;          // 21 H + 6 b + energy + used + valid
-constexpr int kPartStride = 32;  // floats per work-group partial
+constexpr int kPartStride = 32;  // doubles per work-group partial
 constexpr int kTrackBlock = 256;
 constexpr int kMaxGroups = 2048;
 constexpr int kPixPerThread = 2;
@@ -40,7 +42,7 @@ struct TrackArgs {
     int check_lost;      // 1 on the last iteration at the finest level
 };
 
-__device__ inline float wave_sum(float x) {
+__device__ inline double wave_sum(double x) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
     return x;
@@ -157,7 +159,7 @@ __device__ bool solve_and_update(const double* ne, double damping, double* pose)
 
 template <int STORAGE>
 __global__ __launch_bounds__(kTrackBlock) void k_track(MapView M, TrackLevel L, TrackArgs a,
-                                                        double* pose, float* partials,
+                                                        double* pose, double* partials,
                                                         unsigned* ticket, double* out29,
                                                         float* stats, int32_t* status) {
     float acc[kNE];
@@ -216,18 +218,18 @@ __global__ __launch_bounds__(kTrackBlock) void k_track(MapView M, TrackLevel L, 
     }
 
     // ---- work-group reduction
-    __shared__ float red[kTrackBlock / 64][kNE];
+    __shared__ double red[kTrackBlock / 64][kNE];
     __shared__ double fin[8][kNE];
     __shared__ int is_last;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < kNE; ++k) {
-        const float s = wave_sum(acc[k]);
+        const double s = wave_sum((double)acc[k]);
         if (lane == 0) red[wave][k] = s;
     }
     __syncthreads();
     if (threadIdx.x < kNE) {
-        float s = 0.0f;
+        double s = 0.0;
 #pragma unroll
         for (int w = 0; w < kTrackBlock / 64; ++w) s += red[w][threadIdx.x];
         partials[(size_t)blockIdx.x * kPartStride + threadIdx.x] = s;
@@ -248,8 +250,8 @@ __global__ __launch_bounds__(kTrackBlock) void k_track(MapView M, TrackLevel L, 
         const int part = threadIdx.x / kNE;
         double s = 0.0;
         for (int b = part; b < (int)gridDim.x; b += 8)
-            s += (double)__hip_atomic_load(&partials[(size_t)b * kPartStride + k], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+            s += __hip_atomic_load(&partials[(size_t)b * kPartStride + k], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         fin[part][k] = s;
     }
     __syncthreads();
@@ -291,8 +293,8 @@ __global__ void k_pyramid(const float* __restrict__ src, int Ws, float* __restri
               depth_ok(e, zmin, zmax);
     const float mx = fmaxf(fmaxf(a, b), fmaxf(c, e));
     const float mn = fminf(fminf(a, b), fminf(c, e));
-    ok = ok && (__fsub_rn(mx, mn) <= Tf);
-    dst[(size_t)v * Wd + u] = ok ? __fmul_rn(__fadd_rn(__fadd_rn(a, b), __fadd_rn(c, e)), 0.25f) : 0.0f;
+    ok = ok && (sub_rn(mx, mn) <= Tf);
+    dst[(size_t)v * Wd + u] = ok ? mul_rn(add_rn(add_rn(a, b), add_rn(c, e)), 0.25f) : 0.0f;
 }
 
 __global__ void k_zero_ticket(unsigned* ticket) {
@@ -307,7 +309,7 @@ inline ScratchLayout scratch_layout(const gsdf_camera& c, int levels) {
     ScratchLayout s;
     size_t o = 0;
     s.ticket = o;   o = align256(o + 256);
-    s.partials = o; o = align256(o + (size_t)kMaxGroups * kPartStride * 4);
+    s.partials = o; o = align256(o + (size_t)kMaxGroups * kPartStride * 8);
     int W = c.width, H = c.height;
     s.level[0] = 0;
     for (int l = 1; l < 4; ++l) {
@@ -327,13 +329,13 @@ inline int track_groups(int npx) {
 
 template <int STORAGE>
 void launch_track(int g, hipStream_t s, const MapView& M, const TrackLevel& L, const TrackArgs& a,
-                  double* pose, float* partials, unsigned* ticket, double* out29, float* stats,
+                  double* pose, double* partials, unsigned* ticket, double* out29, float* stats,
                   int32_t* status) {
     k_track<STORAGE><<<g, kTrackBlock, 0, s>>>(M, L, a, pose, partials, ticket, out29, stats, status);
 }
 
 void launch_track_any(int storage, int g, hipStream_t s, const MapView& M, const TrackLevel& L,
-                      const TrackArgs& a, double* pose, float* partials, unsigned* ticket,
+                      const TrackArgs& a, double* pose, double* partials, unsigned* ticket,
                       double* out29, float* stats, int32_t* status) {
     TimedLaunch tl(GSDF_K_TRACK, s);
     switch (storage) {
@@ -368,7 +370,7 @@ extern "C" int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, con
     hipStream_t s = (hipStream_t)stream;
     char* base = (char*)scratch_dev;
     unsigned* ticket = (unsigned*)(base + sl.ticket);
-    float* partials = (float*)(base + sl.partials);
+    double* partials = (double*)(base + sl.partials);
 
     TrackLevel lv[4];
     lv[0].depth = depth_dev;
@@ -436,7 +438,7 @@ extern "C" int gsdf_normal_equations(const gsdf_map* map, const float* depth_dev
     hipStream_t s = (hipStream_t)stream;
     char* base = (char*)scratch_dev;
     unsigned* ticket = (unsigned*)(base + sl.ticket);
-    float* partials = (float*)(base + sl.partials);
+    double* partials = (double*)(base + sl.partials);
     TrackLevel L;
     L.depth = depth_dev;
     L.W = cam->width;

@@ -57,9 +57,14 @@ def voxel_coords(keys):
 
 
 def compare_voxels(gpu, orc, keys, voxel_size, exclude=frozenset(), psi_tol=1e-4, g_tol=1e-5,
-                   w_rtol=1e-5):
+                   w_rtol=1e-5, w_atol=1e-4):
     """Parity of psi (in units of the voxel size), g-direction and W on voxels
-    observed by both sides; returns a report dict."""
+    observed by both sides; returns a report dict.
+
+    W is checked as |dW| <= w_rtol W + w_atol: the linear weight has slope
+    1/(T - eps) in d, so a voxel whose observations all lie near d = T has a
+    tiny W whose relative error is large while its absolute error (in units of
+    one full-weight observation) stays ~1e-7 per observation."""
     pg, gg, Wg = gpu
     po, go, Wo = orc
     both = (Wg > 0) & (Wo > 0)
@@ -78,7 +83,7 @@ def compare_voxels(gpu, orc, keys, voxel_size, exclude=frozenset(), psi_tol=1e-4
     ghg = gg[both] / np.linalg.norm(gg[both], axis=-1, keepdims=True)
     gho = go[both] / np.linalg.norm(go[both], axis=-1, keepdims=True)
     dg = np.linalg.norm(ghg - gho, axis=-1)
-    dW = np.abs(Wg[both] - Wo[both]) / Wo[both]
+    dW = np.abs(Wg[both] - Wo[both]) / (Wo[both] + w_atol / w_rtol)
     rep = dict(n=int(both.sum()), excluded=n_excluded, one_side=int(one_side),
                psi_max=float(dpsi.max()), psi_p9999=float(np.quantile(dpsi, 0.9999)),
                g_max=float(dg.max()), w_max=float(dW.max()))
