@@ -138,9 +138,15 @@ int gsdf_map_num_blocks(const gsdf_map* map, int32_t* n_dev, void* stream);
  * k = 0 .. 4T/v_s, each sample is mapped to its voxel floor(q / v_s + 1/2)
  * and the voxel to its block floor(m / 8), all in binary32 with a fixed
  * operation order, so the allocated key set is reproducible bit for bit.
+ * The blocks found (new or old) are also recorded as the frame's touched
+ * set, which the next gsdf_integrate_frame consumes; call the two in pairs
+ * with the same depth, camera and pose.
  * T_wc_dev: 12 float64 (device).  A full table or pool sets GSDF_ECAPACITY. */
 int gsdf_allocate_blocks(gsdf_map* map, const float* depth_dev, const gsdf_camera* cam,
                          const double* T_wc_dev, int32_t* status_dev, void* stream);
+
+/* Scratch bytes gsdf_integrate_frame needs for `cam` (one float4 per pixel). */
+size_t gsdf_integrate_scratch_bytes(const gsdf_camera* cam);
 
 /* integrate_frame (Eq. (1)-(3)): for every valid pixel whose 5x5 normal fit
  * succeeds and whose normal/ray angle passes the filter, every voxel of its
@@ -150,7 +156,8 @@ int gsdf_allocate_blocks(gsdf_map* map, const float* depth_dev, const gsdf_camer
  * Blocks must have been allocated for this frame first. */
 int gsdf_integrate_frame(gsdf_map* map, const float* depth_dev, const gsdf_camera* cam,
                          const double* T_wc_dev, const gsdf_fuse_params* params,
-                         int32_t* status_dev, void* stream);
+                         void* scratch_dev, size_t scratch_bytes, int32_t* status_dev,
+                         void* stream);
 
 /* Scratch bytes gsdf_track_frame / gsdf_normal_equations need for `cam`. */
 size_t gsdf_track_scratch_bytes(const gsdf_camera* cam, int32_t levels);
@@ -184,6 +191,13 @@ int gsdf_normal_equations(const gsdf_map* map, const float* depth_dev, const gsd
  * their count in *n_dev (int32, device). */
 int gsdf_export_keys(const gsdf_map* map, int32_t* keys_out_dev, int32_t* n_dev, void* stream);
 
+/* Work counters accumulated since the last reset (device, 16 uint64):
+ * [0] fusion updates applied, [1] (block, pixel) visits of the fusion
+ * gather, [2] voxels written by fusion, [3] blocks processed by fusion,
+ * [4] distinct (16x16 tile, block) pairs probed by allocation, [5] valid pixel-iterations
+ * of tracking, [6] tracking pixel-iterations that found an observed voxel. */
+int gsdf_map_counters(const gsdf_map* map, uint64_t* out_dev, void* stream);
+
 /* Voxel values of pool slots [0, n_blocks): psi (n x 512), g (n x 512 x 3:
  * the accumulated gradient of Eq. (3) for FP32 storage, the weighted-mean
  * gradient g/W for BF16/FP16), W (n x 512), all float32, device.  Voxel order
@@ -206,7 +220,7 @@ enum {
     GSDF_K_INTEGRATE = 1,
     GSDF_K_TRACK = 2,
     GSDF_K_PYRAMID = 3,
-    GSDF_K_FINALIZE = 4,
+    GSDF_K_NORMALS = 4,
     GSDF_K_BACKWARD = 5,
     GSDF_K_COUNT = 16
 };

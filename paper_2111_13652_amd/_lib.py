@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libgsdf.so")
 
 OK, EINVAL, ECAPACITY, EHIP, ENOTPD, ELOST = 0, -1, -2, -3, -4, -5
 FP32, BF16, FP16 = 0, 1, 2
-K_ALLOCATE, K_INTEGRATE, K_TRACK, K_PYRAMID, K_FINALIZE, K_BACKWARD = 0, 1, 2, 3, 4, 5
+K_ALLOCATE, K_INTEGRATE, K_TRACK, K_PYRAMID, K_NORMALS, K_BACKWARD = 0, 1, 2, 3, 4, 5
 
 
 class MapDesc(C.Structure):
@@ -53,7 +53,10 @@ _SIGNATURES = {
     "gsdf_map_reset": (_I, [C.POINTER(Map), _P]),
     "gsdf_map_num_blocks": (_I, [C.POINTER(Map), _P, _P]),
     "gsdf_allocate_blocks": (_I, [C.POINTER(Map), _P, C.POINTER(Camera), _P, _P, _P]),
-    "gsdf_integrate_frame": (_I, [C.POINTER(Map), _P, C.POINTER(Camera), _P, C.POINTER(FuseParams), _P, _P]),
+    "gsdf_integrate_scratch_bytes": (_SZ, [C.POINTER(Camera)]),
+    "gsdf_integrate_frame": (_I, [C.POINTER(Map), _P, C.POINTER(Camera), _P, C.POINTER(FuseParams), _P,
+                                  _SZ, _P, _P]),
+    "gsdf_map_counters": (_I, [C.POINTER(Map), _P, _P]),
     "gsdf_track_scratch_bytes": (_SZ, [C.POINTER(Camera), _I32]),
     "gsdf_track_frame": (_I, [C.POINTER(Map), _P, C.POINTER(Camera), C.POINTER(TrackParams), _P, _P, _P,
                               _SZ, _P, _P]),

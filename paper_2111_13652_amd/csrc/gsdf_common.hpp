@@ -67,15 +67,11 @@ struct alignas(16) HashEntry {
 
 // Voxel index inside a block: Morton order of (lx, ly, lz), so every 2x2x2
 // sub-cube (8 voxels) is contiguous.
+__host__ __device__ inline int spread3(int x) {  // bits b0 b1 b2 -> positions 0, 3, 6
+    return (x & 1) | ((x & 2) << 2) | ((x & 4) << 4);
+}
 __host__ __device__ inline int morton9(int lx, int ly, int lz) {
-    int r = 0;
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-        r |= ((lx >> b) & 1) << (3 * b);
-        r |= ((ly >> b) & 1) << (3 * b + 1);
-        r |= ((lz >> b) & 1) << (3 * b + 2);
-    }
-    return r;
+    return spread3(lx) | (spread3(ly) << 1) | (spread3(lz) << 2);
 }
 
 __host__ __device__ inline void demorton9(int r, int* lx, int* ly, int* lz) {
@@ -113,13 +109,29 @@ __device__ inline unsigned short pack16(float f, int storage) {
 struct AuxLayout {
     size_t block_keys;   // uint64 per pool slot
     size_t counters;     // 64 int32
+    size_t stats;        // 16 uint64 work counters (cumulative since reset)
     size_t touched_flag; // int32 per pool slot (per-frame touched marker)
-    size_t touched_list; // int32 per pool slot
-    size_t accum;        // float per voxel x 5 (reduced-precision storage only)
     size_t total;
 };
 
-enum Counter { kNumBlocks = 0, kNumTouched = 1 };
+enum Counter { kNumBlocks = 0 };
+
+// Work counters are striped over kStatStripes addresses (work-group b adds
+// into stripe b mod kStatStripes): device-scope atomics on one address
+// serialise, so a counter hit by thousands of work-groups must be spread.
+constexpr int kStatStripes = 64;
+
+// Work counters, used to state the algorithmic bytes a run moved.
+enum Stat {
+    kStatUpdates = 0,       // (pixel, voxel) fusion updates applied
+    kStatPixelVisits = 1,   // (block, pixel) visits by the fusion gather
+    kStatFusedVoxels = 2,   // voxels written by fusion
+    kStatFusedBlocks = 3,   // touched blocks processed by fusion
+    kStatAllocPairs = 4,    // distinct (tile, block) pairs probed by allocation
+    kStatTrackValid = 5,    // valid pixel-iterations in tracking
+    kStatTrackUsed = 6,     // pixel-iterations that found an observed voxel
+    kStatCount = 16
+};
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -129,10 +141,8 @@ __host__ __device__ inline AuxLayout aux_layout(const gsdf_map_desc& d) {
     size_t o = 0;
     a.block_keys = o;   o = align256(o + nb * 8);
     a.counters = o;     o = align256(o + 64 * 4);
+    a.stats = o;        o = align256(o + (size_t)kStatCount * kStatStripes * 8);
     a.touched_flag = o; o = align256(o + nb * 4);
-    a.touched_list = o; o = align256(o + nb * 4);
-    a.accum = o;
-    if (d.storage != GSDF_FP32) o = align256(o + nb * kBlockVoxels * 5 * 4);
     a.total = o;
     return a;
 }
@@ -145,9 +155,8 @@ struct MapView {
     float* weight;
     uint64_t* block_keys;
     int32_t* counters;
+    unsigned long long* stats;
     int32_t* touched_flag;
-    int32_t* touched_list;
-    float* accum;
     int32_t max_blocks;
     int32_t bounded;
     int32_t bmin[3], bmax[3];
@@ -167,9 +176,8 @@ inline MapView make_view(const gsdf_map& m) {
     v.weight = (float*)m.weight;
     v.block_keys = (uint64_t*)(aux + a.block_keys);
     v.counters = (int32_t*)(aux + a.counters);
+    v.stats = (unsigned long long*)(aux + a.stats);
     v.touched_flag = (int32_t*)(aux + a.touched_flag);
-    v.touched_list = (int32_t*)(aux + a.touched_list);
-    v.accum = m.desc.storage != GSDF_FP32 ? (float*)(aux + a.accum) : nullptr;
     v.max_blocks = (int32_t)m.desc.max_blocks;
     v.bounded = m.desc.bounded;
     for (int i = 0; i < 3; ++i) {
@@ -207,33 +215,70 @@ __device__ inline int32_t hash_find(const MapView& M, int bx, int by, int bz) {
 }
 
 // Insert a block key if absent.  The winner of the compare-and-swap takes a
-// pool slot from the block counter.  Returns the number of blocks created
-// by this call (0 or 1).
-__device__ inline int hash_insert(const MapView& M, int bx, int by, int bz, int32_t* status) {
+// pool slot from the block counter.  Returns the block's pool slot when it
+// is known to this thread (-1 while another thread is still assigning it,
+// or when the table or pool is full); *created = 1 for the inserting thread.
+__device__ inline int32_t hash_insert(const MapView& M, int bx, int by, int bz, int32_t* status,
+                                      int* created) {
+    *created = 0;
     const uint64_t key = pack_key(bx, by, bz);
     uint64_t h = mix64(key) & M.mask;
     for (uint64_t probe = 0; probe <= M.mask; ++probe) {
         unsigned long long* kp = reinterpret_cast<unsigned long long*>(&M.hash[h].key);
-        uint64_t k = *kp;
-        if (k == key) return 0;
+        const uint4 e = *reinterpret_cast<const uint4*>(&M.hash[h]);
+        const uint64_t k = (uint64_t)e.x | ((uint64_t)e.y << 32);
+        if (k == key) return (int32_t)e.z;
         if (k == kEmptyKey) {
-            uint64_t old = atomicCAS(kp, (unsigned long long)kEmptyKey, (unsigned long long)key);
+            const uint64_t old = atomicCAS(kp, (unsigned long long)kEmptyKey, (unsigned long long)key);
             if (old == kEmptyKey) {
-                int32_t slot = atomicAdd(&M.counters[kNumBlocks], 1);
+                const int32_t slot = atomicAdd(&M.counters[kNumBlocks], 1);
                 if (slot < M.max_blocks) {
                     M.hash[h].slot = slot;
                     M.block_keys[slot] = key;
-                    return 1;
+                    *created = 1;
+                    return slot;
                 }
                 raise_status(status, GSDF_ECAPACITY);
-                return 0;
+                return -1;
             }
-            if (old == key) return 0;
+            if (old == key) return -1;  // inserted concurrently: slot not known yet
         }
         h = (h + 1) & M.mask;
     }
     raise_status(status, GSDF_ECAPACITY);
-    return 0;
+    return -1;
+}
+
+// Sum over the 64 lanes of a wave (every lane gets the total).
+__device__ inline unsigned long long wave_sum_u64(unsigned long long x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// Record that a block is touched by the current frame: an idempotent flag
+// (plain stores; the fusion kernel that consumes it runs later).
+__device__ inline void mark_touched(const MapView& M, int32_t slot) {
+    if (M.touched_flag[slot] == 0) M.touched_flag[slot] = 1;
+}
+
+// Sum over a work-group (every thread passes its value; thread 0 gets the
+// total).  `scratch` holds one entry per wave.
+__device__ inline unsigned long long block_sum_u64(unsigned long long x, unsigned long long* scratch) {
+    x = wave_sum_u64(x);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) scratch[wave] = x;
+    __syncthreads();
+    unsigned long long t = 0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)((blockDim.x + 63) / 64); ++w) t += scratch[w];
+    __syncthreads();
+    return t;
+}
+
+// Add to a work counter (one call per work-group).
+__device__ inline void add_stat(const MapView& M, int k, unsigned long long v) {
+    if (v) atomicAdd(&M.stats[(size_t)k * kStatStripes + (blockIdx.x & (kStatStripes - 1))], v);
 }
 
 // ---------------------------------------------------------------------------

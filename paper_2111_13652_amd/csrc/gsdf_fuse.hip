@@ -1,22 +1,28 @@
 // integrate_frame: normals from a 5x5 plane fit, the viewing-angle filter,
 // and the running weighted average of SDF and gradient, Eq. (1)-(3) of
-// Gradient-SDF (Sec. 3.1, 3.2), driven pixel by pixel as in the Sec. 5.3
+// Gradient-SDF (Sec. 3.1, 3.2), driven by depth pixels as in the Sec. 5.3
 // setup.
 //
-// One work-group covers a 16x16 pixel tile; its depths plus a 2-pixel halo
-// are staged in LDS once, so the 25-tap normal fit reads LDS only.  Every
-// pixel then walks its ray band (the binary32 rule shared with allocation)
-// and adds w d, w n_w and w into the voxels it crosses.
+// Two kernels.
+//  1. k_pixel_normals: one work-group per 16x16 pixel tile with its 2-pixel
+//     halo staged in LDS; every pixel gets its world-frame normal and depth
+//     (float4), or zeros when it fails the window or the angle test.
+//  2. k_fuse_blocks: one work-group per block touched by the frame (the
+//     allocation step flags them).  It projects the block's box into the
+//     image, walks the pixels of that rectangle, clips each pixel's ray to
+//     the box to find the few band samples that can land inside, evaluates
+//     exactly those samples with the binary32 band rule, and adds w d, w n_w
+//     and w into a 512-voxel accumulator in LDS.  The block then writes each
+//     voxel it changed once.  Each block is owned by one work-group per
+//     frame, so no global atomics are needed and every touched voxel costs
+//     one read and one write of its record.
 //
 // FP32 storage keeps, per voxel, float4 {sum w d, g_x, g_y, g_z} and W:
 // psi = (sum w d) / W is Eq. (1)-(2) unrolled over all observations and g
-// is Eq. (3) exactly, so the update is pure addition (hardware float
-// atomics, no second pass).  Reduced-precision storage keeps normalised
-// values that must be averaged: the pixel pass adds into per-voxel float32
-// accumulators and a second pass over the touched blocks applies Eq. (1)-(3)
-// and rounds once per frame.
+// is Eq. (3) exactly, so the write is an addition.  16-bit storage keeps
+// {psi/T, gbar} (gbar = g / W, bounded) and applies Eq. (1)-(3) with the
+// frame's sums before rounding once.
 #include <hip/hip_runtime.h>
-#include <hip/hip_fp16.h>
 
 #include <climits>
 
@@ -28,16 +34,19 @@ namespace gsdf {
 constexpr int kTile = 16;
 constexpr int kHalo = 2;
 constexpr int kTileH = kTile + 2 * kHalo;
+constexpr int kFuseBlock = 256;
+constexpr int kFuseGroups = 4096;
+constexpr float kBoxMargin = 1e-4f;  // metres; far above binary32 rounding of coordinates
 
 struct FuseConsts {
     BandConsts band;
-    float fxf, fyf, cxf, cyf;     // float32 intrinsics for the normal fit
-    float rcx, rcy;               // (float) cx, cy
-    double ifx_d, ify_d, cx_d, cy_d;
+    float fxf, fyf, rcx, rcy;     // float32 intrinsics for the normal fit
+    double fx_d, fy_d, ifx_d, ify_d, cx_d, cy_d;
     float zmin, zmax;
     float eps, cos_min;
     double inv_vs_d, vs_d;
     float vs_f, T_f;
+    float inv_df;   // 1 / band sample spacing
     int W, H;
 };
 
@@ -47,10 +56,12 @@ __device__ inline float linear_weight(float d, float eps, float T) {
     return (T - d) / (T - eps);
 }
 
-template <int STORAGE>
-__global__ __launch_bounds__(256) void k_integrate(MapView M, const float* __restrict__ depth,
-                                                   FuseConsts fc, const double* __restrict__ Twc,
-                                                   int32_t* status) {
+// ---------------------------------------------------------------------------
+// 1. Normals
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pixel_normals(const float* __restrict__ depth, FuseConsts fc,
+                                                       const double* __restrict__ Twc,
+                                                       float4* __restrict__ pix) {
     __shared__ float tile[kTileH][kTileH + 1];
     const int tx = threadIdx.x & (kTile - 1);
     const int ty = threadIdx.x / kTile;
@@ -67,205 +78,366 @@ __global__ __launch_bounds__(256) void k_integrate(MapView M, const float* __res
 
     const int u = blockIdx.x * kTile + tx;
     const int v = blockIdx.y * kTile + ty;
-    if (u < kHalo || v < kHalo || u >= fc.W - kHalo || v >= fc.H - kHalo) return;
+    if (u >= fc.W || v >= fc.H) return;
+    float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
     const float Dc = tile[ty + kHalo][tx + kHalo];
-    if (!depth_ok(Dc, fc.zmin, fc.zmax)) return;
-
-    // ---- normal: least-squares plane 1/z = a . [x/z, y/z, 1] on the 5x5
-    // window.  Over the symmetric window the design (1, du, dv) is
-    // orthogonal, so the fit has a closed form in the centred inverse depths
-    // 1/D_i - 1/D_c = (D_c - D_i) / (D_i D_c), whose numerators are exact.
-    float s0 = 0.0f, sa = 0.0f, sb = 0.0f;
-    bool ok = true;
+    if (u >= kHalo && v >= kHalo && u < fc.W - kHalo && v < fc.H - kHalo &&
+        depth_ok(Dc, fc.zmin, fc.zmax)) {
+        // least-squares plane 1/z = a . [x/z, y/z, 1] on the 5x5 window.
+        // Over the symmetric window the design (1, du, dv) is orthogonal, so
+        // the fit has a closed form in the centred inverse depths
+        // 1/D_i - 1/D_c = (D_c - D_i) / (D_i D_c), whose numerators are exact.
+        float s0 = 0.0f, sa = 0.0f, sb = 0.0f;
+        bool ok = true;
 #pragma unroll
-    for (int dv = -kHalo; dv <= kHalo; ++dv) {
+        for (int dv = -kHalo; dv <= kHalo; ++dv) {
 #pragma unroll
-        for (int du = -kHalo; du <= kHalo; ++du) {
-            const float Di = tile[ty + kHalo + dv][tx + kHalo + du];
-            ok = ok && depth_ok(Di, fc.zmin, fc.zmax) && (fabsf(Di - Dc) <= fc.band.Tf);
-            const float dy = (Dc - Di) / (Di * Dc);
-            s0 += dy;
-            sa += (float)du * dy;
-            sb += (float)dv * dy;
-        }
-    }
-    if (!ok) return;
-    const float h = 1.0f / Dc + s0 * (1.0f / 25.0f);
-    const float alpha = sa * (1.0f / 50.0f);   // sum du^2 = 50 over the window
-    const float beta = sb * (1.0f / 50.0f);
-    const float ax = alpha * fc.fxf;
-    const float ay = beta * fc.fyf;
-    const float az = h - alpha * ((float)u - fc.rcx) - beta * ((float)v - fc.rcy);
-    const float na = sqrtf(ax * ax + ay * ay + az * az);
-    const float rx = ((float)u - fc.rcx) / fc.fxf;
-    const float ry = ((float)v - fc.rcy) / fc.fyf;
-    const float cosang = h / (na * sqrtf(rx * rx + ry * ry + 1.0f));
-    if (!(cosang >= fc.cos_min)) return;
-    const float nc[3] = {ax / na, ay / na, az / na};   // a . ray = h > 0: faces away
-
-    // ---- pose: rotate the normal; observed point in float64, kept as an
-    // offset from a nearby voxel so voxel-to-point vectors stay small.
-    double Rd[9], td[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j) Rd[3 * i + j] = Twc[4 * i + j];
-        td[i] = Twc[4 * i + 3];
-    }
-    float nw[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-        nw[i] = (float)Rd[3 * i] * nc[0] + (float)Rd[3 * i + 1] * nc[1] + (float)Rd[3 * i + 2] * nc[2];
-    const double Dd = (double)Dc;
-    const double x[3] = {Dd * (((double)u - fc.cx_d) * fc.ifx_d), Dd * (((double)v - fc.cy_d) * fc.ify_d), Dd};
-    int mref[3];
-    float prel[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const double p = Rd[3 * i] * x[0] + Rd[3 * i + 1] * x[1] + Rd[3 * i + 2] * x[2] + td[i];
-        mref[i] = (int)floor(p * fc.inv_vs_d + 0.5);
-        prel[i] = (float)(p - fc.vs_d * (double)mref[i]);
-    }
-
-    // ---- walk the ray band
-    const BandRule br = make_band_rule(Twc, fc.band.ifx, fc.band.ify, fc.band.cxf, fc.band.cyf,
-                                       fc.band.invvs, fc.band.Tf, fc.band.Df, fc.band.nsamples);
-    const float xr = pixel_xr(br, u);
-    const float yr = pixel_yr(br, v);
-    int pm[3] = {INT_MIN, INT_MIN, INT_MIN};
-    int cb[3] = {INT_MIN, INT_MIN, INT_MIN};
-    int32_t slot = -1;
-    for (int k = 0; k < br.nsamples; ++k) {
-        int m[3];
-        if (!band_sample(br, xr, yr, Dc, k, m)) continue;
-        if (m[0] == pm[0] && m[1] == pm[1] && m[2] == pm[2]) continue;
-        pm[0] = m[0];
-        pm[1] = m[1];
-        pm[2] = m[2];
-        const int bx = block_of(m[0]), by = block_of(m[1]), bz = block_of(m[2]);
-        if (bx != cb[0] || by != cb[1] || bz != cb[2]) {
-            cb[0] = bx;
-            cb[1] = by;
-            cb[2] = bz;
-            slot = hash_find(M, bx, by, bz);
-            if (STORAGE != GSDF_FP32 && slot >= 0) {
-                if (__hip_atomic_load(&M.touched_flag[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
-                    atomicCAS(&M.touched_flag[slot], 0, 1) == 0) {
-                    const int32_t pos = atomicAdd(&M.counters[kNumTouched], 1);
-                    M.touched_list[pos] = slot;
-                }
+            for (int du = -kHalo; du <= kHalo; ++du) {
+                const float Di = tile[ty + kHalo + dv][tx + kHalo + du];
+                ok = ok && depth_ok(Di, fc.zmin, fc.zmax) && (fabsf(Di - Dc) <= fc.band.Tf);
+                const float dy = (Dc - Di) / (Di * Dc);
+                s0 += dy;
+                sa += (float)du * dy;
+                sb += (float)dv * dy;
             }
         }
-        if (slot < 0) continue;
-        float off[3];
+        if (ok) {
+            const float h = 1.0f / Dc + s0 * (1.0f / 25.0f);
+            const float alpha = sa * (1.0f / 50.0f);   // sum du^2 = 50 over the window
+            const float beta = sb * (1.0f / 50.0f);
+            const float ax = alpha * fc.fxf;
+            const float ay = beta * fc.fyf;
+            const float az = h - alpha * ((float)u - fc.rcx) - beta * ((float)v - fc.rcy);
+            const float na = sqrtf(ax * ax + ay * ay + az * az);
+            const float rx = ((float)u - fc.rcx) / fc.fxf;
+            const float ry = ((float)v - fc.rcy) / fc.fyf;
+            const float cosang = h / (na * sqrtf(rx * rx + ry * ry + 1.0f));
+            if (cosang >= fc.cos_min) {
+                // a . ray = h > 0: the normal faces away from the camera
+                const float n0 = ax / na, n1 = ay / na, n2 = az / na;
+                float nw[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) off[i] = fc.vs_f * (float)(m[i] - mref[i]) - prel[i];
-        float d = nw[0] * off[0] + nw[1] * off[1] + nw[2] * off[2];
-        d = fminf(fc.T_f, fmaxf(-fc.T_f, d));
-        const float w = linear_weight(d, fc.eps, fc.T_f);
-        if (!(w > 0.0f)) continue;
-        const int64_t vi = (int64_t)slot * kBlockVoxels + morton9(m[0] & 7, m[1] & 7, m[2] & 7);
-        if (STORAGE == GSDF_FP32) {
-            float* rec = reinterpret_cast<float*>(M.vox) + 4 * vi;
-            unsafeAtomicAdd(rec + 0, w * d);
-            unsafeAtomicAdd(rec + 1, w * nw[0]);
-            unsafeAtomicAdd(rec + 2, w * nw[1]);
-            unsafeAtomicAdd(rec + 3, w * nw[2]);
-            unsafeAtomicAdd(M.weight + vi, w);
-        } else {
-            float* acc = M.accum + 5 * vi;
-            unsafeAtomicAdd(acc + 0, w * d);
-            unsafeAtomicAdd(acc + 1, w * nw[0]);
-            unsafeAtomicAdd(acc + 2, w * nw[1]);
-            unsafeAtomicAdd(acc + 3, w * nw[2]);
-            unsafeAtomicAdd(acc + 4, w);
+                for (int i = 0; i < 3; ++i)
+                    nw[i] = (float)Twc[4 * i] * n0 + (float)Twc[4 * i + 1] * n1 + (float)Twc[4 * i + 2] * n2;
+                out = make_float4(nw[0], nw[1], nw[2], Dc);
+            }
         }
     }
+    pix[(size_t)v * fc.W + u] = out;
 }
 
-// ---- reduced-precision storage: apply the frame's sums to touched blocks ----
-__global__ __launch_bounds__(256) void k_finalize(MapView M, int storage) {
-    const int n = M.counters[kNumTouched];
-    for (int b = blockIdx.x; b < n; b += gridDim.x) {
-        const int slot = M.touched_list[b];
-        for (int c = threadIdx.x; c < kBlockVoxels; c += blockDim.x) {
-            const int64_t vi = (int64_t)slot * kBlockVoxels + c;
-            float* acc = M.accum + 5 * vi;
-            const float sw = acc[4];
-            if (!(sw > 0.0f)) continue;
-            const float Wold = M.weight[vi];
-            const ushort4 p = reinterpret_cast<const ushort4*>(M.vox)[vi];
-            const float psi_old = unpack16(p.x, storage) * M.truncation;
-            const float Wn = Wold + sw;
-            const float psi = (Wold * psi_old + acc[0]) / Wn;
-            const float g0 = (Wold * unpack16(p.y, storage) + acc[1]) / Wn;
-            const float g1 = (Wold * unpack16(p.z, storage) + acc[2]) / Wn;
-            const float g2 = (Wold * unpack16(p.w, storage) + acc[3]) / Wn;
-            reinterpret_cast<ushort4*>(M.vox)[vi] =
-                make_ushort4(pack16(psi / M.truncation, storage), pack16(g0, storage),
-                             pack16(g1, storage), pack16(g2, storage));
-            M.weight[vi] = Wn;
-            acc[0] = 0.0f;
-            acc[1] = 0.0f;
-            acc[2] = 0.0f;
-            acc[3] = 0.0f;
-            acc[4] = 0.0f;
+// ---------------------------------------------------------------------------
+// 2. Per-block gather
+// ---------------------------------------------------------------------------
+struct BlockBox {
+    int u0, u1, v0, v1;       // inclusive pixel rectangle (u1 < u0: empty)
+    float lo[3], hi[3];       // box relative to the camera centre, with margin
+    float zmin, zmax;         // camera-frame depth range of the box corners
+    float inv_bw;             // 1 / rectangle width
+};
+
+__device__ inline void block_box(const FuseConsts& fc, const double* R, const double* t, int bx,
+                                 int by, int bz, BlockBox* B) {
+    const int b[3] = {bx, by, bz};
+    double lo[3], hi[3], mag = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        lo[i] = fc.vs_d * (8.0 * b[i] - 0.5);
+        hi[i] = fc.vs_d * (8.0 * b[i] + 7.5);
+        mag = fmax(mag, fmax(fabs(lo[i]), fabs(hi[i])) + fabs(t[i]));
+    }
+    // the margin stays far above the binary32 rounding of sample positions
+    // (a few ulps of the coordinate magnitude)
+    const double margin = kBoxMargin + 4e-6 * mag;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        lo[i] -= margin;
+        hi[i] += margin;
+        B->lo[i] = (float)(lo[i] - t[i]);
+        B->hi[i] = (float)(hi[i] - t[i]);
+    }
+    double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300, zlo = 1e300, zhi = -1e300;
+    bool behind = false;
+    for (int c = 0; c < 8; ++c) {
+        const double X[3] = {(c & 1) ? hi[0] : lo[0], (c & 2) ? hi[1] : lo[1], (c & 4) ? hi[2] : lo[2]};
+        double pc[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            pc[j] = R[j] * (X[0] - t[0]) + R[3 + j] * (X[1] - t[1]) + R[6 + j] * (X[2] - t[2]);
+        zlo = fmin(zlo, pc[2]);
+        zhi = fmax(zhi, pc[2]);
+        if (pc[2] <= 1e-6) behind = true;
+        if (behind) continue;
+        const double u = fc.fx_d * pc[0] / pc[2] + fc.cx_d;
+        const double v = fc.fy_d * pc[1] / pc[2] + fc.cy_d;
+        umin = fmin(umin, u);
+        umax = fmax(umax, u);
+        vmin = fmin(vmin, v);
+        vmax = fmax(vmax, v);
+    }
+    B->zmin = (float)zlo;
+    B->zmax = (float)zhi;
+    if (behind) {
+        B->u0 = 0;
+        B->u1 = fc.W - 1;
+        B->v0 = 0;
+        B->v1 = fc.H - 1;
+        B->inv_bw = 1.0f / (float)fc.W;
+        return;
+    }
+    // clamp in double before converting: far-off projections stay in range
+    B->u0 = (int)fmin(fmax(0.0, floor(umin) - 1.0), (double)fc.W);
+    B->u1 = (int)fmax(fmin((double)(fc.W - 1), ceil(umax) + 1.0), -1.0);
+    B->v0 = (int)fmin(fmax(0.0, floor(vmin) - 1.0), (double)fc.H);
+    B->v1 = (int)fmax(fmin((double)(fc.H - 1), ceil(vmax) + 1.0), -1.0);
+    B->inv_bw = B->u1 >= B->u0 ? 1.0f / (float)(B->u1 - B->u0 + 1) : 0.0f;
+}
+
+template <int STORAGE>
+__global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const float4* __restrict__ pix,
+                                                           FuseConsts fc, const double* __restrict__ Twc) {
+    __shared__ float aS[kBlockVoxels];
+    __shared__ float aG[3][kBlockVoxels];
+    __shared__ float aW[kBlockVoxels];
+    __shared__ BlockBox box;
+
+    double R[9], t[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) R[3 * i + j] = Twc[4 * i + j];
+        t[i] = Twc[4 * i + 3];
+    }
+    const float Rf[9] = {(float)R[0], (float)R[1], (float)R[2], (float)R[3], (float)R[4],
+                         (float)R[5], (float)R[6], (float)R[7], (float)R[8]};
+    const BandRule br = make_band_rule(Twc, fc.band.ifx, fc.band.ify, fc.band.cxf, fc.band.cyf,
+                                       fc.band.invvs, fc.band.Tf, fc.band.Df, fc.band.nsamples);
+    int n_blocks = M.counters[kNumBlocks];
+    n_blocks = n_blocks < M.max_blocks ? n_blocks : M.max_blocks;
+    unsigned long long my_updates = 0, my_visits = 0, my_voxels = 0, my_blocks = 0;
+
+    for (int slot = blockIdx.x; slot < n_blocks; slot += gridDim.x) {
+        if (M.touched_flag[slot] == 0) continue;   // uniform across the work-group
+        ++my_blocks;
+        int bx, by, bz;
+        unpack_key(M.block_keys[slot], &bx, &by, &bz);
+        for (int c = threadIdx.x; c < kBlockVoxels; c += kFuseBlock) {
+            aS[c] = 0.0f;
+            aG[0][c] = 0.0f;
+            aG[1][c] = 0.0f;
+            aG[2][c] = 0.0f;
+            aW[c] = 0.0f;
+        }
+        if (threadIdx.x == 0) block_box(fc, R, t, bx, by, bz, &box);
+        __syncthreads();
+
+        const int bw = box.u1 - box.u0 + 1;
+        const int bh = box.v1 - box.v0 + 1;
+        const int npx = (bw > 0 && bh > 0) ? bw * bh : 0;
+        // lane-major order: the 64 lanes of a wave take pixels npx/64 apart,
+        // so their samples fall in different voxels and the LDS atomics of
+        // one instruction rarely collide
+        const int lane_stride = (npx + 63) / 64;
+        const float inv_bw = box.inv_bw;
+        // the depth band [D - T, D + T] must reach the box's depth range
+        const float zreach_lo = box.zmin - fc.band.Tf - fc.band.Df;
+        const float zreach_hi = box.zmax + fc.band.Tf + fc.band.Df;
+        for (int p = threadIdx.x; p < lane_stride * 64; p += kFuseBlock) {
+            const int q = (p & 63) * lane_stride + (p >> 6);
+            if (q >= npx) continue;
+            // row and column without an integer division (q < 2^24 is exact)
+            int row = (int)(((float)q + 0.5f) * inv_bw);
+            int col = q - row * bw;
+            if (col < 0) {
+                --row;
+                col += bw;
+            } else if (col >= bw) {
+                ++row;
+                col -= bw;
+            }
+            const int u = box.u0 + col;
+            const int v = box.v0 + row;
+            const float4 px = pix[(size_t)v * fc.W + u];
+            const float D = px.w;
+            if (!(D > 0.0f)) continue;
+            if (D < zreach_lo || D > zreach_hi) continue;
+            ++my_visits;
+            // clip the pixel's ray z * (R ray) to the block's box (the box's
+            // margin absorbs the approximate reciprocals)
+            const float xr = pixel_xr(br, u);
+            const float yr = pixel_yr(br, v);
+            float zin = 0.0f, zout = 3.0e38f;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const float dir = Rf[3 * i] * xr + Rf[3 * i + 1] * yr + Rf[3 * i + 2];
+                if (fabsf(dir) < 1e-20f) {
+                    if (box.lo[i] > 0.0f || box.hi[i] < 0.0f) zout = -1.0f;
+                } else {
+                    const float id = __builtin_amdgcn_rcpf(dir);
+                    const float a = box.lo[i] * id, b = box.hi[i] * id;
+                    zin = fmaxf(zin, fminf(a, b));
+                    zout = fminf(zout, fmaxf(a, b));
+                }
+            }
+            // samples inside the box widened by kBoxMargin: no other sample can
+            // land in a voxel of this block (binary32 rounding of a sample's
+            // position is far below the margin), so the run structure of the
+            // consecutive-repeat rule inside the block is the same as over
+            // the whole band
+            const float zb0 = D - fc.band.Tf;  // first band sample
+            if (!(zin <= zout)) continue;
+            const float last = (float)(fc.band.nsamples - 1);
+            const float inv_df = fc.inv_df;
+            const int k0 = (int)fmaxf(0.0f, ceilf(fminf((zin - zb0) * inv_df, last + 1.0f)));
+            const int k1 = (int)fminf(last, floorf(fmaxf((zout - zb0) * inv_df, -1.0f)));
+            if (k0 > k1) continue;
+
+            // observed point in float64, kept as an offset from a nearby voxel
+            const double Dd = (double)D;
+            const double x0 = Dd * (((double)u - fc.cx_d) * fc.ifx_d);
+            const double x1 = Dd * (((double)v - fc.cy_d) * fc.ify_d);
+            int mref[3];
+            float prel[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double q = R[3 * i] * x0 + R[3 * i + 1] * x1 + R[3 * i + 2] * Dd + t[i];
+                mref[i] = (int)floor(q * fc.inv_vs_d + 0.5);
+                prel[i] = (float)(q - fc.vs_d * (double)mref[i]);
+            }
+            int pm[3] = {INT_MIN, INT_MIN, INT_MIN};
+            for (int k = k0; k <= k1; ++k) {
+                int m[3];
+                if (!band_sample(br, xr, yr, D, k, m)) continue;
+                if (m[0] == pm[0] && m[1] == pm[1] && m[2] == pm[2]) continue;
+                pm[0] = m[0];
+                pm[1] = m[1];
+                pm[2] = m[2];
+                if (block_of(m[0]) != bx || block_of(m[1]) != by || block_of(m[2]) != bz) continue;
+                float off[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) off[i] = fc.vs_f * (float)(m[i] - mref[i]) - prel[i];
+                float d = px.x * off[0] + px.y * off[1] + px.z * off[2];
+                d = fminf(fc.T_f, fmaxf(-fc.T_f, d));
+                const float w = linear_weight(d, fc.eps, fc.T_f);
+                if (!(w > 0.0f)) continue;
+                const int c = morton9(m[0] & 7, m[1] & 7, m[2] & 7);
+                atomicAdd(&aS[c], w * d);
+                atomicAdd(&aG[0][c], w * px.x);
+                atomicAdd(&aG[1][c], w * px.y);
+                atomicAdd(&aG[2][c], w * px.z);
+                atomicAdd(&aW[c], w);
+                ++my_updates;
+            }
         }
         __syncthreads();
+
+        // write the voxels this frame changed: this work-group owns the block
+        for (int c = threadIdx.x; c < kBlockVoxels; c += kFuseBlock) {
+            const float sw = aW[c];
+            if (!(sw > 0.0f)) continue;
+            ++my_voxels;
+            const int64_t vi = (int64_t)slot * kBlockVoxels + c;
+            if (STORAGE == GSDF_FP32) {
+                float4* rec = reinterpret_cast<float4*>(M.vox) + vi;
+                float4 r = *rec;
+                r.x += aS[c];
+                r.y += aG[0][c];
+                r.z += aG[1][c];
+                r.w += aG[2][c];
+                *rec = r;
+                M.weight[vi] += sw;
+            } else {
+                ushort4* rec = reinterpret_cast<ushort4*>(M.vox) + vi;
+                const ushort4 p = *rec;
+                const float Wold = M.weight[vi];
+                const float Wn = Wold + sw;
+                const float psi = (Wold * unpack16(p.x, STORAGE) * M.truncation + aS[c]) / Wn;
+                const float g0 = (Wold * unpack16(p.y, STORAGE) + aG[0][c]) / Wn;
+                const float g1 = (Wold * unpack16(p.z, STORAGE) + aG[1][c]) / Wn;
+                const float g2 = (Wold * unpack16(p.w, STORAGE) + aG[2][c]) / Wn;
+                *rec = make_ushort4(pack16(psi / M.truncation, STORAGE), pack16(g0, STORAGE),
+                                    pack16(g1, STORAGE), pack16(g2, STORAGE));
+                M.weight[vi] = Wn;
+            }
+        }
         if (threadIdx.x == 0) M.touched_flag[slot] = 0;
+        __syncthreads();
+    }
+
+    // work counters: one striped atomic per work-group and counter
+    __shared__ unsigned long long red[kFuseBlock / 64];
+    const unsigned long long u_s = block_sum_u64(my_updates, red);
+    const unsigned long long v_s = block_sum_u64(my_visits, red);
+    const unsigned long long x_s = block_sum_u64(my_voxels, red);
+    if (threadIdx.x == 0) {
+        add_stat(M, kStatUpdates, u_s);
+        add_stat(M, kStatPixelVisits, v_s);
+        add_stat(M, kStatFusedVoxels, x_s);
+        add_stat(M, kStatFusedBlocks, my_blocks);
     }
 }
 
-__global__ void k_finalize_done(MapView M) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) M.counters[kNumTouched] = 0;
+inline FuseConsts fuse_consts(const gsdf_map& map, const gsdf_camera& cam, const gsdf_fuse_params& p) {
+    FuseConsts fc;
+    fc.band = band_consts(cam, map.desc.voxel_size, map.desc.truncation);
+    fc.fxf = (float)cam.fx;
+    fc.fyf = (float)cam.fy;
+    fc.rcx = (float)cam.cx;
+    fc.rcy = (float)cam.cy;
+    fc.fx_d = cam.fx;
+    fc.fy_d = cam.fy;
+    fc.ifx_d = 1.0 / cam.fx;
+    fc.ify_d = 1.0 / cam.fy;
+    fc.cx_d = cam.cx;
+    fc.cy_d = cam.cy;
+    fc.zmin = cam.zmin;
+    fc.zmax = cam.zmax;
+    fc.eps = p.eps_weight;
+    fc.cos_min = p.cos_max_angle;
+    fc.inv_vs_d = 1.0 / map.desc.voxel_size;
+    fc.vs_d = map.desc.voxel_size;
+    fc.vs_f = (float)map.desc.voxel_size;
+    fc.T_f = (float)map.desc.truncation;
+    fc.inv_df = (float)(2.0 / map.desc.voxel_size);
+    fc.W = cam.width;
+    fc.H = cam.height;
+    return fc;
 }
 
 }  // namespace gsdf
 
 using namespace gsdf;
 
+extern "C" size_t gsdf_integrate_scratch_bytes(const gsdf_camera* cam) {
+    if (!valid_cam(cam)) return 0;
+    return align256((size_t)cam->width * cam->height * sizeof(float4));
+}
+
 extern "C" int gsdf_integrate_frame(gsdf_map* map, const float* depth_dev, const gsdf_camera* cam,
                                     const double* T_wc_dev, const gsdf_fuse_params* params,
-                                    int32_t* status_dev, void* stream) {
-    if (!valid_map(map) || !depth_dev || !valid_cam(cam) || !T_wc_dev || !params) return GSDF_EINVAL;
+                                    void* scratch_dev, size_t scratch_bytes, int32_t* status_dev,
+                                    void* stream) {
+    (void)status_dev;
+    if (!valid_map(map) || !depth_dev || !valid_cam(cam) || !T_wc_dev || !params || !scratch_dev)
+        return GSDF_EINVAL;
     if (!(params->eps_weight < map->desc.truncation)) return GSDF_EINVAL;
+    if (scratch_bytes < gsdf_integrate_scratch_bytes(cam)) return GSDF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    FuseConsts fc;
-    fc.band = band_consts(*cam, map->desc.voxel_size, map->desc.truncation);
-    fc.fxf = (float)cam->fx;
-    fc.fyf = (float)cam->fy;
-    fc.cxf = (float)cam->cx;
-    fc.cyf = (float)cam->cy;
-    fc.rcx = (float)cam->cx;
-    fc.rcy = (float)cam->cy;
-    fc.ifx_d = 1.0 / cam->fx;
-    fc.ify_d = 1.0 / cam->fy;
-    fc.cx_d = cam->cx;
-    fc.cy_d = cam->cy;
-    fc.zmin = cam->zmin;
-    fc.zmax = cam->zmax;
-    fc.eps = params->eps_weight;
-    fc.cos_min = params->cos_max_angle;
-    fc.inv_vs_d = 1.0 / map->desc.voxel_size;
-    fc.vs_d = map->desc.voxel_size;
-    fc.vs_f = (float)map->desc.voxel_size;
-    fc.T_f = (float)map->desc.truncation;
-    fc.W = cam->width;
-    fc.H = cam->height;
+    const FuseConsts fc = fuse_consts(*map, *cam, *params);
     const MapView M = make_view(*map);
-    dim3 grid(ceil_div(cam->width, kTile), ceil_div(cam->height, kTile));
+    float4* pix = (float4*)scratch_dev;
+    {
+        TimedLaunch t(GSDF_K_NORMALS, s);
+        dim3 grid(ceil_div(cam->width, kTile), ceil_div(cam->height, kTile));
+        k_pixel_normals<<<grid, 256, 0, s>>>(depth_dev, fc, T_wc_dev, pix);
+    }
     {
         TimedLaunch t(GSDF_K_INTEGRATE, s);
         switch (map->desc.storage) {
-            case GSDF_FP32: k_integrate<GSDF_FP32><<<grid, 256, 0, s>>>(M, depth_dev, fc, T_wc_dev, status_dev); break;
-            case GSDF_BF16: k_integrate<GSDF_BF16><<<grid, 256, 0, s>>>(M, depth_dev, fc, T_wc_dev, status_dev); break;
-            default: k_integrate<GSDF_FP16><<<grid, 256, 0, s>>>(M, depth_dev, fc, T_wc_dev, status_dev); break;
+            case GSDF_FP32: k_fuse_blocks<GSDF_FP32><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev); break;
+            case GSDF_BF16: k_fuse_blocks<GSDF_BF16><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev); break;
+            default: k_fuse_blocks<GSDF_FP16><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev); break;
         }
-    }
-    if (map->desc.storage != GSDF_FP32) {
-        TimedLaunch t(GSDF_K_FINALIZE, s);
-        k_finalize<<<2048, 256, 0, s>>>(M, map->desc.storage);
-        k_finalize_done<<<1, 64, 0, s>>>(M);
     }
     return launch_status();
 }

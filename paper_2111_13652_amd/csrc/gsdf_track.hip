@@ -3,17 +3,21 @@
 // Gauss-Newton, and the damped 6x6 Cholesky solve with a left SE(3) update
 // (Sec. 5.1), all on the device.
 //
-// Each Gauss-Newton iteration is one launch.  Every thread walks a strided
-// set of pixels, accumulating the 21 upper entries of H = sum w J J^T, the
-// 6 of b = sum w J r, the energy, the count of pixels used and the count of
-// valid pixels in float32 registers; from there on every sum is float64:
-// waves reduce with cross-lane shuffles, the 4 waves of a work-group through
-// LDS, and the last work-group to finish (a device-scope ticket) adds all
-// work-group partials, solves, updates the pose in place and records the
-// statistics.  Float64 partial sums keep the rounding noise of b far below
-// what a rank-deficient H (a lone sphere) would amplify through the damping.
+// A frame is two launches: one kernel builds every pyramid level, and one
+// cooperative (all work-groups co-resident) kernel runs every Gauss-Newton
+// iteration of every level.  In an iteration each thread walks a strided
+// set of pixels and accumulates, in float32 registers, the 21 upper entries
+// of H = sum w J J^T, the 6 of b = sum w J r, the energy, the count of
+// pixels used and the count of valid pixels.  From there every sum is
+// float64: cross-lane shuffles, then LDS across the waves of a work-group,
+// then one partial per work-group.  The last work-group to arrive (a
+// device-scope ticket) adds the partials, solves, writes the new pose and
+// bumps a generation counter; the others wait for it (a bounded spin, so
+// every wave exits even if something went wrong) and start the next
+// iteration with the new pose.  Float64 partial sums keep the rounding noise
+// of b far below what a rank-deficient H (a lone sphere) would amplify
+// through the damping.
 #include <hip/hip_runtime.h>
-#include <hip/hip_fp16.h>
 
 #include "gsdf_common.hpp"
 #include "gsdf_host.hpp"
@@ -25,6 +29,7 @@ constexpr int kPartStride = 32;  // doubles per work-group partial
 constexpr int kTrackBlock = 256;
 constexpr int kMaxGroups = 2048;
 constexpr int kPixPerThread = 2;
+constexpr unsigned kSpinLimit = 1u << 24;
 
 struct TrackLevel {
     const float* depth;
@@ -33,13 +38,13 @@ struct TrackLevel {
 };
 
 struct TrackArgs {
+    TrackLevel lv[4];
+    int levels;
+    int iters[4];
     float zmin, zmax, delta;
     double inv_vs, vs;
     double damping;
     float min_inlier_frac;
-    int mode;            // 0: solve and update the pose; 1: write sums to out29
-    int stat_slot;       // iteration index for stats, -1 for none
-    int check_lost;      // 1 on the last iteration at the finest level
 };
 
 __device__ inline double wave_sum(double x) {
@@ -77,6 +82,130 @@ __device__ inline bool read_voxel(const MapView& M, int64_t vi, float* psi, floa
     return true;
 }
 
+// Accumulate the normal equations of the pixels this thread owns at `pose`.
+template <int STORAGE>
+__device__ inline void accumulate(const MapView& M, const TrackLevel& L, const TrackArgs& a,
+                                  const double* pose, int first, int stride, float acc[kNE]) {
+#pragma unroll
+    for (int k = 0; k < kNE; ++k) acc[k] = 0.0f;
+    double R[9], t[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) R[3 * i + j] = pose[4 * i + j];
+        t[i] = pose[4 * i + 3];
+    }
+    const int N = L.W * L.H;
+    for (int i = first; i < N; i += stride) {
+        const float D = L.depth[i];
+        if (!depth_ok(D, a.zmin, a.zmax)) continue;
+        acc[29] += 1.0f;
+        const int v = i / L.W;
+        const int u = i - v * L.W;
+        const double Dd = (double)D;
+        const double x0 = Dd * (((double)u - L.cx) * L.ifx);
+        const double x1 = Dd * (((double)v - L.cy) * L.ify);
+        double q[3];
+        int m[3];
+        float qr[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            q[r] = R[3 * r] * x0 + R[3 * r + 1] * x1 + R[3 * r + 2] * Dd + t[r];
+            m[r] = (int)floor(q[r] * a.inv_vs + 0.5);
+            qr[r] = (float)(q[r] - a.vs * (double)m[r]);
+        }
+        const int32_t slot = hash_find(M, block_of(m[0]), block_of(m[1]), block_of(m[2]));
+        if (slot < 0) continue;
+        const int64_t vi = (int64_t)slot * kBlockVoxels + morton9(m[0] & 7, m[1] & 7, m[2] & 7);
+        float psi, gh[3];
+        if (!read_voxel<STORAGE>(M, vi, &psi, gh)) continue;
+        const float r = psi + gh[0] * qr[0] + gh[1] * qr[1] + gh[2] * qr[2];
+        const float qf[3] = {(float)q[0], (float)q[1], (float)q[2]};
+        const float J[6] = {gh[0], gh[1], gh[2], qf[1] * gh[2] - qf[2] * gh[1],
+                            qf[2] * gh[0] - qf[0] * gh[2], qf[0] * gh[1] - qf[1] * gh[0]};
+        const float ar = fabsf(r);
+        const float w = ar <= a.delta ? 1.0f : a.delta / ar;
+        const float e = ar <= a.delta ? 0.5f * r * r : a.delta * (ar - 0.5f * a.delta);
+        int k = 0;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            const float wj = w * J[p];
+#pragma unroll
+            for (int q2 = p; q2 < 6; ++q2) acc[k++] += wj * J[q2];
+        }
+#pragma unroll
+        for (int p = 0; p < 6; ++p) acc[21 + p] += w * J[p] * r;
+        acc[27] += e;
+        acc[28] += 1.0f;
+    }
+}
+
+// Work-group sum: every thread writes its kNE float32 sums to LDS (one
+// transpose), then 8 threads per entry add 32 values each in float64 with
+// independent LDS reads, and the first kNE threads combine the 8 parts and
+// store the work-group partial with device-scope stores.  (Cross-lane
+// shuffles of doubles would chain ~180 dependent LDS permutes per wave.)
+// The barrier at the end waits for those stores; the thread that takes the
+// arrival ticket issues the work-group's single release fence.
+struct ReduceLds {
+    float v[kNE][kTrackBlock];
+    double part[kNE][8];
+};
+
+__device__ inline void store_partial(const float acc[kNE], double* partial, ReduceLds& r) {
+#pragma unroll
+    for (int k = 0; k < kNE; ++k) r.v[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < kNE * 8) {
+        const int k = threadIdx.x >> 3, p = threadIdx.x & 7;
+        const float4* src = reinterpret_cast<const float4*>(&r.v[k][p * (kTrackBlock / 8)]);
+        float4 q[kTrackBlock / 32];
+#pragma unroll
+        for (int j = 0; j < kTrackBlock / 32; ++j) q[j] = src[j];
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < kTrackBlock / 32; ++j) s += ((double)q[j].x + (double)q[j].y) + ((double)q[j].z + (double)q[j].w);
+        r.part[k][p] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < kNE) {
+        double s = 0.0;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) s += r.part[threadIdx.x][p];
+        __hip_atomic_store(&partial[threadIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+}
+
+// Sum of all work-group partials in float64 (called by the last work-group
+// after its acquire fence, so plain loads see every partial).  Thread
+// (k, p) adds entry k of the partials p, p+8, ... with eight loads in flight.
+// Result in ne[] of thread 0.
+__device__ inline void total_partials(const double* partials, int groups, double ne[kNE], ReduceLds& r) {
+    if (threadIdx.x < kNE * 8) {
+        const int k = threadIdx.x >> 3, p = threadIdx.x & 7;
+        double s = 0.0;
+        int b = p;
+        for (; b + 56 < groups; b += 64) {
+            double x[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) x[j] = partials[(size_t)(b + 8 * j) * kPartStride + k];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s += x[j];
+        }
+        for (; b < groups; b += 8) s += partials[(size_t)b * kPartStride + k];
+        r.part[k][p] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < kNE; ++k) {
+            double t = 0.0;
+            for (int p = 0; p < 8; ++p) t += r.part[k][p];
+            ne[k] = t;
+        }
+    }
+}
+
 // Cholesky solve of the damped 6x6 system and left update of the pose.
 __device__ bool solve_and_update(const double* ne, double damping, double* pose) {
     double H[36];
@@ -91,7 +220,7 @@ __device__ bool solve_and_update(const double* ne, double damping, double* pose)
     for (int i = 0; i < 6; ++i) tr += H[7 * i];
     const double mu = damping * tr / 6.0;
     for (int i = 0; i < 6; ++i) H[7 * i] += mu;
-    double L[36];
+    double L[36], inv_d[6];
     for (int i = 0; i < 36; ++i) L[i] = 0.0;
     for (int j = 0; j < 6; ++j) {
         double s = H[7 * j];
@@ -99,22 +228,23 @@ __device__ bool solve_and_update(const double* ne, double damping, double* pose)
         if (!(s > 0.0)) return false;
         const double d = sqrt(s);
         L[7 * j] = d;
+        inv_d[j] = 1.0 / d;
         for (int i = j + 1; i < 6; ++i) {
             double t = H[6 * i + j];
             for (int q = 0; q < j; ++q) t -= L[6 * i + q] * L[6 * j + q];
-            L[6 * i + j] = t / d;
+            L[6 * i + j] = t * inv_d[j];
         }
     }
     double y[6], x[6];
     for (int i = 0; i < 6; ++i) {
         double s = -ne[21 + i];
         for (int q = 0; q < i; ++q) s -= L[6 * i + q] * y[q];
-        y[i] = s / L[7 * i];
+        y[i] = s * inv_d[i];
     }
     for (int i = 5; i >= 0; --i) {
         double s = y[i];
         for (int q = i + 1; q < 6; ++q) s -= L[6 * q + i] * x[q];
-        x[i] = s / L[7 * i];
+        x[i] = s * inv_d[i];
     }
     // exp of the twist (rho, phi) = (x[0..2], x[3..5])
     const double* rho = x;
@@ -157,159 +287,280 @@ __device__ bool solve_and_update(const double* ne, double damping, double* pose)
     return true;
 }
 
-template <int STORAGE>
-__global__ __launch_bounds__(kTrackBlock) void k_track(MapView M, TrackLevel L, TrackArgs a,
-                                                        double* pose, double* partials,
-                                                        unsigned* ticket, double* out29,
-                                                        float* stats, int32_t* status) {
-    float acc[kNE];
-#pragma unroll
-    for (int k = 0; k < kNE; ++k) acc[k] = 0.0f;
+// Sync words in the scratch buffer.  Arrival is a two-level tree of tickets
+// (device-scope atomics on one address serialise, so a single ticket for
+// hundreds of work-groups would cost tens of microseconds): kLeaf
+// work-groups share a leaf ticket, the last of each leaf takes the root
+// ticket.  Two ticket sets alternate between iterations.  Then the
+// published generation and an abort flag.
+constexpr int kLeaf = 16;
+constexpr int kMaxLeaves = kMaxGroups / kLeaf;
+// one set of partials: a partial per work-group, then one per leaf
+constexpr size_t kPartsPerSet = (size_t)(kMaxGroups + kMaxLeaves) * kPartStride;
+enum {
+    kSyncLeaf = 0,                          // [2][kMaxLeaves]
+    kSyncRoot = kSyncLeaf + 2 * kMaxLeaves,  // [2]
+    kSyncGen = kSyncRoot + 2,
+    kSyncAbort = kSyncGen + 1,
+    kSyncWords = kSyncAbort + 1
+};
 
-    double R[9], t[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j) R[3 * i + j] = pose[4 * i + j];
-        t[i] = pose[4 * i + 3];
-    }
-    const int N = L.W * L.H;
-    for (int i = blockIdx.x * kTrackBlock + threadIdx.x; i < N; i += gridDim.x * kTrackBlock) {
-        const float D = L.depth[i];
-        if (!depth_ok(D, a.zmin, a.zmax)) continue;
-        acc[29] += 1.0f;
-        const int v = i / L.W;
-        const int u = i - v * L.W;
-        const double Dd = (double)D;
-        const double x0 = Dd * (((double)u - L.cx) * L.ifx);
-        const double x1 = Dd * (((double)v - L.cy) * L.ify);
-        double q[3];
-        int m[3];
-        float qr[3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            q[r] = R[3 * r] * x0 + R[3 * r + 1] * x1 + R[3 * r + 2] * Dd + t[r];
-            m[r] = (int)floor(q[r] * a.inv_vs + 0.5);
-            qr[r] = (float)(q[r] - a.vs * (double)m[r]);
-        }
-        const int32_t slot = hash_find(M, block_of(m[0]), block_of(m[1]), block_of(m[2]));
-        if (slot < 0) continue;
-        const int64_t vi = (int64_t)slot * kBlockVoxels + morton9(m[0] & 7, m[1] & 7, m[2] & 7);
-        float psi, gh[3];
-        if (!read_voxel<STORAGE>(M, vi, &psi, gh)) continue;
-        const float r = psi + gh[0] * qr[0] + gh[1] * qr[1] + gh[2] * qr[2];
-        const float qf[3] = {(float)q[0], (float)q[1], (float)q[2]};
-        const float J[6] = {gh[0], gh[1], gh[2], qf[1] * gh[2] - qf[2] * gh[1],
-                            qf[2] * gh[0] - qf[0] * gh[2], qf[0] * gh[1] - qf[1] * gh[0]};
-        const float ar = fabsf(r);
-        const float w = ar <= a.delta ? 1.0f : a.delta / ar;
-        const float e = ar <= a.delta ? 0.5f * r * r : a.delta * (ar - 0.5f * a.delta);
-        int k = 0;
-#pragma unroll
-        for (int p = 0; p < 6; ++p) {
-            const float wj = w * J[p];
-#pragma unroll
-            for (int q2 = p; q2 < 6; ++q2) acc[k++] += wj * J[q2];
-        }
-#pragma unroll
-        for (int p = 0; p < 6; ++p) acc[21 + p] += w * J[p] * r;
-        acc[27] += e;
-        acc[28] += 1.0f;
-    }
-
-    // ---- work-group reduction
-    __shared__ double red[kTrackBlock / 64][kNE];
-    __shared__ double fin[8][kNE];
-    __shared__ int is_last;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < kNE; ++k) {
-        const double s = wave_sum((double)acc[k]);
-        if (lane == 0) red[wave][k] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < kNE) {
-        double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < kTrackBlock / 64; ++w) s += red[w][threadIdx.x];
-        partials[(size_t)blockIdx.x * kPartStride + threadIdx.x] = s;
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned prev = atomicAdd(ticket, 1u);
-        is_last = (prev == gridDim.x - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-
-    // ---- last work-group: float64 total of all partials
-    if (threadIdx.x < 8 * kNE) {
-        const int k = threadIdx.x % kNE;
-        const int part = threadIdx.x / kNE;
-        double s = 0.0;
-        for (int b = part; b < (int)gridDim.x; b += 8)
-            s += __hip_atomic_load(&partials[(size_t)b * kPartStride + k], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        fin[part][k] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double ne[kNE];
-        for (int k = 0; k < kNE; ++k) {
-            double s = 0.0;
-            for (int p = 0; p < 8; ++p) s += fin[p][k];
-            ne[k] = s;
-        }
-        if (a.mode == 1) {
-            for (int k = 0; k < 29; ++k) out29[k] = ne[k];
-        } else {
-            if (a.stat_slot >= 0 && stats) {
-                stats[2 * a.stat_slot] = (float)ne[27];
-                stats[2 * a.stat_slot + 1] = (float)ne[28];
-            }
-            if (!solve_and_update(ne, a.damping, pose)) raise_status(status, GSDF_ENOTPD);
-            if (a.check_lost && ne[28] < (double)a.min_inlier_frac * ne[29])
-                raise_status(status, GSDF_ELOST);
-        }
-        *ticket = 0u;
-    }
+// Arrival, thread 0 only.  leaf_arrive: true for the last of the kLeaf
+// work-groups sharing a leaf ticket; root_arrive: true for the last leaf.
+// The release fence before each ticket publishes the partial written just
+// before; the acquire fence of the winner makes the others' partials visible.
+__device__ inline bool leaf_arrive(unsigned* sync, int par, int groups) {
+    const int leaf = blockIdx.x / kLeaf;
+    const int leaf_size = min(kLeaf, groups - leaf * kLeaf);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    unsigned* lc = &sync[kSyncLeaf + par * kMaxLeaves + leaf];
+    if (__hip_atomic_fetch_add(lc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != (unsigned)leaf_size - 1)
+        return false;
+    __hip_atomic_store(lc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
 }
 
-// 2x2 pyramid level in binary32: the mean of four valid depths whose spread
-// is within the truncation, else 0.  Work-item (0,0) also clears the ticket.
-__global__ void k_pyramid(const float* __restrict__ src, int Ws, float* __restrict__ dst, int Wd,
-                          int Hd, float zmin, float zmax, float Tf, unsigned* ticket) {
-    const int u = blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = blockIdx.y * blockDim.y + threadIdx.y;
-    if (ticket && u == 0 && v == 0) *ticket = 0u;
-    if (u >= Wd || v >= Hd) return;
-    const float a = src[(size_t)(2 * v) * Ws + 2 * u];
-    const float b = src[(size_t)(2 * v) * Ws + 2 * u + 1];
-    const float c = src[(size_t)(2 * v + 1) * Ws + 2 * u];
-    const float e = src[(size_t)(2 * v + 1) * Ws + 2 * u + 1];
-    bool ok = depth_ok(a, zmin, zmax) && depth_ok(b, zmin, zmax) && depth_ok(c, zmin, zmax) &&
-              depth_ok(e, zmin, zmax);
+__device__ inline bool root_arrive(unsigned* sync, int par, int groups) {
+    const int nleaf = (groups + kLeaf - 1) / kLeaf;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    unsigned* rc = &sync[kSyncRoot + par];
+    if (__hip_atomic_fetch_add(rc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != (unsigned)nleaf - 1)
+        return false;
+    __hip_atomic_store(rc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
+}
+
+// Two-level sum of the work-group partials: the last work-group of each
+// leaf adds the leaf's partials and stores a leaf partial; the last leaf adds
+// those.  Returns true (in every thread) for the work-group that holds the
+// total, in ne[] of thread 0.  `part` has one partial per work-group,
+// `leafpart` one per leaf.
+__device__ inline bool reduce_tree(const float acc[kNE], double* part, double* leafpart, unsigned* sync,
+                                   int par, int groups, double ne[kNE], ReduceLds& r, int* s_flag) {
+    store_partial(acc, part + (size_t)blockIdx.x * kPartStride, r);
+    if (threadIdx.x == 0) *s_flag = leaf_arrive(sync, par, groups) ? 1 : 0;
+    __syncthreads();
+    if (!*s_flag) return false;
+    const int leaf = blockIdx.x / kLeaf;
+    const int leaf_size = min(kLeaf, groups - leaf * kLeaf);
+    double lsum[kNE];
+    total_partials(part + (size_t)leaf * kLeaf * kPartStride, leaf_size, lsum, r);
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < kNE; ++k)
+            __hip_atomic_store(&leafpart[(size_t)leaf * kPartStride + k], lsum[k], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        *s_flag = root_arrive(sync, par, groups) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!*s_flag) return false;
+    total_partials(leafpart, (groups + kLeaf - 1) / kLeaf, ne, r);
+    return true;
+}
+
+// Wait (thread 0 only) until the published generation reaches `target`;
+// relaxed polling with a short sleep, then one acquire fence.  Returns false
+// on timeout or when another work-group aborted.
+__device__ inline bool wait_generation(unsigned* sync, unsigned target) {
+    unsigned spins = 0;
+    while (__hip_atomic_load(&sync[kSyncGen], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (++spins > kSpinLimit ||
+            __hip_atomic_load(&sync[kSyncAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            return false;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
+}
+
+// Work-groups that take part at a level: enough to give each thread about
+// kPixPerThread pixels, so coarse levels synchronise few groups.
+__device__ inline int level_groups(const TrackLevel& L, int G) {
+    int g = (L.W * L.H + kTrackBlock * kPixPerThread - 1) / (kTrackBlock * kPixPerThread);
+    return g < 1 ? 1 : (g > G ? G : g);
+}
+
+// The whole coarse-to-fine Gauss-Newton of one frame (cooperative launch).
+template <int STORAGE>
+__global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArgs a, double* pose,
+                                                              double* partials, unsigned* sync,
+                                                              float* stats, int32_t* status) {
+    __shared__ double s_pose[12];
+    __shared__ int s_last, s_ok;
+    __shared__ ReduceLds red;
+    const int G = gridDim.x;
+    int gi = 0;  // global iteration index
+    for (int l = a.levels - 1; l >= 0; --l) {
+        const TrackLevel L = a.lv[l];
+        const int Gl = level_groups(L, G);
+        if ((int)blockIdx.x >= Gl) {
+            // no pixels at this level: skip to the end of its iterations
+            gi += a.iters[l];
+            continue;
+        }
+        for (int it = 0; it < a.iters[l]; ++it, ++gi) {
+            // ---- wait for the pose of iteration gi
+            if (threadIdx.x == 0) {
+                const bool ok = gi == 0 || wait_generation(sync, (unsigned)gi);
+                if (ok) {
+                    // after the acquire fence plain loads see the published
+                    // pose; six 16-byte loads are issued back to back
+                    const double2* pp = reinterpret_cast<const double2*>(pose);
+                    double2 v[6];
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) v[k] = pp[k];
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) {
+                        s_pose[2 * k] = v[k].x;
+                        s_pose[2 * k + 1] = v[k].y;
+                    }
+                }
+                s_ok = ok ? 1 : 0;
+            }
+            __syncthreads();
+            if (!s_ok) {
+                if (threadIdx.x == 0) {
+                    __hip_atomic_store(&sync[kSyncAbort], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    raise_status(status, GSDF_EHIP);
+                }
+                return;
+            }
+            double P[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) P[k] = s_pose[k];
+            float acc[kNE];
+            accumulate<STORAGE>(M, L, a, P, blockIdx.x * kTrackBlock + threadIdx.x, Gl * kTrackBlock, acc);
+
+            double* part = partials + (size_t)(gi & 1) * kPartsPerSet;
+            double* leafpart = part + (size_t)kMaxGroups * kPartStride;
+            double ne[kNE];
+            if (!reduce_tree(acc, part, leafpart, sync, gi & 1, Gl, ne, red, &s_last)) continue;
+
+            // ---- the work-group holding the total: solve, publish
+            if (threadIdx.x == 0) {
+                if (stats) {
+                    stats[2 * gi] = (float)ne[27];
+                    stats[2 * gi + 1] = (float)ne[28];
+                }
+                add_stat(M, kStatTrackValid, (unsigned long long)ne[29]);
+                add_stat(M, kStatTrackUsed, (unsigned long long)ne[28]);
+                double Pn[12];
+                for (int k = 0; k < 12; ++k) Pn[k] = s_pose[k];
+                if (solve_and_update(ne, a.damping, Pn)) {
+                    for (int k = 0; k < 12; ++k)
+                        __hip_atomic_store(&pose[k], Pn[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    raise_status(status, GSDF_ENOTPD);
+                }
+                if (l == 0 && it == a.iters[0] - 1 && ne[28] < (double)a.min_inlier_frac * ne[29])
+                    raise_status(status, GSDF_ELOST);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_store(&sync[kSyncGen], (unsigned)(gi + 1), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __syncthreads();
+        }
+    }
+    // Every work-group leaves only after the last pose is published, so the
+    // pose read by the next kernel on the stream is final.
+    if (threadIdx.x == 0 && gi > 0 && !wait_generation(sync, (unsigned)gi)) raise_status(status, GSDF_EHIP);
+}
+
+// One linearisation (gsdf_normal_equations): a single launch whose last
+// work-group writes the float64 totals.
+template <int STORAGE>
+__global__ __launch_bounds__(kTrackBlock) void k_normal_equations(MapView M, TrackArgs a,
+                                                                   const double* pose, double* partials,
+                                                                   unsigned* sync, double* out29) {
+    __shared__ int s_last;
+    __shared__ ReduceLds red;
+    double P[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) P[k] = pose[k];
+    float acc[kNE];
+    accumulate<STORAGE>(M, a.lv[0], a, P, blockIdx.x * kTrackBlock + threadIdx.x,
+                        gridDim.x * kTrackBlock, acc);
+    double ne[kNE];
+    if (!reduce_tree(acc, partials, partials + (size_t)kMaxGroups * kPartStride, sync, 0, gridDim.x, ne, red,
+                     &s_last))
+        return;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 29; ++k) out29[k] = ne[k];
+}
+
+// All pyramid levels in one launch, each by the 2x2 rule in binary32: the
+// mean of four valid depths whose spread is within the truncation, else 0.
+// A work-group covers a 16x16 tile of level 1 (from level 0 in global
+// memory); its 8x8 level-2 and 4x4 level-3 pixels come from LDS.  Work-item
+// (0,0) of the grid also clears the sync words of the tracking kernel.
+struct PyramidArgs {
+    const float* src;
+    float* dst[4];
+    int W[4], H[4];
+    int levels;
+    float zmin, zmax, Tf;
+    unsigned* sync;
+};
+
+__device__ inline float pyr_combine(float a, float b, float c, float e, const PyramidArgs& p) {
+    bool ok = depth_ok(a, p.zmin, p.zmax) && depth_ok(b, p.zmin, p.zmax) && depth_ok(c, p.zmin, p.zmax) &&
+              depth_ok(e, p.zmin, p.zmax);
     const float mx = fmaxf(fmaxf(a, b), fmaxf(c, e));
     const float mn = fminf(fminf(a, b), fminf(c, e));
-    ok = ok && (sub_rn(mx, mn) <= Tf);
-    dst[(size_t)v * Wd + u] = ok ? mul_rn(add_rn(add_rn(a, b), add_rn(c, e)), 0.25f) : 0.0f;
+    ok = ok && (sub_rn(mx, mn) <= p.Tf);
+    return ok ? mul_rn(add_rn(add_rn(a, b), add_rn(c, e)), 0.25f) : 0.0f;
 }
 
-__global__ void k_zero_ticket(unsigned* ticket) {
-    if (threadIdx.x == 0) *ticket = 0u;
+__global__ __launch_bounds__(256) void k_pyramid(PyramidArgs p) {
+    __shared__ float t1[16][17];
+    __shared__ float t2[8][9];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    if (blockIdx.x == 0 && blockIdx.y == 0)
+        for (int k = threadIdx.x; k < kSyncWords; k += blockDim.x) p.sync[k] = 0u;
+    if (p.levels < 2) return;
+    const int u = blockIdx.x * 16 + tx, v = blockIdx.y * 16 + ty;
+    float d1 = 0.0f;
+    if (u < p.W[1] && v < p.H[1]) {
+        const float* r0 = p.src + (size_t)(2 * v) * p.W[0] + 2 * u;
+        const float* r1 = r0 + p.W[0];
+        d1 = pyr_combine(r0[0], r0[1], r1[0], r1[1], p);
+        p.dst[1][(size_t)v * p.W[1] + u] = d1;
+    }
+    t1[ty][tx] = d1;
+    if (p.levels < 3) return;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int a = threadIdx.x & 7, b = threadIdx.x >> 3;
+        const int u2 = blockIdx.x * 8 + a, v2 = blockIdx.y * 8 + b;
+        float d2 = 0.0f;
+        if (u2 < p.W[2] && v2 < p.H[2]) {
+            d2 = pyr_combine(t1[2 * b][2 * a], t1[2 * b][2 * a + 1], t1[2 * b + 1][2 * a],
+                             t1[2 * b + 1][2 * a + 1], p);
+            p.dst[2][(size_t)v2 * p.W[2] + u2] = d2;
+        }
+        t2[b][a] = d2;
+    }
+    if (p.levels < 4) return;
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        const int a = threadIdx.x & 3, b = threadIdx.x >> 2;
+        const int u3 = blockIdx.x * 4 + a, v3 = blockIdx.y * 4 + b;
+        if (u3 < p.W[3] && v3 < p.H[3])
+            p.dst[3][(size_t)v3 * p.W[3] + u3] =
+                pyr_combine(t2[2 * b][2 * a], t2[2 * b][2 * a + 1], t2[2 * b + 1][2 * a], t2[2 * b + 1][2 * a + 1], p);
+    }
 }
 
 struct ScratchLayout {
-    size_t ticket, partials, level[4], total;
+    size_t sync, partials, level[4], total;
 };
 
 inline ScratchLayout scratch_layout(const gsdf_camera& c, int levels) {
     ScratchLayout s;
     size_t o = 0;
-    s.ticket = o;   o = align256(o + 256);
-    s.partials = o; o = align256(o + (size_t)kMaxGroups * kPartStride * 8);
+    s.sync = o;     o = align256(o + kSyncWords * 4);
+    s.partials = o; o = align256(o + 2 * kPartsPerSet * 8);
     int W = c.width, H = c.height;
     s.level[0] = 0;
     for (int l = 1; l < 4; ++l) {
@@ -322,26 +573,66 @@ inline ScratchLayout scratch_layout(const gsdf_camera& c, int levels) {
     return s;
 }
 
-inline int track_groups(int npx) {
+inline int normal_eq_groups(int npx) {
     int g = ceil_div(npx, kTrackBlock * kPixPerThread);
     return g < 1 ? 1 : (g > kMaxGroups ? kMaxGroups : g);
 }
 
+// Co-resident work-group count for the cooperative kernel (cached per device).
 template <int STORAGE>
-void launch_track(int g, hipStream_t s, const MapView& M, const TrackLevel& L, const TrackArgs& a,
-                  double* pose, double* partials, unsigned* ticket, double* out29, float* stats,
-                  int32_t* status) {
-    k_track<STORAGE><<<g, kTrackBlock, 0, s>>>(M, L, a, pose, partials, ticket, out29, stats, status);
+int coop_groups() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (cached[dev] > 0) return cached[dev];
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_track_frame<STORAGE>, kTrackBlock, 0) !=
+        hipSuccess)
+        return 0;
+    int g = cus * (per_cu < 2 ? per_cu : 2);
+    if (g > kMaxGroups) g = kMaxGroups;
+    cached[dev] = g;
+    return g;
 }
 
-void launch_track_any(int storage, int g, hipStream_t s, const MapView& M, const TrackLevel& L,
-                      const TrackArgs& a, double* pose, double* partials, unsigned* ticket,
-                      double* out29, float* stats, int32_t* status) {
+template <int STORAGE>
+int launch_track_frame(hipStream_t s, const MapView& M, const TrackArgs& a, double* pose,
+                       double* partials, unsigned* sync, float* stats, int32_t* status) {
+    const int g = coop_groups<STORAGE>();
+    if (g <= 0) return GSDF_EHIP;
+    MapView Mv = M;
+    TrackArgs av = a;
+    void* args[] = {&Mv, &av, &pose, &partials, &sync, &stats, &status};
     TimedLaunch tl(GSDF_K_TRACK, s);
-    switch (storage) {
-        case GSDF_FP32: launch_track<GSDF_FP32>(g, s, M, L, a, pose, partials, ticket, out29, stats, status); break;
-        case GSDF_BF16: launch_track<GSDF_BF16>(g, s, M, L, a, pose, partials, ticket, out29, stats, status); break;
-        default: launch_track<GSDF_FP16>(g, s, M, L, a, pose, partials, ticket, out29, stats, status); break;
+    if (hipLaunchCooperativeKernel((const void*)k_track_frame<STORAGE>, dim3(g), dim3(kTrackBlock), args, 0,
+                                   s) != hipSuccess)
+        return GSDF_EHIP;
+    return GSDF_OK;
+}
+
+inline void fill_levels(const gsdf_camera& cam, const float* depth, const ScratchLayout& sl, char* base,
+                        int levels, TrackArgs* a) {
+    double fx = cam.fx, fy = cam.fy, cx = cam.cx, cy = cam.cy;
+    a->lv[0].depth = depth;
+    a->lv[0].W = cam.width;
+    a->lv[0].H = cam.height;
+    a->lv[0].ifx = 1.0 / fx;
+    a->lv[0].ify = 1.0 / fy;
+    a->lv[0].cx = cx;
+    a->lv[0].cy = cy;
+    for (int l = 1; l < 4; ++l) {
+        fx /= 2;
+        fy /= 2;
+        cx = (cx + 0.5) / 2 - 0.5;
+        cy = (cy + 0.5) / 2 - 0.5;
+        a->lv[l].depth = l < levels ? (const float*)(base + sl.level[l]) : nullptr;
+        a->lv[l].W = a->lv[l - 1].W / 2;
+        a->lv[l].H = a->lv[l - 1].H / 2;
+        a->lv[l].ifx = 1.0 / fx;
+        a->lv[l].ify = 1.0 / fy;
+        a->lv[l].cx = cx;
+        a->lv[l].cy = cy;
     }
 }
 
@@ -369,43 +660,13 @@ extern "C" int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, con
     if (scratch_bytes < sl.total) return GSDF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     char* base = (char*)scratch_dev;
-    unsigned* ticket = (unsigned*)(base + sl.ticket);
+    unsigned* sync = (unsigned*)(base + sl.sync);
     double* partials = (double*)(base + sl.partials);
 
-    TrackLevel lv[4];
-    lv[0].depth = depth_dev;
-    lv[0].W = cam->width;
-    lv[0].H = cam->height;
-    double fx = cam->fx, fy = cam->fy, cx = cam->cx, cy = cam->cy;
-    lv[0].ifx = 1.0 / fx;
-    lv[0].ify = 1.0 / fy;
-    lv[0].cx = cx;
-    lv[0].cy = cy;
-    for (int l = 1; l < levels; ++l) {
-        fx /= 2;
-        fy /= 2;
-        cx = (cx + 0.5) / 2 - 0.5;
-        cy = (cy + 0.5) / 2 - 0.5;
-        lv[l].depth = (const float*)(base + sl.level[l]);
-        lv[l].W = lv[l - 1].W / 2;
-        lv[l].H = lv[l - 1].H / 2;
-        lv[l].ifx = 1.0 / fx;
-        lv[l].ify = 1.0 / fy;
-        lv[l].cx = cx;
-        lv[l].cy = cy;
-    }
-    {
-        TimedLaunch tp(GSDF_K_PYRAMID, s);
-        if (levels == 1) k_zero_ticket<<<1, 64, 0, s>>>(ticket);
-        for (int l = 1; l < levels; ++l) {
-            dim3 blk(16, 16), grd(ceil_div(lv[l].W, 16), ceil_div(lv[l].H, 16));
-            k_pyramid<<<grd, blk, 0, s>>>(lv[l - 1].depth, lv[l - 1].W, (float*)lv[l].depth, lv[l].W,
-                                          lv[l].H, cam->zmin, cam->zmax, (float)map->desc.truncation,
-                                          l == 1 ? ticket : nullptr);
-        }
-    }
-    const MapView M = make_view(*map);
     TrackArgs a;
+    fill_levels(*cam, depth_dev, sl, base, levels, &a);
+    a.levels = levels;
+    for (int l = 0; l < 4; ++l) a.iters[l] = l < levels ? params->iters[l] : 0;
     a.zmin = cam->zmin;
     a.zmax = cam->zmax;
     a.delta = params->huber_delta;
@@ -413,17 +674,32 @@ extern "C" int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, con
     a.vs = map->desc.voxel_size;
     a.damping = params->damping;
     a.min_inlier_frac = params->min_inlier_frac;
-    a.mode = 0;
-    int slot = 0;
-    for (int l = levels - 1; l >= 0; --l) {
-        const int g = track_groups(lv[l].W * lv[l].H);
-        for (int it = 0; it < params->iters[l]; ++it) {
-            a.stat_slot = slot++;
-            a.check_lost = (l == 0 && it == params->iters[0] - 1) ? 1 : 0;
-            launch_track_any(map->desc.storage, g, s, M, lv[l], a, T_wc_inout_dev, partials, ticket,
-                             nullptr, stats_dev, status_dev);
+
+    {
+        PyramidArgs p;
+        p.src = depth_dev;
+        for (int l = 0; l < 4; ++l) {
+            p.dst[l] = (float*)a.lv[l].depth;
+            p.W[l] = a.lv[l].W;
+            p.H[l] = a.lv[l].H;
         }
+        p.levels = levels;
+        p.zmin = cam->zmin;
+        p.zmax = cam->zmax;
+        p.Tf = (float)map->desc.truncation;
+        p.sync = sync;
+        TimedLaunch tp(GSDF_K_PYRAMID, s);
+        dim3 grd(levels > 1 ? ceil_div(a.lv[1].W, 16) : 1, levels > 1 ? ceil_div(a.lv[1].H, 16) : 1);
+        k_pyramid<<<grd, 256, 0, s>>>(p);
     }
+    const MapView M = make_view(*map);
+    int rc;
+    switch (map->desc.storage) {
+        case GSDF_FP32: rc = launch_track_frame<GSDF_FP32>(s, M, a, T_wc_inout_dev, partials, sync, stats_dev, status_dev); break;
+        case GSDF_BF16: rc = launch_track_frame<GSDF_BF16>(s, M, a, T_wc_inout_dev, partials, sync, stats_dev, status_dev); break;
+        default: rc = launch_track_frame<GSDF_FP16>(s, M, a, T_wc_inout_dev, partials, sync, stats_dev, status_dev); break;
+    }
+    if (rc != GSDF_OK) return rc;
     return launch_status();
 }
 
@@ -437,17 +713,11 @@ extern "C" int gsdf_normal_equations(const gsdf_map* map, const float* depth_dev
     if (scratch_bytes < sl.total) return GSDF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     char* base = (char*)scratch_dev;
-    unsigned* ticket = (unsigned*)(base + sl.ticket);
+    unsigned* sync = (unsigned*)(base + sl.sync);
     double* partials = (double*)(base + sl.partials);
-    TrackLevel L;
-    L.depth = depth_dev;
-    L.W = cam->width;
-    L.H = cam->height;
-    L.ifx = 1.0 / cam->fx;
-    L.ify = 1.0 / cam->fy;
-    L.cx = cam->cx;
-    L.cy = cam->cy;
     TrackArgs a;
+    fill_levels(*cam, depth_dev, sl, base, 1, &a);
+    a.levels = 1;
     a.zmin = cam->zmin;
     a.zmax = cam->zmax;
     a.delta = huber_delta;
@@ -455,11 +725,16 @@ extern "C" int gsdf_normal_equations(const gsdf_map* map, const float* depth_dev
     a.vs = map->desc.voxel_size;
     a.damping = 0.0;
     a.min_inlier_frac = 0.0f;
-    a.mode = 1;
-    a.stat_slot = -1;
-    a.check_lost = 0;
-    k_zero_ticket<<<1, 64, 0, s>>>(ticket);
-    launch_track_any(map->desc.storage, track_groups(L.W * L.H), s, make_view(*map), L, a,
-                     const_cast<double*>(T_wc_dev), partials, ticket, out29_dev, nullptr, nullptr);
+    PyramidArgs p = {};
+    p.levels = 1;
+    p.sync = sync;
+    k_pyramid<<<1, 256, 0, s>>>(p);
+    const int g = normal_eq_groups(cam->width * cam->height);
+    const MapView M = make_view(*map);
+    switch (map->desc.storage) {
+        case GSDF_FP32: k_normal_equations<GSDF_FP32><<<g, kTrackBlock, 0, s>>>(M, a, T_wc_dev, partials, sync, out29_dev); break;
+        case GSDF_BF16: k_normal_equations<GSDF_BF16><<<g, kTrackBlock, 0, s>>>(M, a, T_wc_dev, partials, sync, out29_dev); break;
+        default: k_normal_equations<GSDF_FP16><<<g, kTrackBlock, 0, s>>>(M, a, T_wc_dev, partials, sync, out29_dev); break;
+    }
     return launch_status();
 }

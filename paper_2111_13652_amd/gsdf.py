@@ -97,6 +97,21 @@ class GsdfMap:
             self._scratch[key] = torch.empty(int(n), dtype=torch.uint8, device=self.device)
         return self._scratch[key]
 
+    def _fuse_scratch_for(self, cam: _lib.Camera) -> torch.Tensor:
+        key = ("fuse", cam.width, cam.height)
+        if key not in self._scratch:
+            n = _lib.load().gsdf_integrate_scratch_bytes(C.byref(cam))
+            if n == 0:
+                raise ValueError("invalid camera for fusion")
+            self._scratch[key] = torch.empty(int(n), dtype=torch.uint8, device=self.device)
+        return self._scratch[key]
+
+    def counters(self) -> np.ndarray:
+        """Work counters since the last reset (see gsdf_map_counters)."""
+        out = torch.zeros(16, dtype=torch.int64, device=self.device)
+        _lib.check(_lib.load().gsdf_map_counters(C.byref(self._map), _ptr(out), _stream()), "counters")
+        return out.cpu().numpy().astype(np.uint64)
+
     # ---- the hot path ----
     def allocate(self, depth: torch.Tensor, cam, pose: torch.Tensor) -> None:
         c = camera(cam)
@@ -112,9 +127,11 @@ class GsdfMap:
         _need(depth, torch.float32, (c.height, c.width), "depth")
         _need(pose, torch.float64, (3, 4), "pose")
         p = _lib.FuseParams(float(self.voxel_size if eps is None else eps), float(cos_max_angle))
+        scratch = self._fuse_scratch_for(c)
         _lib.check(_lib.load().gsdf_integrate_frame(C.byref(self._map), _ptr(depth), C.byref(c),
-                                                     _ptr(pose), C.byref(p), _ptr(self.status),
-                                                     _stream()), "integrate_frame")
+                                                     _ptr(pose), C.byref(p), _ptr(scratch),
+                                                     scratch.numel(), _ptr(self.status), _stream()),
+                   "integrate_frame")
 
     def fuse(self, depth: torch.Tensor, cam, pose: torch.Tensor, **kw) -> None:
         self.allocate(depth, cam, pose)
