@@ -30,10 +30,11 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 
-# Algorithmic bytes per unit of work (FP32 storage; see the design notes):
+# Algorithmic bytes per unit of work.  Voxel record: float4 + float W = 20 B
+# (fp32 storage) or 4 x 16-bit + float W = 12 B (bf16 / fp16 storage).
+RECORD_BYTES = {"fp32": 20.0, "bf16": 12.0, "fp16": 12.0}
 B_TRACK_PIXEL = 4.0        # depth read, every pixel of a level, every iteration
-B_TRACK_VALID = 36.0       # hash entry 16 + voxel float4 16 + weight 4, per valid pixel
-B_FUSE_UPDATE = 40.0       # read + write of the 20-byte voxel record per (pixel, voxel) update
+B_HASH_ENTRY = 16.0        # hash entry probed per valid tracked pixel
 B_FUSE_PIXEL = 4.0 + 16.0  # depth read + float4 normal write, per pixel (normals kernel)
 B_ALLOC_PIXEL = 4.0        # depth read per pixel
 B_ALLOC_PAIR = 16.0        # hash entry per distinct (tile, block) probe
@@ -49,6 +50,8 @@ def _parse():
                     help="frames of the stream the oracle runs for the CPU baseline")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--no-h2d", action="store_true", help="skip the PCIe-inclusive pass")
+    ap.add_argument("--storage", choices=("fp32", "bf16", "fp16"), default="fp32",
+                    help="voxel storage: fp32 (plain path) or the 16-bit precision form")
     return ap.parse_args()
 
 
@@ -75,7 +78,7 @@ def main():
     gt = torch.as_tensor(stream.poses).to(dev)                          # (F, 3, 4) float64
     est = torch.zeros_like(gt)
     levels, iters, delta = 3, (4, 5, 10), 0.01
-    m = GsdfMap(cfg["voxel_size"], cfg["truncation"], max_blocks=1 << 16, storage="fp32")
+    m = GsdfMap(cfg["voxel_size"], cfg["truncation"], max_blocks=1 << 16, storage=args.storage)
     s = torch.cuda.current_stream()
 
     def step(f, src=None):
@@ -131,8 +134,9 @@ def main():
     K = args.steps
     npx = cam.width * cam.height
     lvl_px = sum((cam.width >> l) * (cam.height >> l) * iters[l] for l in range(levels))
-    track_bytes = B_TRACK_PIXEL * lvl_px * K + B_TRACK_VALID * work[5]
-    fuse_bytes = B_FUSE_UPDATE * work[0]
+    rec = RECORD_BYTES[args.storage]
+    track_bytes = B_TRACK_PIXEL * lvl_px * K + (B_HASH_ENTRY + rec) * work[5]
+    fuse_bytes = 2.0 * rec * work[0]
     normals_bytes = B_FUSE_PIXEL * npx * K
     alloc_bytes = B_ALLOC_PIXEL * npx * K + B_ALLOC_PAIR * work[4]
     per_kernel_bytes = {"track": track_bytes, "fuse_blocks": fuse_bytes, "normals": normals_bytes,
@@ -195,10 +199,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.storage == "fp32" else f"{args.storage} storage, f32 compute",
         "data": "synthetic (seeded room stream standing in for TUM RGB-D 640x480 depth)",
         "config": {"workload": "room stream 640x480, 1 cm voxels, T 5 cm, 8^3 blocks, 3-level "
-                               "pyramid (4/5/10 GN iterations), fp32 voxels",
+                               f"pyramid (4/5/10 GN iterations), {args.storage} voxels",
                    "frames": n_frames},
         "hbm_frac": eff_gbs / HBM_PEAK_GBS,
         "effective_gbs": eff_gbs,

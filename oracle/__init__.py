@@ -81,6 +81,8 @@ def _load():
         "orc_taylor": (_I, [_P, _P, _P, _P, _P]),
         "orc_loss_grad": (_D, [_P, _I, _P, _P, _P, _P, _D, _P, _I, _P, _I64, _P, _P, _P]),
         "orc_render_taylor": (None, [_P, _P, _P, _D, _D, _P]),
+        "orc_integrate_rounded": (_I64, [_P, _P, _P, _P, _D, _D, _I]),
+        "orc_round_storage": (_D, [_D, _I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -176,6 +178,18 @@ class OracleMap:
                                       eps, float(cos_min), float(margin), _ptr(marg)))
         return (n, marg) if return_marginal else n
 
+    def integrate_rounded(self, depth: np.ndarray, cam, T: np.ndarray, storage: str,
+                          eps: Optional[float] = None,
+                          cos_min: float = float(np.cos(np.deg2rad(75.0)))) -> int:
+        """Fusion with 16-bit storage emulated (psi/T and gbar rounded to
+        bf16 / fp16 once per frame, W to binary32).  The map's g then holds
+        the mean gradient gbar."""
+        d = _c(depth, np.float32)
+        c = cam_struct(cam)
+        eps = self.voxel_size if eps is None else float(eps)
+        return int(_load().orc_integrate_rounded(self._h, _ptr(d), C.byref(c), _ptr(_c(T, np.float64)),
+                                                 eps, float(cos_min), STORAGE_CODES[storage]))
+
     def band_voxels(self, cam, T, u: int, v: int, D: float) -> np.ndarray:
         out = np.zeros((256, 3), np.int32)
         c = cam_struct(cam)
@@ -238,6 +252,14 @@ class OracleMap:
         _load().orc_render_taylor(self._h, C.byref(c), _ptr(_c(T, np.float64)), float(smin),
                                   float(smax), _ptr(out))
         return out
+
+
+STORAGE_CODES = {"fp64": 0, "bf16": 1, "fp16": 2}
+
+
+def round_storage(x: float, storage: str) -> float:
+    """Round to bfloat16 / binary16 (ties to even), as the emulated store."""
+    return float(_load().orc_round_storage(float(x), STORAGE_CODES[storage]))
 
 
 # ---- free functions ----

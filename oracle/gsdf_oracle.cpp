@@ -664,6 +664,92 @@ int64_t orc_integrate(OrcMap* M, const float* depth, const OrcCam* cam, const do
     return updates;
 }
 
+}  // extern "C"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Reduced-precision storage, emulated: psi/T and the mean gradient
+// gbar = g / W are kept rounded to bfloat16 or IEEE binary16 and W to
+// binary32, updated once per frame from float64 per-frame sums:
+//   psi <- (W psi + S_wd) / (W + S_w),  gbar <- (W gbar + S_wn) / (W + S_w),
+//   W <- W + S_w      (Eq. (1)-(3) applied to the frame's observations).
+// For such maps the voxel's g field holds gbar.
+// ---------------------------------------------------------------------------
+double round_to_bits(double x, int bits) {
+    // round to `bits` significant bits, ties to even (default rounding mode)
+    if (x == 0.0 || !std::isfinite(x)) return x;
+    int e;
+    const double m = std::frexp(x, &e);  // x = m 2^e, 0.5 <= |m| < 1
+    return std::ldexp(std::nearbyint(std::ldexp(m, bits)), e - bits);
+}
+
+double round_storage(double x, int storage) {
+    if (storage == 1) return round_to_bits(x, 8);            // bfloat16: 8 significant bits
+    if (storage == 2) {                                        // binary16
+        if (std::fabs(x) < std::ldexp(1.0, -14))               // subnormal: quantum 2^-24
+            return std::ldexp(std::nearbyint(std::ldexp(x, 24)), -24);
+        return round_to_bits(x, 11);
+    }
+    return x;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t orc_integrate_rounded(OrcMap* M, const float* depth, const OrcCam* cam, const double* T,
+                              double eps, double cos_min, int storage) {
+    Decision d = make_decision(M, *cam, T);
+    float Tf = (float)M->T;
+    struct Sum {
+        double w = 0, wd = 0, wn[3] = {0, 0, 0};
+    };
+    std::unordered_map<int64_t, std::unordered_map<int, Sum>> frame;  // block -> voxel -> sums
+    int64_t updates = 0;
+    for (int v = 0; v < cam->height; ++v)
+        for (int u = 0; u < cam->width; ++u) {
+            float Df = depth[(size_t)v * cam->width + u];
+            if (!depth_valid(Df, *cam)) continue;
+            Normal nr = fals_normal(depth, *cam, Tf, u, v);
+            if (!nr.valid || !(nr.cosang >= cos_min)) continue;
+            double D = Df;
+            double x[3] = {D * ((double)u - cam->cx) / cam->fx, D * ((double)v - cam->cy) / cam->fy, D};
+            double p[3], nw[3];
+            transform(T, x, p);
+            for (int i = 0; i < 3; ++i) nw[i] = T[4 * i] * nr.n[0] + T[4 * i + 1] * nr.n[1] + T[4 * i + 2] * nr.n[2];
+            for (const I3& m : band_voxels(d, u, v, Df)) {
+                int bx = floordiv8(m.x), by = floordiv8(m.y), bz = floordiv8(m.z);
+                if (!find_block(M, bx, by, bz)) continue;
+                double vj[3] = {M->vs * m.x, M->vs * m.y, M->vs * m.z};
+                double dist = nw[0] * (vj[0] - p[0]) + nw[1] * (vj[1] - p[1]) + nw[2] * (vj[2] - p[2]);
+                dist = std::min(M->T, std::max(-M->T, dist));
+                double w = w_linear(dist, eps, M->T);
+                if (!(w > 0.0)) continue;
+                Sum& S = frame[pack_key(bx, by, bz)][local_index(m.x - 8 * bx, m.y - 8 * by, m.z - 8 * bz)];
+                S.w += w;
+                S.wd += w * dist;
+                for (int k = 0; k < 3; ++k) S.wn[k] += w * nw[k];
+                ++updates;
+            }
+        }
+    for (auto& bkv : frame) {
+        Block* B = M->blocks[bkv.first].get();
+        for (auto& vkv : bkv.second) {
+            Voxel& V = B->v[vkv.first];
+            const Sum& S = vkv.second;
+            const double Wn = V.W + S.w;
+            const double psi = (V.W * V.psi + S.wd) / Wn;
+            V.psi = M->T * round_storage(psi / M->T, storage);
+            for (int k = 0; k < 3; ++k) V.g[k] = round_storage((V.W * V.g[k] + S.wn[k]) / Wn, storage);
+            V.W = (double)(float)Wn;
+        }
+    }
+    return updates;
+}
+
+double orc_round_storage(double x, int storage) { return round_storage(x, storage); }
+
 // Depth pyramid level (binary32): mean of each 2x2 block when all four are
 // valid and their spread is within the truncation, else 0.
 void orc_pyramid_down(const float* src, const OrcCam* cam, double truncation, float* dst) {

@@ -210,6 +210,16 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
     }
     const float Rf[9] = {(float)R[0], (float)R[1], (float)R[2], (float)R[3], (float)R[4],
                          (float)R[5], (float)R[6], (float)R[7], (float)R[8]};
+    // camera-relative float32 pose for 16-bit storage: voxel nearest the
+    // camera centre and the remainder of the translation
+    int mc[3];
+    float trf[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        mc[i] = (int)floor(t[i] * fc.inv_vs_d + 0.5);
+        trf[i] = (float)(t[i] - fc.vs_d * (double)mc[i]);
+    }
+    const float ivsf = (float)fc.inv_vs_d;
     const BandRule br = make_band_rule(Twc, fc.band.ifx, fc.band.ify, fc.band.cxf, fc.band.cyf,
                                        fc.band.invvs, fc.band.Tf, fc.band.Df, fc.band.nsamples);
     int n_blocks = M.counters[kNumBlocks];
@@ -292,17 +302,31 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
             const int k1 = (int)fminf(last, floorf(fmaxf((zout - zb0) * inv_df, -1.0f)));
             if (k0 > k1) continue;
 
-            // observed point in float64, kept as an offset from a nearby voxel
-            const double Dd = (double)D;
-            const double x0 = Dd * (((double)u - fc.cx_d) * fc.ifx_d);
-            const double x1 = Dd * (((double)v - fc.cy_d) * fc.ify_d);
+            // observed point as an offset from a nearby voxel: formed in
+            // float64 for FP32 storage; camera-relative float32 for 16-bit
+            // storage (q - v_s m_c = R x + t_r, |t_r| < v_s)
             int mref[3];
             float prel[3];
+            if (STORAGE == GSDF_FP32) {
+                const double Dd = (double)D;
+                const double x0 = Dd * (((double)u - fc.cx_d) * fc.ifx_d);
+                const double x1 = Dd * (((double)v - fc.cy_d) * fc.ify_d);
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const double q = R[3 * i] * x0 + R[3 * i + 1] * x1 + R[3 * i + 2] * Dd + t[i];
-                mref[i] = (int)floor(q * fc.inv_vs_d + 0.5);
-                prel[i] = (float)(q - fc.vs_d * (double)mref[i]);
+                for (int i = 0; i < 3; ++i) {
+                    const double q = R[3 * i] * x0 + R[3 * i + 1] * x1 + R[3 * i + 2] * Dd + t[i];
+                    mref[i] = (int)floor(q * fc.inv_vs_d + 0.5);
+                    prel[i] = (float)(q - fc.vs_d * (double)mref[i]);
+                }
+            } else {
+                const float x0 = D * (((float)u - fc.rcx) / fc.fxf);
+                const float x1 = D * (((float)v - fc.rcy) / fc.fyf);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const float qc = Rf[3 * i] * x0 + Rf[3 * i + 1] * x1 + Rf[3 * i + 2] * D + trf[i];
+                    const int dm = (int)floorf(qc * ivsf + 0.5f);
+                    mref[i] = mc[i] + dm;
+                    prel[i] = qc - fc.vs_f * (float)dm;
+                }
             }
             int pm[3] = {INT_MIN, INT_MIN, INT_MIN};
             for (int k = k0; k <= k1; ++k) {

@@ -82,10 +82,34 @@ __device__ inline bool read_voxel(const MapView& M, int64_t vi, float* psi, floa
     return true;
 }
 
+// Compensated (Kahan) float32 accumulation: after any number of add()s,
+// value() is the sum with O(eps) rather than O(n eps) error.
+struct Kahan {
+    float s = 0.0f, c = 0.0f;
+    __device__ inline void add(float x) {
+        const float y = x - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ inline float value() const { return s - c; }
+};
+
 // Accumulate the normal equations of the pixels this thread owns at `pose`.
+//
+// FP32 storage (the plain path): each pixel's world point and its nearest
+// voxel are formed in float64, then the offset from the voxel goes to
+// float32; sums are float32 per thread.
+// 16-bit storage (the precision form): all per-pixel arithmetic is float32,
+// camera-relative: q - v_s m_c = R x + t_r with m_c the voxel nearest the
+// camera centre and t_r = t - v_s m_c (|t_r| < v_s), so no float32 value
+// holds an absolute coordinate at the voxel association; sums are
+// compensated (Kahan) float32.  Only the pose itself is float64.
 template <int STORAGE>
 __device__ inline void accumulate(const MapView& M, const TrackLevel& L, const TrackArgs& a,
-                                  const double* pose, int first, int stride, float acc[kNE]) {
+                                  const double* pose, int first, int stride, float acc[kNE], float cmp[kNE]) {
+    constexpr bool kPrecision = STORAGE != GSDF_FP32;
+    Kahan ks[kNE];
 #pragma unroll
     for (int k = 0; k < kNE; ++k) acc[k] = 0.0f;
     double R[9], t[3];
@@ -95,24 +119,51 @@ __device__ inline void accumulate(const MapView& M, const TrackLevel& L, const T
         for (int j = 0; j < 3; ++j) R[3 * i + j] = pose[4 * i + j];
         t[i] = pose[4 * i + 3];
     }
+    // camera-relative float32 pose (precision form)
+    float Rf[9], trf[3], mcf[3];
+    int mc[3];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Rf[i] = (float)R[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        mc[i] = (int)floor(t[i] * a.inv_vs + 0.5);
+        trf[i] = (float)(t[i] - a.vs * (double)mc[i]);
+        mcf[i] = (float)(a.vs * (double)mc[i]);
+    }
+    const float vsf = (float)a.vs, ivsf = (float)a.inv_vs;
+    const float ifxf = (float)L.ifx, ifyf = (float)L.ify, cxf = (float)L.cx, cyf = (float)L.cy;
+
     const int N = L.W * L.H;
     for (int i = first; i < N; i += stride) {
         const float D = L.depth[i];
         if (!depth_ok(D, a.zmin, a.zmax)) continue;
-        acc[29] += 1.0f;
+        if (kPrecision) ks[29].add(1.0f); else acc[29] += 1.0f;
         const int v = i / L.W;
         const int u = i - v * L.W;
-        const double Dd = (double)D;
-        const double x0 = Dd * (((double)u - L.cx) * L.ifx);
-        const double x1 = Dd * (((double)v - L.cy) * L.ify);
-        double q[3];
         int m[3];
-        float qr[3];
+        float qr[3], qf[3];
+        if (!kPrecision) {
+            const double Dd = (double)D;
+            const double x0 = Dd * (((double)u - L.cx) * L.ifx);
+            const double x1 = Dd * (((double)v - L.cy) * L.ify);
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            q[r] = R[3 * r] * x0 + R[3 * r + 1] * x1 + R[3 * r + 2] * Dd + t[r];
-            m[r] = (int)floor(q[r] * a.inv_vs + 0.5);
-            qr[r] = (float)(q[r] - a.vs * (double)m[r]);
+            for (int r = 0; r < 3; ++r) {
+                const double q = R[3 * r] * x0 + R[3 * r + 1] * x1 + R[3 * r + 2] * Dd + t[r];
+                m[r] = (int)floor(q * a.inv_vs + 0.5);
+                qr[r] = (float)(q - a.vs * (double)m[r]);
+                qf[r] = (float)q;
+            }
+        } else {
+            const float x0 = D * (((float)u - cxf) * ifxf);
+            const float x1 = D * (((float)v - cyf) * ifyf);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const float qc = Rf[3 * r] * x0 + Rf[3 * r + 1] * x1 + Rf[3 * r + 2] * D + trf[r];
+                const int dm = (int)floorf(qc * ivsf + 0.5f);
+                m[r] = mc[r] + dm;
+                qr[r] = qc - vsf * (float)dm;
+                qf[r] = qc + mcf[r];
+            }
         }
         const int32_t slot = hash_find(M, block_of(m[0]), block_of(m[1]), block_of(m[2]));
         if (slot < 0) continue;
@@ -120,7 +171,6 @@ __device__ inline void accumulate(const MapView& M, const TrackLevel& L, const T
         float psi, gh[3];
         if (!read_voxel<STORAGE>(M, vi, &psi, gh)) continue;
         const float r = psi + gh[0] * qr[0] + gh[1] * qr[1] + gh[2] * qr[2];
-        const float qf[3] = {(float)q[0], (float)q[1], (float)q[2]};
         const float J[6] = {gh[0], gh[1], gh[2], qf[1] * gh[2] - qf[2] * gh[1],
                             qf[2] * gh[0] - qf[0] * gh[2], qf[0] * gh[1] - qf[1] * gh[0]};
         const float ar = fabsf(r);
@@ -131,30 +181,52 @@ __device__ inline void accumulate(const MapView& M, const TrackLevel& L, const T
         for (int p = 0; p < 6; ++p) {
             const float wj = w * J[p];
 #pragma unroll
-            for (int q2 = p; q2 < 6; ++q2) acc[k++] += wj * J[q2];
+            for (int q2 = p; q2 < 6; ++q2) {
+                if (kPrecision) ks[k].add(wj * J[q2]); else acc[k] += wj * J[q2];
+                ++k;
+            }
         }
 #pragma unroll
-        for (int p = 0; p < 6; ++p) acc[21 + p] += w * J[p] * r;
-        acc[27] += e;
-        acc[28] += 1.0f;
+        for (int p = 0; p < 6; ++p) {
+            if (kPrecision) ks[21 + p].add(w * J[p] * r); else acc[21 + p] += w * J[p] * r;
+        }
+        if (kPrecision) {
+            ks[27].add(e);
+            ks[28].add(1.0f);
+        } else {
+            acc[27] += e;
+            acc[28] += 1.0f;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kNE; ++k) {
+        if (kPrecision) {
+            acc[k] = ks[k].s;
+            cmp[k] = ks[k].c;
+        } else {
+            cmp[k] = 0.0f;
+        }
     }
 }
 
-// Work-group sum: every thread writes its kNE float32 sums to LDS (one
-// transpose), then 8 threads per entry add 32 values each in float64 with
-// independent LDS reads, and the first kNE threads combine the 8 parts and
-// store the work-group partial with device-scope stores.  (Cross-lane
-// shuffles of doubles would chain ~180 dependent LDS permutes per wave.)
-// The barrier at the end waits for those stores; the thread that takes the
-// arrival ticket issues the work-group's single release fence.
+// Work-group sum: every thread writes its kNE sums to LDS (one transpose),
+// then 8 threads per entry add 32 values each with independent LDS reads,
+// and the first kNE threads combine the 8 parts and store the work-group
+// partial with device-scope stores.  (Cross-lane shuffles of doubles would
+// chain ~180 dependent LDS permutes per wave.)  The plain path adds in
+// float64; the precision form (COMP) uses compensated float32 at every
+// stage.  The barrier at the end waits for the stores; the thread that
+// takes the arrival ticket issues the work-group's single release fence.
 struct ReduceLds {
     float v[kNE][kTrackBlock];
     double part[kNE][8];
 };
 
-__device__ inline void store_partial(const float acc[kNE], double* partial, ReduceLds& r) {
+template <bool COMP>
+__device__ inline void store_partial(const float acc[kNE], const float cmp[kNE], double* partial,
+                                     ReduceLds& r) {
 #pragma unroll
-    for (int k = 0; k < kNE; ++k) r.v[k][threadIdx.x] = acc[k];
+    for (int k = 0; k < kNE; ++k) r.v[k][threadIdx.x] = COMP ? acc[k] - cmp[k] : acc[k];
     __syncthreads();
     if (threadIdx.x < kNE * 8) {
         const int k = threadIdx.x >> 3, p = threadIdx.x & 7;
@@ -162,46 +234,78 @@ __device__ inline void store_partial(const float acc[kNE], double* partial, Redu
         float4 q[kTrackBlock / 32];
 #pragma unroll
         for (int j = 0; j < kTrackBlock / 32; ++j) q[j] = src[j];
-        double s = 0.0;
+        if (COMP) {
+            Kahan ks;
 #pragma unroll
-        for (int j = 0; j < kTrackBlock / 32; ++j) s += ((double)q[j].x + (double)q[j].y) + ((double)q[j].z + (double)q[j].w);
-        r.part[k][p] = s;
+            for (int j = 0; j < kTrackBlock / 32; ++j) {
+                ks.add(q[j].x);
+                ks.add(q[j].y);
+                ks.add(q[j].z);
+                ks.add(q[j].w);
+            }
+            r.part[k][p] = (double)ks.value();
+        } else {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < kTrackBlock / 32; ++j)
+                s += ((double)q[j].x + (double)q[j].y) + ((double)q[j].z + (double)q[j].w);
+            r.part[k][p] = s;
+        }
     }
     __syncthreads();
     if (threadIdx.x < kNE) {
         double s = 0.0;
+        if (COMP) {
+            Kahan ks;
 #pragma unroll
-        for (int p = 0; p < 8; ++p) s += r.part[threadIdx.x][p];
+            for (int p = 0; p < 8; ++p) ks.add((float)r.part[threadIdx.x][p]);
+            s = (double)ks.value();
+        } else {
+#pragma unroll
+            for (int p = 0; p < 8; ++p) s += r.part[threadIdx.x][p];
+        }
         __hip_atomic_store(&partial[threadIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
 }
 
-// Sum of all work-group partials in float64 (called by the last work-group
-// after its acquire fence, so plain loads see every partial).  Thread
-// (k, p) adds entry k of the partials p, p+8, ... with eight loads in flight.
-// Result in ne[] of thread 0.
+// Sum of `groups` partials (called after the acquire fence, so plain loads
+// see every partial).  Thread (k, p) adds entry k of the partials p, p+8, ...
+// with eight loads in flight.  Result in ne[] of thread 0.
+template <bool COMP>
 __device__ inline void total_partials(const double* partials, int groups, double ne[kNE], ReduceLds& r) {
     if (threadIdx.x < kNE * 8) {
         const int k = threadIdx.x >> 3, p = threadIdx.x & 7;
         double s = 0.0;
+        Kahan ks;
         int b = p;
         for (; b + 56 < groups; b += 64) {
             double x[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) x[j] = partials[(size_t)(b + 8 * j) * kPartStride + k];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) s += x[j];
+            for (int j = 0; j < 8; ++j) {
+                if (COMP) ks.add((float)x[j]); else s += x[j];
+            }
         }
-        for (; b < groups; b += 8) s += partials[(size_t)b * kPartStride + k];
-        r.part[k][p] = s;
+        for (; b < groups; b += 8) {
+            const double x = partials[(size_t)b * kPartStride + k];
+            if (COMP) ks.add((float)x); else s += x;
+        }
+        r.part[k][p] = COMP ? (double)ks.value() : s;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int k = 0; k < kNE; ++k) {
-            double t = 0.0;
-            for (int p = 0; p < 8; ++p) t += r.part[k][p];
-            ne[k] = t;
+            if (COMP) {
+                Kahan ks;
+                for (int p = 0; p < 8; ++p) ks.add((float)r.part[k][p]);
+                ne[k] = (double)ks.value();
+            } else {
+                double t = 0.0;
+                for (int p = 0; p < 8; ++p) t += r.part[k][p];
+                ne[k] = t;
+            }
         }
     }
 }
@@ -337,16 +441,18 @@ __device__ inline bool root_arrive(unsigned* sync, int par, int groups) {
 // those.  Returns true (in every thread) for the work-group that holds the
 // total, in ne[] of thread 0.  `part` has one partial per work-group,
 // `leafpart` one per leaf.
-__device__ inline bool reduce_tree(const float acc[kNE], double* part, double* leafpart, unsigned* sync,
-                                   int par, int groups, double ne[kNE], ReduceLds& r, int* s_flag) {
-    store_partial(acc, part + (size_t)blockIdx.x * kPartStride, r);
+template <bool COMP>
+__device__ inline bool reduce_tree(const float acc[kNE], const float cmp[kNE], double* part, double* leafpart,
+                                   unsigned* sync, int par, int groups, double ne[kNE], ReduceLds& r,
+                                   int* s_flag) {
+    store_partial<COMP>(acc, cmp, part + (size_t)blockIdx.x * kPartStride, r);
     if (threadIdx.x == 0) *s_flag = leaf_arrive(sync, par, groups) ? 1 : 0;
     __syncthreads();
     if (!*s_flag) return false;
     const int leaf = blockIdx.x / kLeaf;
     const int leaf_size = min(kLeaf, groups - leaf * kLeaf);
     double lsum[kNE];
-    total_partials(part + (size_t)leaf * kLeaf * kPartStride, leaf_size, lsum, r);
+    total_partials<COMP>(part + (size_t)leaf * kLeaf * kPartStride, leaf_size, lsum, r);
     if (threadIdx.x == 0) {
         for (int k = 0; k < kNE; ++k)
             __hip_atomic_store(&leafpart[(size_t)leaf * kPartStride + k], lsum[k], __ATOMIC_RELAXED,
@@ -355,7 +461,7 @@ __device__ inline bool reduce_tree(const float acc[kNE], double* part, double* l
     }
     __syncthreads();
     if (!*s_flag) return false;
-    total_partials(leafpart, (groups + kLeaf - 1) / kLeaf, ne, r);
+    total_partials<COMP>(leafpart, (groups + kLeaf - 1) / kLeaf, ne, r);
     return true;
 }
 
@@ -429,13 +535,14 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
             double P[12];
 #pragma unroll
             for (int k = 0; k < 12; ++k) P[k] = s_pose[k];
-            float acc[kNE];
-            accumulate<STORAGE>(M, L, a, P, blockIdx.x * kTrackBlock + threadIdx.x, Gl * kTrackBlock, acc);
+            float acc[kNE], cmp[kNE];
+            accumulate<STORAGE>(M, L, a, P, blockIdx.x * kTrackBlock + threadIdx.x, Gl * kTrackBlock, acc, cmp);
 
             double* part = partials + (size_t)(gi & 1) * kPartsPerSet;
             double* leafpart = part + (size_t)kMaxGroups * kPartStride;
             double ne[kNE];
-            if (!reduce_tree(acc, part, leafpart, sync, gi & 1, Gl, ne, red, &s_last)) continue;
+            if (!reduce_tree<STORAGE != GSDF_FP32>(acc, cmp, part, leafpart, sync, gi & 1, Gl, ne, red, &s_last))
+                continue;
 
             // ---- the work-group holding the total: solve, publish
             if (threadIdx.x == 0) {
@@ -478,12 +585,12 @@ __global__ __launch_bounds__(kTrackBlock) void k_normal_equations(MapView M, Tra
     double P[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) P[k] = pose[k];
-    float acc[kNE];
+    float acc[kNE], cmp[kNE];
     accumulate<STORAGE>(M, a.lv[0], a, P, blockIdx.x * kTrackBlock + threadIdx.x,
-                        gridDim.x * kTrackBlock, acc);
+                        gridDim.x * kTrackBlock, acc, cmp);
     double ne[kNE];
-    if (!reduce_tree(acc, partials, partials + (size_t)kMaxGroups * kPartStride, sync, 0, gridDim.x, ne, red,
-                     &s_last))
+    if (!reduce_tree<STORAGE != GSDF_FP32>(acc, cmp, partials, partials + (size_t)kMaxGroups * kPartStride, sync,
+                                           0, gridDim.x, ne, red, &s_last))
         return;
     if (threadIdx.x == 0)
         for (int k = 0; k < 29; ++k) out29[k] = ne[k];

@@ -1,0 +1,217 @@
+"""The reduced-precision form on the GPU: 16-bit (bf16 / fp16) voxel storage,
+FP32 residuals with compensated sums, FP64 solve.
+
+* fusion against the oracle's emulation of the same storage (per-frame FP64
+  update, then psi/T and the mean gradient rounded to the 16-bit format):
+  keys bit-exact, values within one unit in the last place of the format;
+* tracking against the FP64 oracle on the identical (exported) map: pose
+  within 1e-5 rad / 1e-5 m;
+* the error of the 16-bit forms against the FP64 oracle and the FP32 GPU
+  path on the 1280x720, 5 mm stream, stated and bounded."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2111_13652_amd import synth
+from tests.gpu_helpers import align_voxels, assert_same_keys, dev, log, marginal_voxels, pose_diff
+
+pytestmark = pytest.mark.gpu
+
+ROOM = synth.CONFIG_ROOM
+HD = synth.CONFIG_ROOM_HD
+COS75 = math.cos(math.radians(75.0))
+MANTISSA = {"bf16": 8, "fp16": 11}   # significant bits of the storage format
+
+
+
+def _dtypes():
+    import torch
+    return {"bf16": torch.bfloat16, "fp16": torch.float16}
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    from paper_2111_13652_amd import gsdf  # noqa: F401  (loads libgsdf.so or fails)
+    return torch
+
+
+@pytest.fixture(scope="module")
+def room_stream():
+    return synth.make_stream(ROOM["cam"], 6, 1, 2, 3)
+
+
+def _gpu_map(vs, T, max_blocks=60000, **kw):
+    from paper_2111_13652_amd.gsdf import GsdfMap
+    return GsdfMap(vs, T, max_blocks, **kw)
+
+
+def _ulp_bound(a, b, storage):
+    """One unit in the last place of the larger magnitude (upper bound)."""
+    return 2.0 ** (1 - MANTISSA[storage]) * np.maximum(np.abs(a), np.abs(b)) + 2.0 ** -24
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp16"])
+def test_fusion_matches_emulated_storage(torch_mod, room_stream, storage):
+    """Each frame's update from an identical stored state: before every
+    frame the oracle takes the GPU's stored values, then both fuse the frame.
+
+    Bar per value: one unit in the last place of the format at the larger
+    magnitude (a pre-rounding difference can straddle a rounding boundary),
+    plus what the float32 geometry of the 16-bit path moves before rounding.
+    That path forms d camera-relative in float32: |dd| <~ 5e-7 m over a 4 m
+    range, i.e. < 2e-5 in units of T = 5 cm (1e-5 on the gradient, from the
+    float32 closed-form normal).  The linear weight has slope 1/(T - eps)
+    = 25 per metre, so each observation's weight moves by ~1.3e-5, and a
+    weighted mean of n observations by at most 2 n 1.3e-5 / W: with n <= 8
+    observations per voxel and frame this is the 2e-4 / W term, which only
+    matters for voxels seen near d = +-T (tiny W).  A difference carried
+    from an earlier frame is not part of this check; the stream-level error
+    is stated by the 1280x720 report below."""
+    torch = torch_mod
+    DTYPES = _dtypes()
+    st = room_stream
+    cam = st.cam
+    vs, T = ROOM["voxel_size"], ROOM["truncation"]
+    O = oracle.OracleMap(vs, T)
+    G = _gpu_map(vs, T, storage=storage)
+    loc = np.stack([np.arange(512) % 8, (np.arange(512) // 8) % 8, np.arange(512) // 64], -1)
+    for f in range(4):
+        log(f"case: {storage} fusion, room 640x480, frame {f} at ground truth")
+        D, P = dev(st.depth[f]), dev(st.poses[f])
+        G.allocate(D, cam, P)
+        O.allocate(st.depth[f], cam, st.poses[f])
+        assert_same_keys(G.keys(), O.keys())
+        if f:
+            gk = G.keys()
+            psi, g, W = G.voxels(len(gk))
+            O.set_voxels(gk, psi.astype(np.float64), g.astype(np.float64), W.astype(np.float64))
+        _, marg = O.clone().integrate(st.depth[f], cam, st.poses[f], return_marginal=True)
+        exclude = marginal_voxels(O, st.depth[f], cam, st.poses[f], marg)
+        O.integrate_rounded(st.depth[f], cam, st.poses[f], storage)
+        G.integrate(D, cam, P)
+        torch.cuda.synchronize()
+        (pg, gg, Wg), (po, go, Wo), keys = align_voxels(G, O)
+        both = (Wg > 0) & (Wo > 0)
+        if exclude:
+            c = 8 * keys[:, None, :] + loc[None]
+            for b, j in np.argwhere(both):
+                if tuple(c[b, j]) in exclude:
+                    both[b, j] = False
+        assert ((Wg > 0) != (Wo > 0)).sum() <= len(exclude)
+        x_g, x_o = pg[both] / T, po[both] / T
+        wterm = 2e-4 / Wo[both]
+        dpsi = np.abs(x_g - x_o) / (_ulp_bound(x_g, x_o, storage) + 2e-5 + wterm)
+        dg = np.abs(gg[both] - go[both]) / (_ulp_bound(gg[both], go[both], storage) + 1e-5
+                                           + wterm[:, None])
+        dW = np.abs(Wg[both] - Wo[both]) / (Wo[both] + 10.0)
+        q = lambda x: torch.tensor(x, dtype=torch.float32).to(DTYPES[storage]).float().numpy()
+        rep = dict(n=int(both.sum()), excluded=len(exclude), psi_rel_bar=float(dpsi.max()),
+                   g_rel_bar=float(dg.max()), psi_frac_differ=float(np.mean(q(x_g) != q(x_o))),
+                   g_frac_differ=float(np.mean(gg[both] != go[both])), w_rel=float(dW.max()))
+        log("precision fusion parity", storage, rep)
+        for i in np.argsort(-dg.max(axis=1))[:3]:
+            log(f"  g {gg[both][i]} vs {go[both][i]}; W {Wg[both][i]:.6g} vs {Wo[both][i]:.6g}")
+        assert rep["n"] > 50000
+        assert rep["psi_rel_bar"] <= 1.0 and rep["g_rel_bar"] <= 1.0, rep
+        assert rep["w_rel"] <= 1e-5, rep
+    assert G.status_flags() == []
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp16"])
+def test_tracking_matches_oracle_on_the_same_map(torch_mod, room_stream, storage):
+    torch = torch_mod
+    st = room_stream
+    cam = st.cam
+    vs, T = ROOM["voxel_size"], ROOM["truncation"]
+    log(f"case: {storage} tracking of frame 4 against the fused frames 0-3")
+    G = _gpu_map(vs, T, storage=storage)
+    for f in range(4):
+        D, P = dev(st.depth[f]), dev(st.poses[f])
+        G.allocate(D, cam, P)
+        G.integrate(D, cam, P)
+    keys = G.keys()
+    psi, g, W = G.voxels(len(keys))
+    O = oracle.OracleMap(vs, T)
+    O.set_voxels(keys, psi.astype(np.float64), g.astype(np.float64), W.astype(np.float64))
+    T0 = st.poses[3]
+    # normal equations at one pose (the oracle in FP64 on the same values)
+    ne_o = O.normal_equations(st.depth[4].astype(np.float64), cam, T0, 0.01)
+    ne_g = G.normal_equations(dev(st.depth[4]), cam, dev(T0), 0.01).cpu().numpy()
+    Ho, bo, Eo, no = oracle.unpack_upper(ne_o)
+    Hg, bg, Eg, ng = oracle.unpack_upper(ne_g)
+    relH = np.linalg.norm(Hg - Ho) / np.linalg.norm(Ho)
+    relb = np.linalg.norm(bg - bo) / np.linalg.norm(bo)
+    log(f"  n {ng} vs {no}; rel H {relH:.2e}; rel b {relb:.2e}; rel E {abs(Eg - Eo) / Eo:.2e}")
+    assert abs(ng - no) <= 1e-5 * no
+    assert relH < 1e-5 and relb < 1e-5 and abs(Eg - Eo) < 1e-5 * Eo
+    To, _, _ = O.track(st.depth[4], cam, T0, 3, [4, 5, 10], 0.01)
+    P = dev(T0.copy())
+    G.track(dev(st.depth[4]), cam, P, levels=3, iters=(4, 5, 10), delta=0.01)
+    da, dt = pose_diff(P.cpu().numpy(), To)
+    log("pose GPU vs oracle on the same map", storage, da, dt)
+    assert da < 1e-5 and dt < 1e-5
+    assert G.status_flags() == []
+
+
+def test_hd_error_against_fp64_oracle_and_fp32_path(torch_mod):
+    """1280x720, 5 mm voxels: SDF error (fused at ground truth) and tracked
+    poses of the three storage forms, each against the FP64 oracle and the
+    16-bit forms also against the FP32 GPU path."""
+    torch = torch_mod
+    cam = HD["cam"]
+    vs, T = HD["voxel_size"], HD["truncation"]
+    F = 5
+    st = synth.make_stream(cam, F, scene_seed=1, traj_seed=5, noise_seed=6)
+    log(f"case: HD error report, {F} frames")
+    # SDF error: everything fused at the ground-truth poses
+    O = oracle.OracleMap(vs, T)
+    for f in range(F):
+        O.allocate(st.depth[f], cam, st.poses[f])
+        O.integrate(st.depth[f], cam, st.poses[f])
+    maps = {}
+    for storage in ("fp32", "bf16", "fp16"):
+        G = _gpu_map(vs, T, max_blocks=120000, storage=storage)
+        for f in range(F):
+            D, P = dev(st.depth[f]), dev(st.poses[f])
+            G.allocate(D, cam, P)
+            G.integrate(D, cam, P)
+        torch.cuda.synchronize()
+        assert_same_keys(G.keys(), O.keys())
+        maps[storage] = align_voxels(G, O)
+        assert G.status_flags() == []
+    (po, go, Wo) = maps["fp32"][1]
+    report = {}
+    for storage in ("fp32", "bf16", "fp16"):
+        pg, gg, Wg = maps[storage][0]
+        both = (Wg > 0) & (Wo > 0) & (np.abs(po) < T)
+        e = np.abs(pg[both] - po[both])
+        e32 = np.abs(pg[both] - maps["fp32"][0][0][both])
+        report[storage] = dict(psi_max_vs_oracle=float(e.max() / vs), psi_rms_vs_oracle=float(
+            np.sqrt(np.mean(e ** 2)) / vs), psi_max_vs_fp32=float(e32.max() / vs))
+    # pose: the tracked loop of each form against the FP64 oracle's loop
+    _, To = oracle.track_stream(st.depth, cam, st.poses, vs, T)
+    from paper_2111_13652_amd.gsdf import run_stream
+    est = {}
+    for storage in ("fp32", "bf16", "fp16"):
+        G = _gpu_map(vs, T, max_blocks=120000, storage=storage)
+        est[storage] = run_stream(G, dev(st.depth), cam, dev(st.poses[0])).cpu().numpy()
+        assert G.status_flags() == []
+    for storage in ("fp32", "bf16", "fp16"):
+        d_or = max(pose_diff(est[storage][f], To[f]) for f in range(F))
+        d_32 = max(pose_diff(est[storage][f], est["fp32"][f]) for f in range(F))
+        d_gt = max(pose_diff(est[storage][f], st.poses[f]) for f in range(F))
+        report[storage].update(pose_vs_oracle=d_or, pose_vs_fp32=d_32, pose_vs_truth=d_gt)
+    for k, v in report.items():
+        log("HD error", k, v)
+    # FP32 storage is the plain path: oracle tolerances
+    assert report["fp32"]["psi_max_vs_oracle"] <= 1e-4
+    assert max(report["fp32"]["pose_vs_oracle"]) < 1e-5
+    # 16-bit storage: per-frame rounding of psi/T with relative step 2^-p,
+    # at most F roundings accumulate; poses within 0.1 mrad / 0.1 mm
+    for storage in ("bf16", "fp16"):
+        bound = F * T * 2.0 ** -MANTISSA[storage] / vs
+        assert report[storage]["psi_max_vs_oracle"] <= bound, (storage, bound)
+        assert max(report[storage]["pose_vs_oracle"]) < 1e-4
