@@ -40,6 +40,34 @@ B_ALLOC_PIXEL = 4.0        # depth read per pixel
 B_ALLOC_PAIR = 16.0        # hash entry per distinct (tile, block) probe
 
 
+# HBM-side bytes per launch from two rocprofv3 --pmc passes (FETCH_SIZE, then
+# WRITE_SIZE) over this workload, each scaled by what the same counter reads
+# for a plain 256 MiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  A
+# figure is reported only while the kernel's sources still hash to the
+# values they had when the counters were taken.
+MEASURED_TRAFFIC = {
+    "track": {"bytes": (13749.0 * 2.0 + 1111.3) * 1024,
+              "sources": {"gsdf_track.hip": "95f3afd2eb2ce8c3b7b9f12d2ec0f64625a50df6947bc0f4b99f6d4f80aa83d4",
+                          "gsdf_common.hpp": "accfd9a487ef21d1dc41374aca70c29fa5bd8d073cea674d16d78099d8a35574"}},
+    "fuse_blocks": {"bytes": (20546.1 * 2.0 + 11865.1) * 1024,
+                    "sources": {"gsdf_fuse.hip": "d8f43ab934dc8395440fcdc5bf253025b40818b93c1ead3af4f0fe581c302c85",
+                                "gsdf_common.hpp": "accfd9a487ef21d1dc41374aca70c29fa5bd8d073cea674d16d78099d8a35574"}},
+}
+
+
+def _traffic(kernel: str, storage: str):
+    import hashlib
+    m = MEASURED_TRAFFIC.get(kernel)
+    if m is None or storage != "fp32":
+        return None
+    csrc = os.path.join(ROOT, "paper_2111_13652_amd", "csrc")
+    for name, digest in m["sources"].items():
+        with open(os.path.join(csrc, name), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return m["bytes"]
+
+
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,6 +78,9 @@ def _parse():
                     help="frames of the stream the oracle runs for the CPU baseline")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--no-h2d", action="store_true", help="skip the PCIe-inclusive pass")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB three times "
+                         "(scale reference for hardware byte counters)")
     ap.add_argument("--storage", choices=("fp32", "bf16", "fp16"), default="fp32",
                     help="voxel storage: fp32 (plain path) or the 16-bit precision form")
     return ap.parse_args()
@@ -96,6 +127,16 @@ def main():
         for f in range(1, 1 + args.warmup):
             step(f)
         torch.cuda.synchronize()
+
+    if args.copy_mib > 0:
+        n = args.copy_mib << 18
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy reference: 3 x {args.copy_mib} MiB read + written", file=sys.stderr, flush=True)
+        del src, dst
 
     start()
     lib = _lib.load()
@@ -152,7 +193,7 @@ def main():
         bytes_per_launch = per_kernel_bytes[dom] / launches
         achieved = bytes_per_launch / avg_s / 1e9
         roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": _traffic(dom, args.storage),
                     "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6}
 
     # accuracy alongside throughput: ATE of the estimated trajectory
