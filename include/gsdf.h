@@ -184,6 +184,76 @@ int gsdf_normal_equations(const gsdf_map* map, const float* depth_dev, const gsd
                           void* scratch_dev, size_t scratch_bytes, void* stream);
 
 /* ---------------------------------------------------------------------- */
+/* Differentiable form: keyframe loss and its adjoint                      */
+/* ---------------------------------------------------------------------- */
+
+/* Per-voxel parameters: `params` is a float32 buffer of param_blocks x 512
+ * float4 {psi, g_x, g_y, g_z} indexed by pool slot, voxel (lx, ly, lz) of a
+ * block at Morton index gsdf_voxel_order()[lx + 8 ly + 64 lz].  g is the
+ * map's stored gradient (the accumulated gradient of Eq. (3) for FP32
+ * storage, its weighted mean for BF16/FP16); only its direction enters the
+ * residual.  Slots >= param_blocks count as unobserved. */
+
+/* Copy the map's voxels into params (psi = sum w d / W for FP32 storage);
+ * rows beyond the map's block count are zero.  params_dev holds
+ * param_blocks x 512 x 4 float32 (device). */
+int gsdf_export_params(const gsdf_map* map, float* params_dev, int64_t param_blocks, void* stream);
+
+/* Write params back into the map's observed voxels (W > 0), keeping W
+ * (for BF16/FP16 storage psi/T and g are rounded to the format). */
+int gsdf_import_params(gsdf_map* map, const float* params_dev, int64_t param_blocks, void* stream);
+
+/* Host call: order_out[lx + 8 ly + 64 lz] = that voxel's index inside its
+ * block in the map's (and the params') layout. */
+int gsdf_voxel_order(int32_t order_out[512]);
+
+/* T_out[i] = exp(xi_i^) T0[i] for i < n (Sec. 5.1 left pose update):
+ * T0_dev, T_out_dev n x 12 float64, xi_dev n x 6 float64 (device); T_out
+ * may alias T0. */
+int gsdf_compose_poses(int32_t n, const double* T0_dev, const double* xi_dev, double* T_out_dev,
+                       void* stream);
+
+/* Scratch bytes of gsdf_keyframe_loss / gsdf_keyframe_backward. */
+size_t gsdf_keyframe_scratch_bytes(const gsdf_camera* cam, int32_t n_keyframes);
+
+/* Keyframe loss (Sec. 4.1 Eq. (5), (14); Huber penalty of Sec. 5.1): for
+ * each keyframe i, L_i = sum over its valid pixels of rho_delta(r) with
+ * r = psi_j + g^_j . (q - v_j), q = T_i x, T_i = exp(xi_i^) T0_i, j the voxel
+ * nearest to q, (psi_j, g_j) read from params, and pixels whose voxel is
+ * absent, unobserved (W = 0) or has g = 0 skipped.
+ *   depth_dev: K x H x W float32 (device), 0 = invalid;
+ *   T0_dev: K x 12 float64 (device), row-major 3x4 camera-to-world;
+ *   xi_dev: K x 6 float64 (device), twist (translation, rotation) of the
+ *     left increment;
+ *   assoc_dev (optional): K x H x W x 3 int32 voxel coordinates: freeze = 0
+ *     writes each pixel's nearest voxel (INT32_MIN when unused), freeze = 1
+ *     reads them instead of searching (for finite differences);
+ *   loss_dev: K float64 (device); count_dev (optional): K float64 pixels used.
+ * Errors: GSDF_EINVAL for bad sizes, null buffers, freeze without assoc or
+ * scratch smaller than gsdf_keyframe_scratch_bytes. */
+int gsdf_keyframe_loss(const gsdf_map* map, const float* depth_dev, int32_t n_keyframes,
+                       const gsdf_camera* cam, const double* T0_dev, const double* xi_dev,
+                       const float* params_dev, int64_t param_blocks, float huber_delta,
+                       int32_t* assoc_dev, int32_t freeze, double* loss_dev, double* count_dev,
+                       void* scratch_dev, size_t scratch_bytes, void* stream);
+
+/* Adjoint of gsdf_keyframe_loss, recomputing every residual (nothing per
+ * pixel is stored between the two calls).  With s_i = grad_loss_dev[i]
+ * (K float32, device), rho' the Huber derivative and g^ = g/|g|:
+ *   dparams[j] += sum s_i rho'(r) {1, (I - g^ g^T)(q - v_j) / |g_j|}
+ *     (scatter-added at the voxel's slot: clear dparams_dev first),
+ *   dxi_dev[i] = Jl(xi_i)^T sum_k s_i rho'(r_k) [g^ ; q x g^]
+ *     (K x 6 float64, overwritten; Jl the left Jacobian of SE(3)),
+ *   loss_dev (optional) as gsdf_keyframe_loss.
+ * Same argument rules as gsdf_keyframe_loss. */
+int gsdf_keyframe_backward(const gsdf_map* map, const float* depth_dev, int32_t n_keyframes,
+                           const gsdf_camera* cam, const double* T0_dev, const double* xi_dev,
+                           const float* params_dev, int64_t param_blocks, float huber_delta,
+                           int32_t* assoc_dev, int32_t freeze, const float* grad_loss_dev,
+                           float* dparams_dev, double* dxi_dev, double* loss_dev,
+                           void* scratch_dev, size_t scratch_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Inspection, import (used for parity checks and checkpoints)             */
 /* ---------------------------------------------------------------------- */
 
@@ -222,6 +292,7 @@ enum {
     GSDF_K_PYRAMID = 3,
     GSDF_K_NORMALS = 4,
     GSDF_K_BACKWARD = 5,
+    GSDF_K_LOSS = 6,
     GSDF_K_COUNT = 16
 };
 

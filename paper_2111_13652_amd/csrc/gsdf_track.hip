@@ -21,6 +21,7 @@
 
 #include "gsdf_common.hpp"
 #include "gsdf_host.hpp"
+#include "gsdf_se3.hpp"
 
 namespace gsdf {
 
@@ -350,44 +351,7 @@ __device__ bool solve_and_update(const double* ne, double damping, double* pose)
         for (int q = i + 1; q < 6; ++q) s -= L[6 * q + i] * x[q];
         x[i] = s * inv_d[i];
     }
-    // exp of the twist (rho, phi) = (x[0..2], x[3..5])
-    const double* rho = x;
-    const double* phi = x + 3;
-    const double th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
-    const double th = sqrt(th2);
-    double A, B, C;
-    if (th < 1e-4) {
-        A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
-        B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
-        C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
-    } else {
-        const double sn = sin(th), cs = cos(th);
-        A = sn / th;
-        B = (1.0 - cs) / th2;
-        C = (th - sn) / (th2 * th);
-    }
-    const double K[9] = {0, -phi[2], phi[1], phi[2], 0, -phi[0], -phi[1], phi[0], 0};
-    double K2[9];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            K2[3 * i + j] = K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j] + K[3 * i + 2] * K[6 + j];
-    double Rd[9], V[9];
-    for (int i = 0; i < 9; ++i) {
-        const double I = (i % 4 == 0) ? 1.0 : 0.0;
-        Rd[i] = I + A * K[i] + B * K2[i];
-        V[i] = I + B * K[i] + C * K2[i];
-    }
-    double td[3];
-    for (int i = 0; i < 3; ++i) td[i] = V[3 * i] * rho[0] + V[3 * i + 1] * rho[1] + V[3 * i + 2] * rho[2];
-    double out[12];
-    for (int i = 0; i < 3; ++i) {
-        for (int j = 0; j < 4; ++j) {
-            double s = Rd[3 * i] * pose[j] + Rd[3 * i + 1] * pose[4 + j] + Rd[3 * i + 2] * pose[8 + j];
-            if (j == 3) s += td[i];
-            out[4 * i + j] = s;
-        }
-    }
-    for (int i = 0; i < 12; ++i) pose[i] = out[i];
+    se3_apply_left(x, pose);   // twist (rho, phi) = (x[0..2], x[3..5])
     return true;
 }
 

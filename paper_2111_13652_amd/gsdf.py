@@ -170,6 +170,33 @@ class GsdfMap:
                    "normal_equations")
         return out
 
+    # ---- differentiable form ----
+    def export_params(self, n_blocks: Optional[int] = None) -> torch.Tensor:
+        """Per-voxel parameters {psi, g} as a (n_blocks, 512, 4) float32 device
+        tensor in pool order, voxel index = Morton order (see voxel_order)."""
+        n = self.num_blocks() if n_blocks is None else int(n_blocks)
+        out = torch.empty((max(n, 0), 512, 4), dtype=torch.float32, device=self.device)
+        _lib.check(_lib.load().gsdf_export_params(C.byref(self._map), _ptr(out), n, _stream()),
+                   "export_params")
+        return out
+
+    def import_params(self, params: torch.Tensor) -> None:
+        """Write refined {psi, g} back into the observed voxels (W kept)."""
+        _need(params, torch.float32, None, "params")
+        if params.dim() != 3 or params.shape[1:] != (512, 4):
+            raise ValueError("params must be (n_blocks, 512, 4)")
+        _lib.check(_lib.load().gsdf_import_params(C.byref(self._map), _ptr(params), int(params.shape[0]),
+                                                   _stream()), "import_params")
+
+    def _keyframe_scratch(self, c: _lib.Camera, K: int) -> torch.Tensor:
+        key = ("kf", c.width, c.height, K)
+        if key not in self._scratch:
+            n = _lib.load().gsdf_keyframe_scratch_bytes(C.byref(c), int(K))
+            if n == 0:
+                raise ValueError("invalid camera / keyframe count")
+            self._scratch[key] = torch.empty(int(n), dtype=torch.uint8, device=self.device)
+        return self._scratch[key]
+
     # ---- inspection ----
     def num_blocks(self) -> int:
         n = torch.zeros(1, dtype=torch.int32, device=self.device)
@@ -206,6 +233,117 @@ class GsdfMap:
 
     def status_flags(self):
         return _lib.status_bits(int(self.status.item()))
+
+
+def voxel_order() -> np.ndarray:
+    """order[lx + 8 ly + 64 lz] = index of that voxel inside a block of the
+    map's (and the params') layout."""
+    out = np.zeros(512, np.int32)
+    _lib.check(_lib.load().gsdf_voxel_order(out.ctypes.data_as(C.c_void_p)), "voxel_order")
+    return out
+
+
+def _kf_args(gmap: GsdfMap, depth, cam, T0, xi, params, assoc):
+    c = camera(cam)
+    if depth.dim() != 3:
+        raise ValueError("depth must be (K, H, W)")
+    K = depth.shape[0]
+    _need(depth, torch.float32, (K, c.height, c.width), "depth")
+    _need(T0, torch.float64, (K, 3, 4), "T0")
+    _need(xi, torch.float64, (K, 6), "xi")
+    _need(params, torch.float32, None, "params")
+    if params.dim() != 3 or params.shape[1:] != (512, 4):
+        raise ValueError("params must be (n_blocks, 512, 4)")
+    if assoc is not None:
+        _need(assoc, torch.int32, (K, c.height, c.width, 3), "assoc")
+    return c, K
+
+
+def keyframe_loss(gmap: GsdfMap, params: torch.Tensor, xi: torch.Tensor, depth: torch.Tensor, cam,
+                  T0: torch.Tensor, delta: float = 0.01, assoc: Optional[torch.Tensor] = None,
+                  freeze: bool = False, count: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Per-keyframe Huber loss (K float64), no gradient."""
+    c, K = _kf_args(gmap, depth, cam, T0, xi, params, assoc)
+    loss = torch.empty(K, dtype=torch.float64, device=depth.device)
+    scratch = gmap._keyframe_scratch(c, K)
+    _lib.check(_lib.load().gsdf_keyframe_loss(
+        C.byref(gmap._map), _ptr(depth), K, C.byref(c), _ptr(T0), _ptr(xi), _ptr(params),
+        int(params.shape[0]), float(delta), _ptr(assoc), 1 if freeze else 0, _ptr(loss), _ptr(count),
+        _ptr(scratch), scratch.numel(), _stream()), "keyframe_loss")
+    return loss
+
+
+class KeyframeLoss(torch.autograd.Function):
+    """L_i = sum_k rho_delta(psi_j + g^_j . (T_i x_k - v_j)), T_i = exp(xi_i^) T0_i,
+    differentiable in the per-voxel parameters {psi, g} (scatter-added at the
+    voxel's slot) and the twists xi.  The backward kernel recomputes the
+    residuals; nothing per pixel is kept between the passes.
+
+        loss = KeyframeLoss.apply(params, xi, gmap, depth, cam, T0, delta)
+    """
+
+    @staticmethod
+    def forward(ctx, params, xi, gmap, depth, cam, T0, delta=0.01, assoc=None, freeze=False):
+        loss = keyframe_loss(gmap, params, xi, depth, cam, T0, delta, assoc, freeze)
+        ctx.save_for_backward(params, xi)
+        ctx.rest = (gmap, depth, cam, T0, delta, assoc, freeze)
+        return loss
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        params, xi = ctx.saved_tensors
+        gmap, depth, cam, T0, delta, assoc, freeze = ctx.rest
+        c, K = _kf_args(gmap, depth, cam, T0, xi, params, assoc)
+        gl = grad_loss.to(torch.float32).contiguous()
+        dparams = torch.zeros_like(params)
+        dxi = torch.empty_like(xi)
+        scratch = gmap._keyframe_scratch(c, K)
+        _lib.check(_lib.load().gsdf_keyframe_backward(
+            C.byref(gmap._map), _ptr(depth), K, C.byref(c), _ptr(T0), _ptr(xi), _ptr(params),
+            int(params.shape[0]), float(delta), _ptr(assoc), 1 if freeze else 0, _ptr(gl), _ptr(dparams),
+            _ptr(dxi), None, _ptr(scratch), scratch.numel(), _stream()), "keyframe_backward")
+        return (dparams if ctx.needs_input_grad[0] else None, dxi if ctx.needs_input_grad[1] else None,
+                None, None, None, None, None, None, None)
+
+
+def refine_keyframes(gmap: GsdfMap, depth: torch.Tensor, cam, T0: torch.Tensor, steps: int = 50,
+                     delta: float = 0.01, lr_pose: float = 1e-3, lr_geom: float = 0.0,
+                     params: Optional[torch.Tensor] = None, write_back: bool = False):
+    """Joint refinement of keyframe poses and (if lr_geom > 0) voxel
+    parameters by Adam on the summed keyframe loss.  Returns (poses (K,3,4),
+    params, losses per step).  With write_back the refined parameters are
+    imported into the map."""
+    K = depth.shape[0]
+    if params is None:
+        params = gmap.export_params()
+    params = params.detach().clone().requires_grad_(lr_geom > 0)
+    xi = torch.zeros((K, 6), dtype=torch.float64, device=depth.device, requires_grad=True)
+    groups = [{"params": [xi], "lr": lr_pose}]
+    if lr_geom > 0:
+        groups.append({"params": [params], "lr": lr_geom})
+    opt = torch.optim.Adam(groups)
+    losses = []
+    for _ in range(steps):
+        opt.zero_grad(set_to_none=True)
+        loss = KeyframeLoss.apply(params, xi, gmap, depth, cam, T0, delta).sum()
+        loss.backward()
+        opt.step()
+        losses.append(loss.detach())
+    poses = compose_left(xi.detach(), T0)
+    if write_back:
+        gmap.import_params(params.detach())
+    return poses, params.detach(), torch.stack(losses).cpu().numpy()
+
+
+def compose_left(xi: torch.Tensor, T0: torch.Tensor) -> torch.Tensor:
+    """exp(xi_i^) T0_i for (K, 6) / (K, 3, 4) float64 device tensors."""
+    K = T0.shape[0]
+    _need(T0, torch.float64, (K, 3, 4), "T0")
+    xi = xi.detach().contiguous()
+    _need(xi, torch.float64, (K, 6), "xi")
+    out = torch.empty_like(T0)
+    _lib.check(_lib.load().gsdf_compose_poses(K, _ptr(T0), _ptr(xi), _ptr(out), _stream()), "compose_poses")
+    return out
 
 
 def run_stream(m: GsdfMap, depth: torch.Tensor, cam, pose0: torch.Tensor, levels: int = 3,

@@ -56,3 +56,28 @@ def test_host_side_validation_without_gpu():
     assert lib.gsdf_track_scratch_bytes(C.byref(cam), 5) == 0
     assert lib.gsdf_integrate_scratch_bytes(C.byref(cam)) >= 640 * 480 * 16
     assert lib.gsdf_status_string(_lib.ECAPACITY) == b"hash table or block pool full"
+
+
+def test_voxel_order_and_differentiable_calls_validate_without_gpu():
+    import numpy as np
+    from paper_2111_13652_amd import _lib
+    lib = _lib.load()
+    order = np.zeros(512, np.int32)
+    assert lib.gsdf_voxel_order(order.ctypes.data_as(C.c_void_p)) == 0
+    assert sorted(order.tolist()) == list(range(512))
+    # every 2x2x2 sub-cube occupies 8 consecutive indices
+    c = np.arange(512)
+    lx, ly, lz = c % 8, (c // 8) % 8, c // 64
+    cube = (lx // 2) + 4 * (ly // 2) + 16 * (lz // 2)
+    for k in range(64):
+        idx = np.sort(order[cube == k])
+        assert idx[-1] - idx[0] == 7
+    cam = _lib.Camera(525.0, 525.0, 319.5, 239.5, 640, 480, 0.4, 4.0)
+    assert lib.gsdf_keyframe_scratch_bytes(C.byref(cam), 10) > 0
+    assert lib.gsdf_keyframe_scratch_bytes(C.byref(cam), 0) == 0
+    assert lib.gsdf_keyframe_loss(None, None, 1, C.byref(cam), None, None, None, 0, 0.01, None, 0, None,
+                                  None, None, 0, None) == _lib.EINVAL
+    assert lib.gsdf_keyframe_backward(None, None, 1, C.byref(cam), None, None, None, 0, 0.01, None, 0, None,
+                                      None, None, None, None, 0, None) == _lib.EINVAL
+    assert lib.gsdf_compose_poses(-1, None, None, None, None) == _lib.EINVAL
+    assert lib.gsdf_compose_poses(0, None, None, None, None) == _lib.OK
