@@ -78,6 +78,7 @@ def _parse():
                     help="frames of the stream the oracle runs for the CPU baseline")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--no-h2d", action="store_true", help="skip the PCIe-inclusive pass")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation measurement")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times "
                          "(scale reference for hardware byte counters)")
@@ -201,6 +202,59 @@ def main():
     G = stream.poses[: first + K]
     ate = float(np.sqrt(np.mean(np.sum((E[:, :, 3] - G[:, :, 3]) ** 2, axis=1))))
 
+    # ---- differentiation: keyframe loss + adjoint over 10 keyframes of the
+    # stream (poses perturbed by 1 deg / 1 cm) on the map fused above
+    diff = None
+    if not args.no_adjoint:
+        from paper_2111_13652_amd.gsdf import KeyframeLoss
+        kf = [first + i * (K // 10) for i in range(10)] if K >= 10 else list(range(first, first + K))
+        T0 = torch.as_tensor(np.stack([synth.perturb_pose(stream.poses[f], 100 + i, 1.0, 0.01)
+                                       for i, f in enumerate(kf)])).to(dev)
+        D = depth[kf].contiguous()
+        params = m.export_params().requires_grad_(True)
+        xi = torch.zeros((len(kf), 6), dtype=torch.float64, device=dev, requires_grad=True)
+
+        def fwd_bwd():
+            params.grad = None
+            xi.grad = None
+            KeyframeLoss.apply(params, xi, m, D, cam, T0, delta).sum().backward()
+
+        for _ in range(3):
+            fwd_bwd()
+        reps = 20
+        if timing:
+            lib.gsdf_timing_enable(1)
+        torch.cuda.synchronize()
+        ev0.record(s)
+        for _ in range(reps):
+            fwd_bwd()
+        ev1.record(s)
+        torch.cuda.synchronize()
+        dms = ev0.elapsed_time(ev1) / reps
+        dk = {}
+        if timing:
+            for name, kid in (("loss", _lib.K_LOSS), ("backward", _lib.K_BACKWARD)):
+                tot = C.c_double()
+                n = C.c_int64()
+                lib.gsdf_timing_read(kid, C.byref(tot), C.byref(n))
+                dk[name] = {"avg_us": 1e3 * tot.value / max(1, n.value), "launches": n.value}
+            lib.gsdf_timing_enable(0)
+        from paper_2111_13652_amd.gsdf import keyframe_loss
+        cnt = torch.zeros(len(kf), dtype=torch.float64, device=dev)
+        keyframe_loss(m, params.detach(), xi.detach(), D, cam, T0, delta, count=cnt)
+        used = float(cnt.sum().item())
+        observed = int((m.weight[: m.num_blocks() * 512] > 0).sum().item())
+        diff = {"keyframes": len(kf), "ms_per_forward_backward": dms,
+                "pixels_used": used, "observed_voxels": observed,
+                "param_blocks": int(params.shape[0]), "kernels": dk}
+        if dk:
+            # backward: depth 4 + hash entry 16 + W 4 + params 16 B read, 16 B of
+            # atomic adds per pixel used; 4 B depth per other pixel
+            npx_all = len(kf) * npx
+            bb = 4.0 * npx_all + (16 + 4 + 16 + 16) * used
+            diff["backward_algorithmic_gbs"] = bb / (dk["backward"]["avg_us"] * 1e-6) / 1e9
+        del params, xi
+
     # ---- PCIe-inclusive rate: each frame copied from pinned host memory first
     h2d = None
     if not args.no_h2d:
@@ -251,6 +305,7 @@ def main():
         "cpu_baseline": cpu,
         "fps_with_h2d": h2d,
         "accuracy": {"ate_rmse_m": ate, "status": status},
+        "differentiation": diff,
         "work_per_frame": {"fusion_updates": work[0] / K, "fusion_pixel_visits": work[1] / K,
                            "fused_voxels": work[2] / K, "fused_blocks": work[3] / K,
                            "alloc_pairs": work[4] / K, "track_valid_px_iters": work[5] / K,

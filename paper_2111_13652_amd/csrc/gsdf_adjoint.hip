@@ -135,33 +135,70 @@ __global__ __launch_bounds__(kAdjBlock) void k_keyframe_loss(MapView M, AdjArgs 
 #pragma unroll
     for (int k = 0; k < kAdjPart; ++k) acc[k] = 0.0f;
 
-    for (int i = blockIdx.x * kAdjBlock + threadIdx.x; i < N; i += a.groups * kAdjBlock) {
-        const int v = i / a.W;
-        const int u = i - v * a.W;
+    // Lanes of a wave take consecutive pixels of a row, so neighbouring lanes
+    // often share a voxel.  The gradient pass first sums each run of lanes
+    // with the same voxel (a segmented reduction over the wave) and lets the
+    // run's first lane issue the atomic adds: one set per (run, voxel)
+    // instead of one per pixel.
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int base = blockIdx.x * kAdjBlock + wave * 64; base < N; base += a.groups * kAdjBlock) {
+        const int i = base + lane;
         PixelTerm P;
-        if (!pixel_term(M, a, R, t, params, dimg[i], u, v, aimg ? aimg + 3 * (size_t)i : nullptr, &P)) continue;
-        const float r = P.psi + P.gh[0] * P.dq[0] + P.gh[1] * P.dq[1] + P.gh[2] * P.dq[2];
-        const float ar = fabsf(r);
-        const bool quad = ar <= a.delta;
-        acc[0] += quad ? 0.5f * r * r : a.delta * (ar - 0.5f * a.delta);
-        acc[7] += 1.0f;
-        if (GRAD) {
-            const float rp = s * (quad ? r : copysignf(a.delta, r));   // s rho'(r)
-            const float J[6] = {P.gh[0], P.gh[1], P.gh[2], P.q[1] * P.gh[2] - P.q[2] * P.gh[1],
-                                P.q[2] * P.gh[0] - P.q[0] * P.gh[2], P.q[0] * P.gh[1] - P.q[1] * P.gh[0]};
+        bool ok = false;
+        if (i < N) {
+            const int v = i / a.W;
+            const int u = i - v * a.W;
+            ok = pixel_term(M, a, R, t, params, dimg[i], u, v, aimg ? aimg + 3 * (size_t)i : nullptr, &P);
+        }
+        float g4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (ok) {
+            const float r = P.psi + P.gh[0] * P.dq[0] + P.gh[1] * P.dq[1] + P.gh[2] * P.dq[2];
+            const float ar = fabsf(r);
+            const bool quad = ar <= a.delta;
+            acc[0] += quad ? 0.5f * r * r : a.delta * (ar - 0.5f * a.delta);
+            acc[7] += 1.0f;
+            if (GRAD) {
+                const float rp = s * (quad ? r : copysignf(a.delta, r));   // s rho'(r)
+                const float J[6] = {P.gh[0], P.gh[1], P.gh[2], P.q[1] * P.gh[2] - P.q[2] * P.gh[1],
+                                    P.q[2] * P.gh[0] - P.q[0] * P.gh[2], P.q[0] * P.gh[1] - P.q[1] * P.gh[0]};
 #pragma unroll
-            for (int k = 0; k < 6; ++k) acc[1 + k] += rp * J[k];
-            const float gd = P.gh[0] * P.dq[0] + P.gh[1] * P.dq[1] + P.gh[2] * P.dq[2];
-            const float c = rp * P.inv_ng;
-            float* dst = dparams + 4 * P.vi;
-            atomicAdd(dst, rp);
-            atomicAdd(dst + 1, c * (P.dq[0] - P.gh[0] * gd));
-            atomicAdd(dst + 2, c * (P.dq[1] - P.gh[1] * gd));
-            atomicAdd(dst + 3, c * (P.dq[2] - P.gh[2] * gd));
+                for (int k = 0; k < 6; ++k) acc[1 + k] += rp * J[k];
+                const float gd = P.gh[0] * P.dq[0] + P.gh[1] * P.dq[1] + P.gh[2] * P.dq[2];
+                const float c = rp * P.inv_ng;
+                g4[0] = rp;
+                g4[1] = c * (P.dq[0] - P.gh[0] * gd);
+                g4[2] = c * (P.dq[1] - P.gh[1] * gd);
+                g4[3] = c * (P.dq[2] - P.gh[2] * gd);
+            }
+        }
+        if (GRAD) {
+            const int64_t key = ok ? P.vi : -1 - (int64_t)lane;   // unusable lanes: runs of their own
+            const int lo = __shfl_up((int)(key & 0xffffffff), 1);
+            const int hi = __shfl_up((int)(key >> 32), 1);
+            const int64_t prev = ((int64_t)hi << 32) | (uint32_t)lo;
+            const bool head = lane == 0 || prev != key;
+            const unsigned long long heads = __ballot(head);
+            const int rid = __popcll(heads & ((2ull << lane) - 1ull));   // run index, inclusive count
+            for (int off = 1; off < 64; off <<= 1) {
+                const int j = lane + off;
+                const bool same = j < 64 && __popcll(heads & ((2ull << j) - 1ull)) == rid;
+                if (!__any(same)) break;
+                float o[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) o[k] = __shfl_down(g4[k], off);
+                if (same) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) g4[k] += o[k];
+                }
+            }
+            if (ok && head) {
+                float* dst = dparams + 4 * P.vi;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) atomicAdd(dst + k, g4[k]);
+            }
         }
     }
     // work-group sums in float64: wave shuffles, then one value per wave
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < kAdjPart; ++k) {
         double x = (double)acc[k];
