@@ -83,6 +83,8 @@ def _load():
         "orc_render_taylor": (None, [_P, _P, _P, _D, _D, _P]),
         "orc_integrate_rounded": (_I64, [_P, _P, _P, _P, _D, _D, _I]),
         "orc_round_storage": (_D, [_D, _I]),
+        "orc_photo_loss_grad": (_D, [_P, _I, _P, _P, _P, _P, _P, _P, _I64, _P, _D, _D, _P, _P, _P, _P, _P]),
+        "orc_mean_color": (None, [_P, _I, _P, _P, _P, _P, _P, _P, _I64, _P, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -245,6 +247,39 @@ class OracleMap:
                                   _ptr(assoc), 1 if freeze else 0, _ptr(keys), nk, _ptr(dpsi),
                                   _ptr(dg), _ptr(dxi))
         return L, dpsi, dg, dxi
+
+    def photo_loss_grad(self, depths: np.ndarray, rgb: np.ndarray, cam, T0, xi, colors, delta: float,
+                        lam: float = 1.0, keys: Optional[np.ndarray] = None, want_grads: bool = True):
+        """Photometric keyframe loss against stored voxel colours (see
+        orc_photo_loss_grad).  Returns (loss per keyframe, dpsi, dcolor, dxi,
+        number of visible (voxel, keyframe) pairs)."""
+        K = depths.shape[0]
+        c = cam_struct(cam)
+        keys = self.keys() if keys is None else _c(keys, np.int32).reshape(-1, 3)
+        nk = len(keys)
+        loss = np.zeros(K)
+        dpsi = np.zeros((nk, 512)) if want_grads else None
+        dcol = np.zeros((nk, 512, 3)) if want_grads else None
+        dxi = np.zeros((K, 6)) if want_grads else None
+        nvis = C.c_int64()
+        _load().orc_photo_loss_grad(self._h, K, _ptr(_c(depths, np.float64)), _ptr(_c(rgb, np.float64)),
+                                    C.byref(c), _ptr(_c(T0, np.float64)), _ptr(_c(xi, np.float64)), _ptr(keys),
+                                    nk, _ptr(_c(colors, np.float64)), float(delta), float(lam), _ptr(loss),
+                                    _ptr(dpsi), _ptr(dcol), _ptr(dxi), C.byref(nvis))
+        return loss, dpsi, dcol, dxi, int(nvis.value)
+
+    def mean_color(self, depths: np.ndarray, rgb: np.ndarray, cam, T0, xi, keys: Optional[np.ndarray] = None):
+        """Eq. (21) colour of every surface voxel and its view count N_j."""
+        K = depths.shape[0]
+        c = cam_struct(cam)
+        keys = self.keys() if keys is None else _c(keys, np.int32).reshape(-1, 3)
+        nk = len(keys)
+        col = np.zeros((nk, 512, 3))
+        cnt = np.zeros((nk, 512))
+        _load().orc_mean_color(self._h, K, _ptr(_c(depths, np.float64)), _ptr(_c(rgb, np.float64)), C.byref(c),
+                               _ptr(_c(T0, np.float64)), _ptr(_c(xi, np.float64)), _ptr(keys), nk, _ptr(col),
+                               _ptr(cnt))
+        return col, cnt
 
     def render_taylor(self, cam, T, smin: float = 0.05, smax: float = 10.0) -> np.ndarray:
         out = np.zeros((cam.height, cam.width))

@@ -1003,3 +1003,196 @@ void orc_render_taylor(const OrcMap* M, const OrcCam* cam, const double* T, doub
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Photometric term over keyframes (joint refinement with colour).
+//
+// Surface point of voxel j (Sec. 4.2 Eq. (18)): p_j = v_j - psi_j gh_j, with
+// gh_j held fixed (the paper treats it as a constant direction while psi
+// changes).  Only voxels whose cell contains their surface point take part
+// ("voxels that actually contain surface points", Sec. 4.2):
+// max_k |psi_j gh_jk| <= v_s / 2, besides W > 0 and g != 0.
+// Visibility nu_ij: x = R_i^T (p_j - t_i) has z >= zmin, projects to
+// (u, v) = (fx x/z + cx, fy y/z + cy) with 0 <= u < width-1 and
+// 0 <= v < height-1 (bilinear support), the depth D of the nearest pixel
+// is valid with |z - D| <= T, and the surface faces the camera:
+// gh_j . (p_j - t_i) > 0 (gh points into the solid).
+// Residual per colour channel c against the voxel's stored colour rho_j:
+//   r = I_i^c(u, v) - rho_j^c   (bilinear image sample),
+// loss_i = lambda sum_{j visible} sum_c huber_delta(r).
+// Gradients: d/drho = -lambda rho'(r); with e = sum_c lambda rho'(r_c) dI^c/d(u,v)
+// and a = R_i (e . dpi/dx) (world frame): d/dpsi_j = -a . gh_j, and for a
+// left increment of T_i, [-a ; a x p_j]; dxi_i = Jl(xi_i)^T of that sum.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct PhotoSample {
+    double u, v, z, x[3];
+};
+
+bool photo_visible(const OrcCam& cam, const double* depth_i, const double* T, const double* p,
+                   const double* gh, double trunc, PhotoSample* S) {
+    double d[3] = {p[0] - T[3], p[1] - T[7], p[2] - T[11]};
+    for (int r = 0; r < 3; ++r) S->x[r] = T[r] * d[0] + T[4 + r] * d[1] + T[8 + r] * d[2];  // R^T d
+    S->z = S->x[2];
+    if (!(S->z >= cam.zmin)) return false;
+    S->u = cam.fx * S->x[0] / S->z + cam.cx;
+    S->v = cam.fy * S->x[1] / S->z + cam.cy;
+    if (!(S->u >= 0.0 && S->u < cam.width - 1 && S->v >= 0.0 && S->v < cam.height - 1)) return false;
+    int iu = (int)std::floor(S->u + 0.5), iv = (int)std::floor(S->v + 0.5);
+    double D = depth_i[(size_t)iv * cam.width + iu];
+    if (!(std::isfinite(D) && D > 0 && (float)D >= (float)cam.zmin && (float)D <= (float)cam.zmax)) return false;
+    if (!(std::fabs(S->z - D) <= trunc)) return false;
+    return gh[0] * d[0] + gh[1] * d[1] + gh[2] * d[2] > 0.0;
+}
+
+// Bilinear sample of an H x W x 3 image and its derivatives in u and v.
+void bilinear3(const double* img, const OrcCam& cam, double u, double v, double I[3], double dIu[3],
+               double dIv[3]) {
+    int u0 = (int)std::floor(u), v0 = (int)std::floor(v);
+    double a = u - u0, b = v - v0;
+    const double* p00 = img + 3 * ((size_t)v0 * cam.width + u0);
+    const double* p10 = p00 + 3;
+    const double* p01 = p00 + 3 * (size_t)cam.width;
+    const double* p11 = p01 + 3;
+    for (int c = 0; c < 3; ++c) {
+        I[c] = (1 - a) * (1 - b) * p00[c] + a * (1 - b) * p10[c] + (1 - a) * b * p01[c] + a * b * p11[c];
+        dIu[c] = (1 - b) * (p10[c] - p00[c]) + b * (p11[c] - p01[c]);
+        dIv[c] = (1 - a) * (p01[c] - p00[c]) + a * (p11[c] - p10[c]);
+    }
+}
+
+bool photo_surface(const Voxel& V, double vs, double gh[3]) {
+    double ng = std::sqrt(V.g[0] * V.g[0] + V.g[1] * V.g[1] + V.g[2] * V.g[2]);
+    if (!(V.W > 0.0) || !(ng > 0.0)) return false;
+    for (int k = 0; k < 3; ++k) gh[k] = V.g[k] / ng;
+    for (int k = 0; k < 3; ++k)
+        if (std::fabs(V.psi * gh[k]) > 0.5 * vs) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Photometric loss and gradients.  colors / dcolor: nkeys x 512 x 3 in the
+// order of `keys` (voxel lx + 8 ly + 64 lz); dpsi: nkeys x 512; all gradient
+// outputs optional (overwritten).  loss_kf: K values.  Returns the total.
+double orc_photo_loss_grad(const OrcMap* M, int K, const double* depth, const double* rgb, const OrcCam* cam,
+                           const double* T0, const double* xi, const int32_t* keys, int64_t nkeys,
+                           const double* colors, double delta, double lambda, double* loss_kf,
+                           double* dpsi, double* dcolor, double* dxi, int64_t* n_visible) {
+    const size_t npx = (size_t)cam->width * cam->height;
+    std::vector<double> T((size_t)12 * K), gl((size_t)6 * K, 0.0);
+    for (int i = 0; i < K; ++i) {
+        double E[12];
+        se3_exp(xi + 6 * i, E);
+        std::memcpy(&T[12 * i], T0 + 12 * i, 12 * sizeof(double));
+        compose_left(E, &T[12 * i]);
+        loss_kf[i] = 0.0;
+    }
+    if (dpsi) std::fill(dpsi, dpsi + nkeys * kBV, 0.0);
+    if (dcolor) std::fill(dcolor, dcolor + nkeys * kBV * 3, 0.0);
+    int64_t nvis = 0;
+    for (int64_t b = 0; b < nkeys; ++b) {
+        const Block* B = find_block(M, keys[3 * b], keys[3 * b + 1], keys[3 * b + 2]);
+        if (!B) continue;
+        for (int c = 0; c < kBV; ++c) {
+            const Voxel& V = B->v[c];
+            double gh[3];
+            if (!photo_surface(V, M->vs, gh)) continue;
+            int m[3] = {8 * keys[3 * b] + c % 8, 8 * keys[3 * b + 1] + (c / 8) % 8, 8 * keys[3 * b + 2] + c / 64};
+            double p[3];
+            for (int k = 0; k < 3; ++k) p[k] = M->vs * m[k] - V.psi * gh[k];
+            const double* rho = colors + 3 * (b * kBV + c);
+            for (int i = 0; i < K; ++i) {
+                const double* Ti = &T[12 * i];
+                PhotoSample S;
+                if (!photo_visible(*cam, depth + i * npx, Ti, p, gh, M->T, &S)) continue;
+                ++nvis;
+                double I[3], dIu[3], dIv[3];
+                bilinear3(rgb + 3 * i * npx, *cam, S.u, S.v, I, dIu, dIv);
+                double eu = 0, ev = 0;
+                for (int ch = 0; ch < 3; ++ch) {
+                    double r = I[ch] - rho[ch];
+                    loss_kf[i] += lambda * huber_rho(r, delta);
+                    double rp = lambda * huber_weight(r, delta) * r;
+                    if (dcolor) dcolor[3 * (b * kBV + c) + ch] -= rp;
+                    eu += rp * dIu[ch];
+                    ev += rp * dIv[ch];
+                }
+                // dL/dx (camera frame) through the projection, then world frame
+                double gx[3] = {eu * cam->fx / S.z, ev * cam->fy / S.z,
+                                -(eu * cam->fx * S.x[0] + ev * cam->fy * S.x[1]) / (S.z * S.z)};
+                double a[3];
+                for (int r = 0; r < 3; ++r) a[r] = Ti[4 * r] * gx[0] + Ti[4 * r + 1] * gx[1] + Ti[4 * r + 2] * gx[2];
+                if (dpsi) dpsi[b * kBV + c] -= a[0] * gh[0] + a[1] * gh[1] + a[2] * gh[2];
+                double* g6 = &gl[6 * i];
+                g6[0] -= a[0];
+                g6[1] -= a[1];
+                g6[2] -= a[2];
+                g6[3] += a[1] * p[2] - a[2] * p[1];
+                g6[4] += a[2] * p[0] - a[0] * p[2];
+                g6[5] += a[0] * p[1] - a[1] * p[0];
+            }
+        }
+    }
+    if (dxi) {
+        for (int i = 0; i < K; ++i) {
+            double Jl[36];
+            se3_left_jacobian(xi + 6 * i, Jl);
+            for (int q = 0; q < 6; ++q) {
+                double s = 0;
+                for (int k = 0; k < 6; ++k) s += Jl[6 * k + q] * gl[6 * i + k];
+                dxi[6 * i + q] = s;
+            }
+        }
+    }
+    if (n_visible) *n_visible = nvis;
+    double L = 0;
+    for (int i = 0; i < K; ++i) L += loss_kf[i];
+    return L;
+}
+
+// Mean colour of each surface voxel over the keyframes that see it
+// (Sec. 4.2 Eq. (21)); count_out = N_j.  Voxels seen by none get 0.
+void orc_mean_color(const OrcMap* M, int K, const double* depth, const double* rgb, const OrcCam* cam,
+                    const double* T0, const double* xi, const int32_t* keys, int64_t nkeys, double* colors_out,
+                    double* count_out) {
+    const size_t npx = (size_t)cam->width * cam->height;
+    std::vector<double> T((size_t)12 * K);
+    for (int i = 0; i < K; ++i) {
+        double E[12];
+        se3_exp(xi + 6 * i, E);
+        std::memcpy(&T[12 * i], T0 + 12 * i, 12 * sizeof(double));
+        compose_left(E, &T[12 * i]);
+    }
+    std::fill(colors_out, colors_out + nkeys * kBV * 3, 0.0);
+    std::fill(count_out, count_out + nkeys * kBV, 0.0);
+    for (int64_t b = 0; b < nkeys; ++b) {
+        const Block* B = find_block(M, keys[3 * b], keys[3 * b + 1], keys[3 * b + 2]);
+        if (!B) continue;
+        for (int c = 0; c < kBV; ++c) {
+            const Voxel& V = B->v[c];
+            double gh[3];
+            if (!photo_surface(V, M->vs, gh)) continue;
+            int m[3] = {8 * keys[3 * b] + c % 8, 8 * keys[3 * b + 1] + (c / 8) % 8, 8 * keys[3 * b + 2] + c / 64};
+            double p[3];
+            for (int k = 0; k < 3; ++k) p[k] = M->vs * m[k] - V.psi * gh[k];
+            double sum[3] = {0, 0, 0}, n = 0;
+            for (int i = 0; i < K; ++i) {
+                PhotoSample S;
+                if (!photo_visible(*cam, depth + i * npx, &T[12 * i], p, gh, M->T, &S)) continue;
+                double I[3], dIu[3], dIv[3];
+                bilinear3(rgb + 3 * i * npx, *cam, S.u, S.v, I, dIu, dIv);
+                for (int ch = 0; ch < 3; ++ch) sum[ch] += I[ch];
+                n += 1;
+            }
+            count_out[b * kBV + c] = n;
+            if (n > 0)
+                for (int ch = 0; ch < 3; ++ch) colors_out[3 * (b * kBV + c) + ch] = sum[ch] / n;
+        }
+    }
+}
+
+}  // extern "C"

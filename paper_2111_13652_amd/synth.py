@@ -33,6 +33,7 @@ __all__ = [
     "Camera", "Scene", "sphere_scene", "room_scene", "render_depth",
     "depth_noise_sigma", "add_depth_noise", "smooth_trajectory",
     "look_at", "perturb_pose", "rotation_about", "Stream", "make_stream",
+    "render_ids", "Albedo", "make_albedo", "surface_normal", "shade", "render_rgbd", "make_rgbd_stream",
     "CONFIG_SPHERE", "CONFIG_ROOM", "CONFIG_ROOM_HD",
 ]
 
@@ -228,26 +229,120 @@ def _screen_rect(cam: Camera, R, t, centre, radius):
     return u0, u1, v0, v1
 
 
-def render_depth(scene: Scene, cam: Camera, T_wc: np.ndarray) -> np.ndarray:
-    """Exact noiseless z-depth (float64, inf where nothing is hit)."""
+def render_ids(scene: Scene, cam: Camera, T_wc: np.ndarray):
+    """Exact noiseless z-depth (float64, inf where nothing is hit) and the
+    index of the surface hit: 0 the room, 1 + i sphere i, 1 + Ns + j box j,
+    -1 nothing."""
     T = np.asarray(T_wc, np.float64).reshape(3, 4)
     R, t = T[:, :3], T[:, 3]
     rays = cam.rays()
     dirs = rays @ R.T  # world directions; the camera ray has z = 1
     best = np.full(dirs.shape[:-1], np.inf)
+    obj = np.full(dirs.shape[:-1], -1, np.int32)
     if scene.room is not None:
         best = _ray_room_exit(t, dirs.reshape(-1, 3), scene.room).reshape(best.shape)
+        obj[np.isfinite(best)] = 0
     prims = [(s, _ray_sphere, s[:3], s[3]) for s in scene.spheres]
     prims += [(b, _ray_box, b[:3], float(np.linalg.norm(b[3:6]))) for b in scene.boxes]
-    for p, fn, c, r in prims:
+    for idx, (p, fn, c, r) in enumerate(prims):
         rect = _screen_rect(cam, R, t, c, r)
         if rect is None:
             continue
         u0, u1, v0, v1 = rect
         sub = dirs[v0:v1, u0:u1].reshape(-1, 3)
         hit = fn(t, sub, p).reshape(v1 - v0, u1 - u0)
-        np.minimum(best[v0:v1, u0:u1], hit, out=best[v0:v1, u0:u1])
-    return best  # ray parameter == z-depth because the camera ray has z = 1
+        closer = hit < best[v0:v1, u0:u1]
+        best[v0:v1, u0:u1] = np.where(closer, hit, best[v0:v1, u0:u1])
+        obj[v0:v1, u0:u1] = np.where(closer, idx + 1, obj[v0:v1, u0:u1])
+    return best, obj  # ray parameter == z-depth because the camera ray has z = 1
+
+
+def render_depth(scene: Scene, cam: Camera, T_wc: np.ndarray) -> np.ndarray:
+    """Exact noiseless z-depth (float64, inf where nothing is hit)."""
+    return render_ids(scene, cam, T_wc)[0]
+
+
+# --------------------------------------------------------------------------
+# Colour: per-object smooth albedo fields with Lambertian shading
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class Albedo:
+    """Per-object albedo a_c(p) = base_c + amp * mean_m sin(k_m . p + phase_mc),
+    clipped to [0, 1]; objects indexed as by ``render_ids``."""
+    base: np.ndarray     # (n_obj, 3)
+    amp: np.ndarray      # (n_obj,)
+    k: np.ndarray        # (n_obj, 3 terms, 3) wave vectors, rad/m
+    phase: np.ndarray    # (n_obj, 3 terms, 3 channels)
+    light: np.ndarray    # (3,) unit direction towards the light
+    ambient: float = 0.3
+
+
+def make_albedo(scene: Scene, seed: int, k_range=(10.0, 40.0)) -> Albedo:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = 1 + len(scene.spheres) + len(scene.boxes)
+    dirs = rng.standard_normal((n, 3, 3))
+    dirs /= np.linalg.norm(dirs, axis=-1, keepdims=True)
+    k = dirs * rng.uniform(*k_range, size=(n, 3, 1))
+    light = np.array([0.3, -0.5, 0.8])
+    return Albedo(base=rng.uniform(0.3, 0.7, (n, 3)), amp=rng.uniform(0.1, 0.3, n), k=k,
+                  phase=rng.uniform(0.0, 2 * math.pi, (n, 3, 3)), light=light / np.linalg.norm(light))
+
+
+def surface_normal(scene: Scene, p: np.ndarray, obj: np.ndarray) -> np.ndarray:
+    """Unit normal pointing into free space at surface points ``p`` (N, 3)
+    of objects ``obj`` (N,) (0 = room wall, as ``render_ids``)."""
+    n = np.zeros_like(p)
+    ns = len(scene.spheres)
+    room = obj == 0
+    if room.any() and scene.room is not None:
+        lo, hi = scene.room
+        q = p[room]
+        d = np.concatenate([q - lo, hi - q], axis=1)          # distances to the 6 walls
+        w = np.argmin(np.abs(d), axis=1)
+        nr = np.zeros_like(q)
+        nr[np.arange(len(q)), w % 3] = np.where(w < 3, 1.0, -1.0)   # into the room
+        n[room] = nr
+    for i, sph in enumerate(scene.spheres):
+        m = obj == 1 + i
+        if m.any():
+            d = p[m] - sph[:3]
+            n[m] = d / np.linalg.norm(d, axis=1, keepdims=True)
+    for j, b in enumerate(scene.boxes):
+        m = obj == 1 + ns + j
+        if m.any():
+            c, h, yaw = b[:3], b[3:6], b[6]
+            cs, sn = math.cos(yaw), math.sin(yaw)
+            d = p[m] - c
+            loc = np.stack([cs * d[:, 0] + sn * d[:, 1], -sn * d[:, 0] + cs * d[:, 1], d[:, 2]], 1)
+            face = np.argmax(np.abs(loc) - h, axis=1)
+            nl = np.zeros_like(loc)
+            nl[np.arange(len(loc)), face] = np.sign(loc[np.arange(len(loc)), face])
+            n[m] = np.stack([cs * nl[:, 0] - sn * nl[:, 1], sn * nl[:, 0] + cs * nl[:, 1], nl[:, 2]], 1)
+    return n
+
+
+def shade(alb: Albedo, scene: Scene, p: np.ndarray, obj: np.ndarray) -> np.ndarray:
+    """Lambertian colour (N, 3) of surface points ``p`` on objects ``obj``."""
+    k = alb.k[obj]                                             # (N, 3, 3)
+    arg = np.einsum("nmd,nd->nm", k, p)[:, :, None] + alb.phase[obj]
+    a = alb.base[obj] + alb.amp[obj, None] * np.mean(np.sin(arg), axis=1)
+    n = surface_normal(scene, p, obj)
+    lam = alb.ambient + (1.0 - alb.ambient) * np.maximum(0.0, n @ alb.light)
+    return np.clip(a, 0.0, 1.0) * lam[:, None]
+
+
+def render_rgbd(scene: Scene, cam: Camera, T_wc: np.ndarray, alb: Albedo):
+    """Exact z-depth (float64, inf = no hit) and noiseless colour (H, W, 3)
+    float32 in [0, 1] (0 where nothing is hit)."""
+    z, obj = render_ids(scene, cam, T_wc)
+    T = np.asarray(T_wc, np.float64).reshape(3, 4)
+    hit = np.isfinite(z)
+    rgb = np.zeros(z.shape + (3,), np.float64)
+    if hit.any():
+        x = cam.rays()[hit] * z[hit][:, None]                  # camera frame
+        p = x @ T[:, :3].T + T[:, 3]
+        rgb[hit] = shade(alb, scene, p, obj[hit])
+    return z, rgb.astype(np.float32)
 
 
 def depth_noise_sigma(z: np.ndarray) -> np.ndarray:
@@ -382,6 +477,8 @@ class Stream:
     depth: np.ndarray      # (F, H, W) float32, 0 = invalid
     poses: np.ndarray      # (F, 3, 4) float64 ground-truth camera-to-world
     scene: Scene
+    rgb: Optional[np.ndarray] = None      # (F, H, W, 3) float32 colour, when rendered
+    albedo: Optional[Albedo] = None
 
 
 def make_stream(cam: Camera, n_frames: int, scene_seed: int = 1, traj_seed: int = 2,
@@ -401,3 +498,28 @@ def make_stream(cam: Camera, n_frames: int, scene_seed: int = 1, traj_seed: int 
             z = add_depth_noise(z, np.random.Generator(np.random.PCG64(kids[i])))
         depth[i] = to_depth_image(z, cam)
     return Stream(cam=cam, depth=depth, poses=poses, scene=scene)
+
+
+def make_rgbd_stream(cam: Camera, n_frames: int, scene_seed: int = 1, traj_seed: int = 2,
+                     noise_seed: Optional[int] = 3, albedo_seed: int = 4, color_noise: float = 0.005,
+                     n_objects: int = 20) -> Stream:
+    """The room stream with colour: the depth exactly as ``make_stream`` (same
+    seeds give the same depth), plus Lambertian colour of seeded per-object
+    albedo fields with Gaussian noise ``color_noise`` (second child seed of
+    each frame), clipped to [0, 1]."""
+    poses = smooth_trajectory(traj_seed, n_frames)
+    scene = room_scene(scene_seed, poses[:, :, 3], n_objects=n_objects)
+    alb = make_albedo(scene, albedo_seed)
+    kids = np.random.SeedSequence(noise_seed).spawn(n_frames) if noise_seed is not None else None
+    depth = np.empty((n_frames, cam.height, cam.width), np.float32)
+    rgb = np.empty((n_frames, cam.height, cam.width, 3), np.float32)
+    for i in range(n_frames):
+        z, col = render_rgbd(scene, cam, poses[i], alb)
+        if kids is not None:
+            z = add_depth_noise(z, np.random.Generator(np.random.PCG64(kids[i])))
+            g = np.random.Generator(np.random.PCG64(kids[i].spawn(1)[0]))
+            col = np.clip(col + g.standard_normal(col.shape).astype(np.float32) * np.float32(color_noise),
+                          0.0, 1.0)
+        depth[i] = to_depth_image(z, cam)
+        rgb[i] = col
+    return Stream(cam=cam, depth=depth, poses=poses, scene=scene, rgb=rgb, albedo=alb)
