@@ -254,6 +254,56 @@ int gsdf_keyframe_backward(const gsdf_map* map, const float* depth_dev, int32_t 
                            void* scratch_dev, size_t scratch_bytes, void* stream);
 
 /* ---------------------------------------------------------------------- */
+/* Photometric term (joint refinement with colour)                         */
+/* ---------------------------------------------------------------------- */
+
+/* Surface point of voxel j (Sec. 4.2 Eq. (18)): p_j = v_j - psi_j g^_j with
+ * g^_j = g_j/|g_j| held fixed while psi_j changes; voxels with W > 0, g != 0
+ * whose cell contains p_j (max_k |psi_j g^_jk| <= v_s/2) take part.
+ * Keyframe i sees p_j when x = R_i^T (p_j - t_i) has z >= zmin, projects
+ * inside [0, width-1) x [0, height-1), the nearest pixel's depth D is valid
+ * with |z - D| <= T, and g^_j . (p_j - t_i) > 0.  rgb_dev: K x H x W x 3
+ * float32 colour (device), sampled bilinearly.  colors: param_blocks x 512
+ * x 3 float32 per-voxel colour rho_j in the params' slot/voxel order.
+ * T_i = exp(xi_i^) T0_i as for gsdf_keyframe_loss. */
+
+/* Scratch bytes of the photometric calls. */
+size_t gsdf_photometric_scratch_bytes(int64_t param_blocks, int32_t n_keyframes);
+
+/* L_i = weight * sum_{j seen by i} sum_c huber_delta(I_i^c(pi(x)) - rho_j^c)
+ * into loss_dev (K float64); count_dev (optional, K float64): (voxel,
+ * keyframe) pairs seen. */
+int gsdf_photometric_loss(const gsdf_map* map, const float* depth_dev, const float* rgb_dev,
+                          int32_t n_keyframes, const gsdf_camera* cam, const double* T0_dev,
+                          const double* xi_dev, const float* params_dev, const float* colors_dev,
+                          int64_t param_blocks, float huber_delta, float weight, double* loss_dev,
+                          double* count_dev, void* scratch_dev, size_t scratch_bytes, void* stream);
+
+/* Adjoint of gsdf_photometric_loss, recomputing every sample; with
+ * s_i = grad_loss_dev[i]: dparams[j].psi += sum_i s_i dL_i/dpsi_j (g^ held
+ * fixed, so the g components get nothing), dcolors[j] += sum_i s_i
+ * dL_i/drho_j, dxi_dev[i] = Jl(xi_i)^T (left-increment gradient of s_i L_i)
+ * (overwritten); loss_dev optional.  Each voxel's entries are written by
+ * one thread (no atomics); call after, not concurrently with, other writers
+ * of dparams. */
+int gsdf_photometric_backward(const gsdf_map* map, const float* depth_dev, const float* rgb_dev,
+                              int32_t n_keyframes, const gsdf_camera* cam, const double* T0_dev,
+                              const double* xi_dev, const float* params_dev, const float* colors_dev,
+                              int64_t param_blocks, float huber_delta, float weight,
+                              const float* grad_loss_dev, float* dparams_dev, float* dcolors_dev,
+                              double* dxi_dev, double* loss_dev, void* scratch_dev,
+                              size_t scratch_bytes, void* stream);
+
+/* Mean colour of each taking-part voxel over the keyframes that see it
+ * (Sec. 4.2 Eq. (21)): colors_out_dev (param_blocks x 512 x 3 float32, 0
+ * where no keyframe sees the voxel) and count_out_dev (optional,
+ * param_blocks x 512 float32, N_j). */
+int gsdf_mean_color(const gsdf_map* map, const float* depth_dev, const float* rgb_dev, int32_t n_keyframes,
+                    const gsdf_camera* cam, const double* T0_dev, const double* xi_dev,
+                    const float* params_dev, int64_t param_blocks, float* colors_out_dev,
+                    float* count_out_dev, void* scratch_dev, size_t scratch_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Inspection, import (used for parity checks and checkpoints)             */
 /* ---------------------------------------------------------------------- */
 
@@ -293,6 +343,7 @@ enum {
     GSDF_K_NORMALS = 4,
     GSDF_K_BACKWARD = 5,
     GSDF_K_LOSS = 6,
+    GSDF_K_PHOTOMETRIC = 7,
     GSDF_K_COUNT = 16
 };
 

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libgsdf.so")
 
 OK, EINVAL, ECAPACITY, EHIP, ENOTPD, ELOST = 0, -1, -2, -3, -4, -5
 FP32, BF16, FP16 = 0, 1, 2
-K_ALLOCATE, K_INTEGRATE, K_TRACK, K_PYRAMID, K_NORMALS, K_BACKWARD, K_LOSS = 0, 1, 2, 3, 4, 5, 6
+K_ALLOCATE, K_INTEGRATE, K_TRACK, K_PYRAMID, K_NORMALS, K_BACKWARD, K_LOSS, K_PHOTOMETRIC = range(8)
 
 
 class MapDesc(C.Structure):
@@ -73,6 +73,13 @@ _SIGNATURES = {
                                 C.c_float, _P, _I32, _P, _P, _P, _SZ, _P]),
     "gsdf_keyframe_backward": (_I, [C.POINTER(Map), _P, _I32, C.POINTER(Camera), _P, _P, _P, C.c_int64,
                                     C.c_float, _P, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
+    "gsdf_photometric_scratch_bytes": (_SZ, [C.c_int64, _I32]),
+    "gsdf_photometric_loss": (_I, [C.POINTER(Map), _P, _P, _I32, C.POINTER(Camera), _P, _P, _P, _P, C.c_int64,
+                                   C.c_float, C.c_float, _P, _P, _P, _SZ, _P]),
+    "gsdf_photometric_backward": (_I, [C.POINTER(Map), _P, _P, _I32, C.POINTER(Camera), _P, _P, _P, _P,
+                                       C.c_int64, C.c_float, C.c_float, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "gsdf_mean_color": (_I, [C.POINTER(Map), _P, _P, _I32, C.POINTER(Camera), _P, _P, _P, C.c_int64, _P, _P,
+                             _P, _SZ, _P]),
     "gsdf_timing_enable": (_I, [_I32]),
     "gsdf_timing_read": (_I, [_I32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "gsdf_status_string": (C.c_char_p, [_I32]),

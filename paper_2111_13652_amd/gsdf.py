@@ -306,33 +306,176 @@ class KeyframeLoss(torch.autograd.Function):
                 None, None, None, None, None, None, None)
 
 
+def adjoint_se3(T: torch.Tensor) -> torch.Tensor:
+    """Adjoint matrices (K, 6, 6) of poses (K, 3, 4) for twists (rho, phi):
+    exp((Ad(T) xi)^) = T exp(xi^) T^-1.  The refinement drivers take their
+    pose variables in each camera's own frame (rotation about the camera
+    centre) and hand Ad(T0) xi to the kernels, which compose on the left."""
+    R = T[:, :, :3]
+    t = T[:, :, 3]
+    z = torch.zeros_like(t[:, 0])
+    th = torch.stack([torch.stack([z, -t[:, 2], t[:, 1]], -1), torch.stack([t[:, 2], z, -t[:, 0]], -1),
+                      torch.stack([-t[:, 1], t[:, 0], z], -1)], -2)
+    A = torch.zeros((T.shape[0], 6, 6), dtype=T.dtype, device=T.device)
+    A[:, :3, :3] = R
+    A[:, :3, 3:] = th @ R
+    A[:, 3:, 3:] = R
+    return A
+
+
 def refine_keyframes(gmap: GsdfMap, depth: torch.Tensor, cam, T0: torch.Tensor, steps: int = 50,
-                     delta: float = 0.01, lr_pose: float = 1e-3, lr_geom: float = 0.0,
+                     delta: float = 0.01, lr_pose: float = 4e-3, lr_geom: float = 0.0,
                      params: Optional[torch.Tensor] = None, write_back: bool = False):
-    """Joint refinement of keyframe poses and (if lr_geom > 0) voxel
-    parameters by Adam on the summed keyframe loss.  Returns (poses (K,3,4),
-    params, losses per step).  With write_back the refined parameters are
-    imported into the map."""
+    """Refinement of keyframe poses and (if lr_geom > 0) voxel parameters by
+    Adam on the summed keyframe loss, the pose variables taken in each
+    camera's frame, learning rates on a cosine schedule.  Returns (poses
+    (K,3,4), params, losses per step).  With write_back the refined
+    parameters are imported into the map."""
     K = depth.shape[0]
     if params is None:
         params = gmap.export_params()
     params = params.detach().clone().requires_grad_(lr_geom > 0)
-    xi = torch.zeros((K, 6), dtype=torch.float64, device=depth.device, requires_grad=True)
-    groups = [{"params": [xi], "lr": lr_pose}]
+    ad = adjoint_se3(T0)
+    xc = torch.zeros((K, 6), dtype=torch.float64, device=depth.device, requires_grad=True)
+    groups = [{"params": [xc], "lr": lr_pose}]
     if lr_geom > 0:
         groups.append({"params": [params], "lr": lr_geom})
     opt = torch.optim.Adam(groups)
+    sched = torch.optim.lr_scheduler.CosineAnnealingLR(opt, steps)
     losses = []
     for _ in range(steps):
         opt.zero_grad(set_to_none=True)
+        xi = (ad @ xc.unsqueeze(-1)).squeeze(-1)
         loss = KeyframeLoss.apply(params, xi, gmap, depth, cam, T0, delta).sum()
         loss.backward()
         opt.step()
+        sched.step()
         losses.append(loss.detach())
-    poses = compose_left(xi.detach(), T0)
+    poses = compose_left((ad @ xc.detach().unsqueeze(-1)).squeeze(-1), T0)
     if write_back:
         gmap.import_params(params.detach())
     return poses, params.detach(), torch.stack(losses).cpu().numpy()
+
+
+def _photo_args(gmap: GsdfMap, depth, rgb, cam, T0, xi, params, colors):
+    c, K = _kf_args(gmap, depth, cam, T0, xi, params, None)
+    _need(rgb, torch.float32, (K, c.height, c.width, 3), "rgb")
+    if colors is not None:
+        _need(colors, torch.float32, (params.shape[0], 512, 3), "colors")
+    key = ("photo", int(params.shape[0]), K)
+    if key not in gmap._scratch:
+        n = _lib.load().gsdf_photometric_scratch_bytes(int(params.shape[0]), K)
+        if n == 0:
+            raise ValueError("invalid keyframe count for the photometric term")
+        gmap._scratch[key] = torch.empty(int(n), dtype=torch.uint8, device=gmap.device)
+    return c, K, gmap._scratch[key]
+
+
+def mean_color(gmap: GsdfMap, params: torch.Tensor, xi: torch.Tensor, depth: torch.Tensor, rgb: torch.Tensor,
+               cam, T0: torch.Tensor):
+    """Mean colour of every surface voxel over the keyframes that see it
+    (Eq. (21)) and its view count: ((n, 512, 3), (n, 512)) float32."""
+    c, K, scratch = _photo_args(gmap, depth, rgb, cam, T0, xi, params, None)
+    n = int(params.shape[0])
+    col = torch.empty((n, 512, 3), dtype=torch.float32, device=depth.device)
+    cnt = torch.empty((n, 512), dtype=torch.float32, device=depth.device)
+    _lib.check(_lib.load().gsdf_mean_color(C.byref(gmap._map), _ptr(depth), _ptr(rgb), K, C.byref(c), _ptr(T0),
+                                            _ptr(xi.detach().contiguous()), _ptr(params.detach().contiguous()), n,
+                                            _ptr(col), _ptr(cnt), _ptr(scratch), scratch.numel(), _stream()),
+               "mean_color")
+    return col, cnt
+
+
+class PhotometricLoss(torch.autograd.Function):
+    """L_i = weight * sum_j sum_c huber_delta(I_i^c(pi(R_i^T (v_j - psi_j g^_j - t_i))) - rho_j^c)
+    over the surface voxels keyframe i sees (Eq. (18) surface point, g^
+    held fixed); differentiable in psi (params[..., 0]), the voxel colours
+    rho and the twists xi.
+
+        loss = PhotometricLoss.apply(params, colors, xi, gmap, depth, rgb, cam, T0, delta, weight)
+    """
+
+    @staticmethod
+    def forward(ctx, params, colors, xi, gmap, depth, rgb, cam, T0, delta=0.1, weight=1.0):
+        c, K, scratch = _photo_args(gmap, depth, rgb, cam, T0, xi, params, colors)
+        loss = torch.empty(K, dtype=torch.float64, device=depth.device)
+        _lib.check(_lib.load().gsdf_photometric_loss(
+            C.byref(gmap._map), _ptr(depth), _ptr(rgb), K, C.byref(c), _ptr(T0), _ptr(xi), _ptr(params),
+            _ptr(colors), int(params.shape[0]), float(delta), float(weight), _ptr(loss), None, _ptr(scratch),
+            scratch.numel(), _stream()), "photometric_loss")
+        ctx.save_for_backward(params, colors, xi)
+        ctx.rest = (gmap, depth, rgb, cam, T0, delta, weight)
+        return loss
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        params, colors, xi = ctx.saved_tensors
+        gmap, depth, rgb, cam, T0, delta, weight = ctx.rest
+        c, K, scratch = _photo_args(gmap, depth, rgb, cam, T0, xi, params, colors)
+        gl = grad_loss.to(torch.float32).contiguous()
+        dparams = torch.zeros_like(params)
+        dcolors = torch.zeros_like(colors)
+        dxi = torch.empty_like(xi)
+        _lib.check(_lib.load().gsdf_photometric_backward(
+            C.byref(gmap._map), _ptr(depth), _ptr(rgb), K, C.byref(c), _ptr(T0), _ptr(xi), _ptr(params),
+            _ptr(colors), int(params.shape[0]), float(delta), float(weight), _ptr(gl), _ptr(dparams),
+            _ptr(dcolors), _ptr(dxi), None, _ptr(scratch), scratch.numel(), _stream()), "photometric_backward")
+        return (dparams if ctx.needs_input_grad[0] else None, dcolors if ctx.needs_input_grad[1] else None,
+                dxi if ctx.needs_input_grad[2] else None, None, None, None, None, None, None, None)
+
+
+def refine_joint(gmap: GsdfMap, depth: torch.Tensor, rgb: torch.Tensor, cam, T0: torch.Tensor,
+                 steps: int = 50, delta: float = 0.01, photo_delta: float = 0.1, photo_weight: float = 0.01,
+                 lr_psi: float = 2e-5, lr_color: float = 1e-2, pose_solver: str = "gn", lr_pose: float = 4e-3,
+                 write_back: bool = True):
+    """Joint refinement over keyframes of the voxel distances and gradients,
+    the voxel colours and the keyframe poses on the sum of the SDF keyframe
+    loss and the photometric loss.  Each step takes an Adam step on the
+    voxel parameters and colours (gradients from both adjoint kernels), then
+    updates the poses: ``pose_solver="gn"`` writes the parameters into the
+    map (rounded to its storage format) and takes one Gauss-Newton
+    iteration of the tracking kernel per keyframe on the updated map;
+    ``"adam"`` moves camera-frame pose variables by Adam on the joint loss.
+    Colours start from the Eq. (21) mean at the initial poses.  The default
+    photometric weight (delta / photo_delta)^2 prices a residual at either
+    Huber threshold equally; learning rates decay on a cosine schedule.
+    Returns (poses (K,3,4), params, colours, losses)."""
+    K = depth.shape[0]
+    params = gmap.export_params().detach().clone()
+    T = T0.detach().clone()
+    ad = adjoint_se3(T0)
+    xc = torch.zeros((K, 6), dtype=torch.float64, device=depth.device)
+    colors, _ = mean_color(gmap, params, xc, depth, rgb, cam, T)
+    params.requires_grad_(True)
+    colors.requires_grad_(True)
+    groups = [{"params": [params], "lr": lr_psi}, {"params": [colors], "lr": lr_color}]
+    if pose_solver == "adam":
+        xc.requires_grad_(True)
+        groups.append({"params": [xc], "lr": lr_pose})
+    elif pose_solver != "gn":
+        raise ValueError("pose_solver must be 'gn' or 'adam'")
+    opt = torch.optim.Adam(groups)
+    sched = torch.optim.lr_scheduler.CosineAnnealingLR(opt, steps)
+    losses = []
+    for _ in range(steps):
+        opt.zero_grad(set_to_none=True)
+        xi = (ad @ xc.unsqueeze(-1)).squeeze(-1)
+        loss = (KeyframeLoss.apply(params, xi, gmap, depth, cam, T, delta).sum()
+                + PhotometricLoss.apply(params, colors, xi, gmap, depth, rgb, cam, T, photo_delta,
+                                        photo_weight).sum())
+        loss.backward()
+        opt.step()
+        sched.step()
+        losses.append(loss.detach())
+        if pose_solver == "gn":
+            gmap.import_params(params.detach())
+            for i in range(K):
+                gmap.track(depth[i], cam, T[i], levels=1, iters=(1,), delta=delta)
+    if pose_solver == "adam":
+        T = compose_left((ad @ xc.detach().unsqueeze(-1)).squeeze(-1), T0)
+    if write_back:
+        gmap.import_params(params.detach())
+    return T, params.detach(), colors.detach(), torch.stack(losses).cpu().numpy()
 
 
 def compose_left(xi: torch.Tensor, T0: torch.Tensor) -> torch.Tensor:

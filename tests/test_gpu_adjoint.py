@@ -157,14 +157,14 @@ def test_refinement_recovers_keyframe_poses(torch_mod, room_stream):
     D = dev(st.depth[list(idx)])
     before = [pose_diff(T0[i], st.poses[f]) for i, f in enumerate(idx)]
     log("case: pose refinement of 5 keyframes; initial errors", before)
-    poses, _, losses = refine_keyframes(G, D, st.cam, dev(T0), steps=150, lr_pose=1e-3)
+    poses, _, losses = refine_keyframes(G, D, st.cam, dev(T0), steps=150)
     P = poses.cpu().numpy()
     after = [pose_diff(P[i], st.poses[f]) for i, f in enumerate(idx)]
     log("  loss", losses[0], "->", losses[-1], "; final errors", after)
     assert losses[-1] < 0.5 * losses[0]
     for (ra, ta) in after:
         assert ra < np.deg2rad(0.1) and ta < 2e-3
-    _, params, jl = refine_keyframes(G, D, st.cam, dev(T0), steps=150, lr_pose=1e-3, lr_geom=1e-4)
+    _, params, jl = refine_keyframes(G, D, st.cam, dev(T0), steps=150, lr_geom=1e-4)
     log("  joint loss", jl[0], "->", jl[-1])
     assert jl[-1] < losses[-1]
     assert G.status_flags() == []
