@@ -29,7 +29,6 @@ constexpr int kNE = 30;          // 21 H + 6 b + energy + used + valid
 constexpr int kPartStride = 32;  // doubles per work-group partial
 constexpr int kTrackBlock = 256;
 constexpr int kMaxGroups = 2048;
-constexpr int kPixPerThread = 2;
 constexpr unsigned kSpinLimit = 1u << 24;
 
 struct TrackLevel {
@@ -106,10 +105,20 @@ struct Kahan {
 // camera centre and t_r = t - v_s m_c (|t_r| < v_s), so no float32 value
 // holds an absolute coordinate at the voxel association; sums are
 // compensated (Kahan) float32.  Only the pose itself is float64.
+//
+// A thread takes its pixels kTrackBatch at a time and issues each stage's
+// loads for the whole batch before using any of them (depths, then the
+// first hash probe of each, then weight and voxel record together), so a
+// batch costs three dependent memory round trips instead of four per
+// pixel.  Hash collisions fall back to the probing loop.
+constexpr int kTrackBatch = 3;
+
 template <int STORAGE>
 __device__ inline void accumulate(const MapView& M, const TrackLevel& L, const TrackArgs& a,
-                                  const double* pose, int first, int stride, float acc[kNE], float cmp[kNE]) {
+                                  const double* pose, int first, int stride, const float* Dpre, float acc[kNE],
+                                  float cmp[kNE]) {
     constexpr bool kPrecision = STORAGE != GSDF_FP32;
+    constexpr int B = kTrackBatch;
     Kahan ks[kNE];
 #pragma unroll
     for (int k = 0; k < kNE; ++k) acc[k] = 0.0f;
@@ -135,68 +144,146 @@ __device__ inline void accumulate(const MapView& M, const TrackLevel& L, const T
     const float ifxf = (float)L.ifx, ifyf = (float)L.ify, cxf = (float)L.cx, cyf = (float)L.cy;
 
     const int N = L.W * L.H;
-    for (int i = first; i < N; i += stride) {
-        const float D = L.depth[i];
-        if (!depth_ok(D, a.zmin, a.zmax)) continue;
-        if (kPrecision) ks[29].add(1.0f); else acc[29] += 1.0f;
-        const int v = i / L.W;
-        const int u = i - v * L.W;
-        int m[3];
-        float qr[3], qf[3];
-        if (!kPrecision) {
-            const double Dd = (double)D;
-            const double x0 = Dd * (((double)u - L.cx) * L.ifx);
-            const double x1 = Dd * (((double)v - L.cy) * L.ify);
+    for (int base = first; base < N; base += B * stride) {
+        // ---- stage 1: depths (preloaded for the first batch when given)
+        float D[B];
 #pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                const double q = R[3 * r] * x0 + R[3 * r + 1] * x1 + R[3 * r + 2] * Dd + t[r];
-                m[r] = (int)floor(q * a.inv_vs + 0.5);
-                qr[r] = (float)(q - a.vs * (double)m[r]);
-                qf[r] = (float)q;
-            }
-        } else {
-            const float x0 = D * (((float)u - cxf) * ifxf);
-            const float x1 = D * (((float)v - cyf) * ifyf);
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                const float qc = Rf[3 * r] * x0 + Rf[3 * r + 1] * x1 + Rf[3 * r + 2] * D + trf[r];
-                const int dm = (int)floorf(qc * ivsf + 0.5f);
-                m[r] = mc[r] + dm;
-                qr[r] = qc - vsf * (float)dm;
-                qf[r] = qc + mcf[r];
-            }
+        for (int j = 0; j < B; ++j) {
+            const int i = base + j * stride;
+            D[j] = (Dpre && base == first) ? Dpre[j * kTrackBlock + threadIdx.x] : (i < N ? L.depth[i] : 0.0f);
         }
-        const int32_t slot = hash_find(M, block_of(m[0]), block_of(m[1]), block_of(m[2]));
-        if (slot < 0) continue;
-        const int64_t vi = (int64_t)slot * kBlockVoxels + morton9(m[0] & 7, m[1] & 7, m[2] & 7);
-        float psi, gh[3];
-        if (!read_voxel<STORAGE>(M, vi, &psi, gh)) continue;
-        const float r = psi + gh[0] * qr[0] + gh[1] * qr[1] + gh[2] * qr[2];
-        const float J[6] = {gh[0], gh[1], gh[2], qf[1] * gh[2] - qf[2] * gh[1],
-                            qf[2] * gh[0] - qf[0] * gh[2], qf[0] * gh[1] - qf[1] * gh[0]};
-        const float ar = fabsf(r);
-        const float w = ar <= a.delta ? 1.0f : a.delta / ar;
-        const float e = ar <= a.delta ? 0.5f * r * r : a.delta * (ar - 0.5f * a.delta);
-        int k = 0;
+        // ---- stage 2: point, nearest voxel, first hash probe
+        int m[B][3];
+        float qr[B][3], qf[B][3];
+        uint64_t key[B], h[B];
+        bool live[B];
+        uint4 e[B];
 #pragma unroll
-        for (int p = 0; p < 6; ++p) {
-            const float wj = w * J[p];
+        for (int j = 0; j < B; ++j) {
+            const int i = base + j * stride;
+            live[j] = i < N && depth_ok(D[j], a.zmin, a.zmax);
+            if (!live[j]) continue;
+            if (kPrecision) ks[29].add(1.0f); else acc[29] += 1.0f;
+            const int v = i / L.W;
+            const int u = i - v * L.W;
+            if (!kPrecision) {
+                const double Dd = (double)D[j];
+                const double x0 = Dd * (((double)u - L.cx) * L.ifx);
+                const double x1 = Dd * (((double)v - L.cy) * L.ify);
 #pragma unroll
-            for (int q2 = p; q2 < 6; ++q2) {
-                if (kPrecision) ks[k].add(wj * J[q2]); else acc[k] += wj * J[q2];
-                ++k;
+                for (int r = 0; r < 3; ++r) {
+                    const double q = R[3 * r] * x0 + R[3 * r + 1] * x1 + R[3 * r + 2] * Dd + t[r];
+                    m[j][r] = (int)floor(q * a.inv_vs + 0.5);
+                    qr[j][r] = (float)(q - a.vs * (double)m[j][r]);
+                    qf[j][r] = (float)q;
+                }
+            } else {
+                const float x0 = D[j] * (((float)u - cxf) * ifxf);
+                const float x1 = D[j] * (((float)v - cyf) * ifyf);
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const float qc = Rf[3 * r] * x0 + Rf[3 * r + 1] * x1 + Rf[3 * r + 2] * D[j] + trf[r];
+                    const int dm = (int)floorf(qc * ivsf + 0.5f);
+                    m[j][r] = mc[r] + dm;
+                    qr[j][r] = qc - vsf * (float)dm;
+                    qf[j][r] = qc + mcf[r];
+                }
             }
+            const int bx = block_of(m[j][0]), by = block_of(m[j][1]), bz = block_of(m[j][2]);
+            if (!key_in_range(bx, by, bz)) {
+                live[j] = false;
+                continue;
+            }
+            key[j] = pack_key(bx, by, bz);
+            h[j] = mix64(key[j]) & M.mask;
+            e[j] = *reinterpret_cast<const uint4*>(&M.hash[h[j]]);
         }
+        // ---- stage 3: resolve the probe, then weight and record together
+        int64_t vi[B];
+        float Wv[B];
+        float4 rec32[B];
+        ushort4 rec16[B];
 #pragma unroll
-        for (int p = 0; p < 6; ++p) {
-            if (kPrecision) ks[21 + p].add(w * J[p] * r); else acc[21 + p] += w * J[p] * r;
+        for (int j = 0; j < B; ++j) {
+            if (!live[j]) continue;
+            const uint64_t k = (uint64_t)e[j].x | ((uint64_t)e[j].y << 32);
+            int32_t slot;
+            if (k == key[j]) {
+                slot = (int32_t)e[j].z;
+            } else if (k == kEmptyKey) {
+                slot = -1;
+            } else {
+                slot = -1;
+                uint64_t hh = h[j];
+                for (uint64_t probe = 1; probe <= M.mask; ++probe) {
+                    hh = (hh + 1) & M.mask;
+                    const uint4 f = *reinterpret_cast<const uint4*>(&M.hash[hh]);
+                    const uint64_t kk = (uint64_t)f.x | ((uint64_t)f.y << 32);
+                    if (kk == key[j]) {
+                        slot = (int32_t)f.z;
+                        break;
+                    }
+                    if (kk == kEmptyKey) break;
+                }
+            }
+            if (slot < 0) {
+                live[j] = false;
+                continue;
+            }
+            vi[j] = (int64_t)slot * kBlockVoxels + morton9(m[j][0] & 7, m[j][1] & 7, m[j][2] & 7);
+            Wv[j] = M.weight[vi[j]];
+            if (STORAGE == GSDF_FP32)
+                rec32[j] = reinterpret_cast<const float4*>(M.vox)[vi[j]];
+            else
+                rec16[j] = reinterpret_cast<const ushort4*>(M.vox)[vi[j]];
         }
-        if (kPrecision) {
-            ks[27].add(e);
-            ks[28].add(1.0f);
-        } else {
-            acc[27] += e;
-            acc[28] += 1.0f;
+        // ---- stage 4: residuals and sums
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            if (!live[j] || !(Wv[j] > 0.0f)) continue;
+            float psi, g0, g1, g2;
+            if (STORAGE == GSDF_FP32) {
+                psi = rec32[j].x / Wv[j];
+                g0 = rec32[j].y;
+                g1 = rec32[j].z;
+                g2 = rec32[j].w;
+            } else {
+                psi = unpack16(rec16[j].x, STORAGE) * M.truncation;
+                g0 = unpack16(rec16[j].y, STORAGE);
+                g1 = unpack16(rec16[j].z, STORAGE);
+                g2 = unpack16(rec16[j].w, STORAGE);
+            }
+            const float n2 = g0 * g0 + g1 * g1 + g2 * g2;
+            if (!(n2 > 0.0f)) continue;
+            const float inv = 1.0f / sqrtf(n2);
+            const float gh[3] = {g0 * inv, g1 * inv, g2 * inv};
+            const float r = psi + gh[0] * qr[j][0] + gh[1] * qr[j][1] + gh[2] * qr[j][2];
+            const float J[6] = {gh[0], gh[1], gh[2], qf[j][1] * gh[2] - qf[j][2] * gh[1],
+                                qf[j][2] * gh[0] - qf[j][0] * gh[2], qf[j][0] * gh[1] - qf[j][1] * gh[0]};
+            const float ar = fabsf(r);
+            const float w = ar <= a.delta ? 1.0f : a.delta / ar;
+            const float en = ar <= a.delta ? 0.5f * r * r : a.delta * (ar - 0.5f * a.delta);
+            int k = 0;
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                const float wj = w * J[p];
+#pragma unroll
+                for (int q2 = p; q2 < 6; ++q2) {
+                    if (kPrecision) ks[k].add(wj * J[q2]); else acc[k] += wj * J[q2];
+                    ++k;
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                if (kPrecision) ks[21 + p].add(w * J[p] * r); else acc[21 + p] += w * J[p] * r;
+            }
+            if (kPrecision) {
+                ks[27].add(en);
+                ks[28].add(1.0f);
+            } else {
+                acc[27] += en;
+                acc[28] += 1.0f;
+            }
         }
     }
 #pragma unroll
@@ -221,6 +308,7 @@ __device__ inline void accumulate(const MapView& M, const TrackLevel& L, const T
 struct ReduceLds {
     float v[kNE][kTrackBlock];
     double part[kNE][8];
+    double tot[kNE];
 };
 
 template <bool COMP>
@@ -296,19 +384,21 @@ __device__ inline void total_partials(const double* partials, int groups, double
         r.part[k][p] = COMP ? (double)ks.value() : s;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < kNE; ++k) {
-            if (COMP) {
-                Kahan ks;
-                for (int p = 0; p < 8; ++p) ks.add((float)r.part[k][p]);
-                ne[k] = (double)ks.value();
-            } else {
-                double t = 0.0;
-                for (int p = 0; p < 8; ++p) t += r.part[k][p];
-                ne[k] = t;
-            }
+    if (threadIdx.x < kNE) {
+        const int k = threadIdx.x;
+        if (COMP) {
+            Kahan ks;
+            for (int p = 0; p < 8; ++p) ks.add((float)r.part[k][p]);
+            r.tot[k] = (double)ks.value();
+        } else {
+            double t = 0.0;
+            for (int p = 0; p < 8; ++p) t += r.part[k][p];
+            r.tot[k] = t;
         }
     }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 0; k < kNE; ++k) ne[k] = r.tot[k];
 }
 
 // Cholesky solve of the damped 6x6 system and left update of the pose.
@@ -389,6 +479,19 @@ __device__ inline bool leaf_arrive(unsigned* sync, int par, int groups) {
     return true;
 }
 
+// Single-level arrival (grids of at most kSingleLevel work-groups): the
+// serialised same-address atomics cost less than a second tree level.
+constexpr int kSingleLevel = 16;
+__device__ inline bool root_arrive_direct(unsigned* sync, int par, int groups) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    unsigned* rc = &sync[kSyncRoot + par];
+    if (__hip_atomic_fetch_add(rc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != (unsigned)groups - 1)
+        return false;
+    __hip_atomic_store(rc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
+}
+
 __device__ inline bool root_arrive(unsigned* sync, int par, int groups) {
     const int nleaf = (groups + kLeaf - 1) / kLeaf;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -410,6 +513,14 @@ __device__ inline bool reduce_tree(const float acc[kNE], const float cmp[kNE], d
                                    unsigned* sync, int par, int groups, double ne[kNE], ReduceLds& r,
                                    int* s_flag) {
     store_partial<COMP>(acc, cmp, part + (size_t)blockIdx.x * kPartStride, r);
+    if (groups <= kSingleLevel) {
+        // few work-groups: one arrival counter, the last sums every partial
+        if (threadIdx.x == 0) *s_flag = root_arrive_direct(sync, par, groups) ? 1 : 0;
+        __syncthreads();
+        if (!*s_flag) return false;
+        total_partials<COMP>(part, groups, ne, r);
+        return true;
+    }
     if (threadIdx.x == 0) *s_flag = leaf_arrive(sync, par, groups) ? 1 : 0;
     __syncthreads();
     if (!*s_flag) return false;
@@ -444,11 +555,18 @@ __device__ inline bool wait_generation(unsigned* sync, unsigned target) {
     return true;
 }
 
-// Work-groups that take part at a level: enough to give each thread about
-// kPixPerThread pixels, so coarse levels synchronise few groups.
+// Work-groups that take part at a level: about kPixPerGroup pixels each,
+// at least kMinGroups (so coarse levels keep enough memory parallelism and
+// a two-level arrival tree) and at most the grid.  Measured on MI355X at
+// 640x480: the per-iteration cost of the coarse levels is dominated by the
+// grid-wide reduction, which falls with fewer groups until the per-thread
+// pixel chains and the arrival contention take over.
+constexpr int kPixPerGroup = 1024;
+constexpr int kMinGroups = 72;
 __device__ inline int level_groups(const TrackLevel& L, int G) {
-    int g = (L.W * L.H + kTrackBlock * kPixPerThread - 1) / (kTrackBlock * kPixPerThread);
-    return g < 1 ? 1 : (g > G ? G : g);
+    int g = (L.W * L.H + kPixPerGroup - 1) / kPixPerGroup;
+    g = g < kMinGroups ? kMinGroups : g;
+    return g > G ? G : g;
 }
 
 // The whole coarse-to-fine Gauss-Newton of one frame (cooperative launch).
@@ -459,6 +577,7 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
     __shared__ double s_pose[12];
     __shared__ int s_last, s_ok;
     __shared__ ReduceLds red;
+    __shared__ float s_depth[kTrackBatch * kTrackBlock];
     const int G = gridDim.x;
     int gi = 0;  // global iteration index
     for (int l = a.levels - 1; l >= 0; --l) {
@@ -468,6 +587,15 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
             // no pixels at this level: skip to the end of its iterations
             gi += a.iters[l];
             continue;
+        }
+        // this work-group's pixels are the same in every iteration of the
+        // level: the depths of each thread's first batch are loaded once,
+        // before the first wait, and kept in LDS
+        const int first = blockIdx.x * kTrackBlock + threadIdx.x;
+#pragma unroll
+        for (int j = 0; j < kTrackBatch; ++j) {
+            const int i = first + j * Gl * kTrackBlock;
+            s_depth[j * kTrackBlock + threadIdx.x] = i < L.W * L.H ? L.depth[i] : 0.0f;
         }
         for (int it = 0; it < a.iters[l]; ++it, ++gi) {
             // ---- wait for the pose of iteration gi
@@ -500,7 +628,7 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
 #pragma unroll
             for (int k = 0; k < 12; ++k) P[k] = s_pose[k];
             float acc[kNE], cmp[kNE];
-            accumulate<STORAGE>(M, L, a, P, blockIdx.x * kTrackBlock + threadIdx.x, Gl * kTrackBlock, acc, cmp);
+            accumulate<STORAGE>(M, L, a, P, first, Gl * kTrackBlock, s_depth, acc, cmp);
 
             double* part = partials + (size_t)(gi & 1) * kPartsPerSet;
             double* leafpart = part + (size_t)kMaxGroups * kPartStride;
@@ -510,12 +638,6 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
 
             // ---- the work-group holding the total: solve, publish
             if (threadIdx.x == 0) {
-                if (stats) {
-                    stats[2 * gi] = (float)ne[27];
-                    stats[2 * gi + 1] = (float)ne[28];
-                }
-                add_stat(M, kStatTrackValid, (unsigned long long)ne[29]);
-                add_stat(M, kStatTrackUsed, (unsigned long long)ne[28]);
                 double Pn[12];
                 for (int k = 0; k < 12; ++k) Pn[k] = s_pose[k];
                 if (solve_and_update(ne, a.damping, Pn)) {
@@ -529,6 +651,13 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 __hip_atomic_store(&sync[kSyncGen], (unsigned)(gi + 1), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
+                // bookkeeping after the publish, off the critical path
+                if (stats) {
+                    stats[2 * gi] = (float)ne[27];
+                    stats[2 * gi + 1] = (float)ne[28];
+                }
+                add_stat(M, kStatTrackValid, (unsigned long long)ne[29]);
+                add_stat(M, kStatTrackUsed, (unsigned long long)ne[28]);
             }
             __syncthreads();
         }
@@ -551,7 +680,7 @@ __global__ __launch_bounds__(kTrackBlock) void k_normal_equations(MapView M, Tra
     for (int k = 0; k < 12; ++k) P[k] = pose[k];
     float acc[kNE], cmp[kNE];
     accumulate<STORAGE>(M, a.lv[0], a, P, blockIdx.x * kTrackBlock + threadIdx.x,
-                        gridDim.x * kTrackBlock, acc, cmp);
+                        gridDim.x * kTrackBlock, nullptr, acc, cmp);
     double ne[kNE];
     if (!reduce_tree<STORAGE != GSDF_FP32>(acc, cmp, partials, partials + (size_t)kMaxGroups * kPartStride, sync,
                                            0, gridDim.x, ne, red, &s_last))
@@ -645,7 +774,7 @@ inline ScratchLayout scratch_layout(const gsdf_camera& c, int levels) {
 }
 
 inline int normal_eq_groups(int npx) {
-    int g = ceil_div(npx, kTrackBlock * kPixPerThread);
+    int g = ceil_div(npx, kTrackBlock * 2);   // about two pixels per thread
     return g < 1 ? 1 : (g > kMaxGroups ? kMaxGroups : g);
 }
 
