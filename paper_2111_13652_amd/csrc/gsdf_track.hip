@@ -303,8 +303,8 @@ __device__ inline void accumulate(const MapView& M, const TrackLevel& L, const T
 // partial with device-scope stores.  (Cross-lane shuffles of doubles would
 // chain ~180 dependent LDS permutes per wave.)  The plain path adds in
 // float64; the precision form (COMP) uses compensated float32 at every
-// stage.  The barrier at the end waits for the stores; the thread that
-// takes the arrival ticket issues the work-group's single release fence.
+// stage.  The storing threads are lanes of wave 0, so thread 0 (which takes
+// the arrival ticket) waits for their completion before signalling.
 struct ReduceLds {
     float v[kNE][kTrackBlock];
     double part[kNE][8];
@@ -358,9 +358,10 @@ __device__ inline void store_partial(const float acc[kNE], const float cmp[kNE],
     __syncthreads();
 }
 
-// Sum of `groups` partials (called after the acquire fence, so plain loads
-// see every partial).  Thread (k, p) adds entry k of the partials p, p+8, ...
-// with eight loads in flight.  Result in ne[] of thread 0.
+// Sum of `groups` partials (called by the last arriver; device-scope loads
+// see every partial stored before its ticket).  Thread (k, p) adds entry k of
+// the partials p, p+8, ... with eight loads in flight.  Result in ne[] of
+// thread 0.
 template <bool COMP>
 __device__ inline void total_partials(const double* partials, int groups, double ne[kNE], ReduceLds& r) {
     if (threadIdx.x < kNE * 8) {
@@ -371,14 +372,17 @@ __device__ inline void total_partials(const double* partials, int groups, double
         for (; b + 56 < groups; b += 64) {
             double x[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) x[j] = partials[(size_t)(b + 8 * j) * kPartStride + k];
+            for (int j = 0; j < 8; ++j)
+                x[j] = __hip_atomic_load(&partials[(size_t)(b + 8 * j) * kPartStride + k], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 if (COMP) ks.add((float)x[j]); else s += x[j];
             }
         }
         for (; b < groups; b += 8) {
-            const double x = partials[(size_t)b * kPartStride + k];
+            const double x = __hip_atomic_load(&partials[(size_t)b * kPartStride + k], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
             if (COMP) ks.add((float)x); else s += x;
         }
         r.part[k][p] = COMP ? (double)ks.value() : s;
@@ -445,6 +449,19 @@ __device__ bool solve_and_update(const double* ne, double damping, double* pose)
     return true;
 }
 
+// Memory ordering between work-groups.  Everything one work-group hands to
+// another (partial sums, leaf sums, the pose, counters, the generation) is
+// written and read only with device-scope atomic operations, which the
+// hardware keeps coherent per location across the XCDs without cache
+// maintenance.  Ordering is then all that is needed: a producer waits until
+// its device-scope stores have completed before it signals (s_waitcnt on all
+// counters, below), and a consumer issues its loads only after the signal's
+// value has returned.  A release/acquire fence at device scope would add an
+// L2 write-back and invalidation per work-group and iteration (measured at
+// about 10 % of the kernel at 640x480) to order plain memory operations,
+// which this kernel does not exchange.
+__device__ inline void complete_device_stores() { __builtin_amdgcn_s_waitcnt(0); }
+
 // Sync words in the scratch buffer.  Arrival is a two-level tree of tickets
 // (device-scope atomics on one address serialise, so a single ticket for
 // hundreds of work-groups would cost tens of microseconds): kLeaf
@@ -465,17 +482,16 @@ enum {
 
 // Arrival, thread 0 only.  leaf_arrive: true for the last of the kLeaf
 // work-groups sharing a leaf ticket; root_arrive: true for the last leaf.
-// The release fence before each ticket publishes the partial written just
-// before; the acquire fence of the winner makes the others' partials visible.
+// Before each ticket the work-group's device-scope partial stores have
+// completed; the winner reads the others' partials with device-scope loads.
 __device__ inline bool leaf_arrive(unsigned* sync, int par, int groups) {
     const int leaf = blockIdx.x / kLeaf;
     const int leaf_size = min(kLeaf, groups - leaf * kLeaf);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    complete_device_stores();
     unsigned* lc = &sync[kSyncLeaf + par * kMaxLeaves + leaf];
     if (__hip_atomic_fetch_add(lc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != (unsigned)leaf_size - 1)
         return false;
     __hip_atomic_store(lc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return true;
 }
 
@@ -483,23 +499,21 @@ __device__ inline bool leaf_arrive(unsigned* sync, int par, int groups) {
 // serialised same-address atomics cost less than a second tree level.
 constexpr int kSingleLevel = 16;
 __device__ inline bool root_arrive_direct(unsigned* sync, int par, int groups) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    complete_device_stores();
     unsigned* rc = &sync[kSyncRoot + par];
     if (__hip_atomic_fetch_add(rc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != (unsigned)groups - 1)
         return false;
     __hip_atomic_store(rc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return true;
 }
 
 __device__ inline bool root_arrive(unsigned* sync, int par, int groups) {
     const int nleaf = (groups + kLeaf - 1) / kLeaf;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    complete_device_stores();
     unsigned* rc = &sync[kSyncRoot + par];
     if (__hip_atomic_fetch_add(rc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != (unsigned)nleaf - 1)
         return false;
     __hip_atomic_store(rc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return true;
 }
 
@@ -541,8 +555,8 @@ __device__ inline bool reduce_tree(const float acc[kNE], const float cmp[kNE], d
 }
 
 // Wait (thread 0 only) until the published generation reaches `target`;
-// relaxed polling with a short sleep, then one acquire fence.  Returns false
-// on timeout or when another work-group aborted.
+// device-scope polling with a short sleep.  Returns false on timeout or when
+// another work-group aborted.
 __device__ inline bool wait_generation(unsigned* sync, unsigned target) {
     unsigned spins = 0;
     while (__hip_atomic_load(&sync[kSyncGen], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -551,7 +565,6 @@ __device__ inline bool wait_generation(unsigned* sync, unsigned target) {
             return false;
         __builtin_amdgcn_s_sleep(2);
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return true;
 }
 
@@ -602,17 +615,14 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
             if (threadIdx.x == 0) {
                 const bool ok = gi == 0 || wait_generation(sync, (unsigned)gi);
                 if (ok) {
-                    // after the acquire fence plain loads see the published
-                    // pose; six 16-byte loads are issued back to back
-                    const double2* pp = reinterpret_cast<const double2*>(pose);
-                    double2 v[6];
+                    // the pose was stored (device scope) before the
+                    // generation; twelve device-scope loads issued back to back
+                    double v[12];
 #pragma unroll
-                    for (int k = 0; k < 6; ++k) v[k] = pp[k];
+                    for (int k = 0; k < 12; ++k)
+                        v[k] = __hip_atomic_load(&pose[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
-                    for (int k = 0; k < 6; ++k) {
-                        s_pose[2 * k] = v[k].x;
-                        s_pose[2 * k + 1] = v[k].y;
-                    }
+                    for (int k = 0; k < 12; ++k) s_pose[k] = v[k];
                 }
                 s_ok = ok ? 1 : 0;
             }
@@ -648,7 +658,7 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
                 }
                 if (l == 0 && it == a.iters[0] - 1 && ne[28] < (double)a.min_inlier_frac * ne[29])
                     raise_status(status, GSDF_ELOST);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                complete_device_stores();
                 __hip_atomic_store(&sync[kSyncGen], (unsigned)(gi + 1), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
                 // bookkeeping after the publish, off the critical path
