@@ -24,6 +24,9 @@
 // frame's sums before rounding once.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+
 #include <climits>
 
 #include "gsdf_common.hpp"
@@ -35,6 +38,7 @@ constexpr int kTile = 16;
 constexpr int kHalo = 2;
 constexpr int kTileH = kTile + 2 * kHalo;
 constexpr int kFuseBlock = 256;
+constexpr int kFuseChunk = 2048;   // box pixels scanned per pass (LDS queue capacity)
 constexpr int kFuseGroups = 4096;
 constexpr float kBoxMargin = 1e-4f;  // metres; far above binary32 rounding of coordinates
 
@@ -48,6 +52,8 @@ struct FuseConsts {
     float vs_f, T_f;
     float inv_df;   // 1 / band sample spacing
     int W, H;
+    float fix_scale;     // 2^f: fixed-point scale of the per-frame voxel sums
+    double fix_inv;      // 2^-f
 };
 
 __device__ inline float linear_weight(float d, float eps, float T) {
@@ -193,13 +199,31 @@ __device__ inline void block_box(const FuseConsts& fc, const double* R, const do
     B->inv_bw = B->u1 >= B->u0 ? 1.0f / (float)(B->u1 - B->u0 + 1) : 0.0f;
 }
 
+// Fixed point with f fraction bits for the per-frame voxel sums.  Scaling a
+// float by 2^f is exact, so a term converts exactly unless it is below
+// 2^(23-f) (then it is rounded to 2^-f); integer sums are exact, and the
+// total is rounded once, to float.  f is chosen on the host so that the
+// largest possible sum fits (see fix_bits).
+__device__ inline unsigned long long to_fixed(float x, float scale) {
+    return (unsigned long long)__float2ll_rn(x * scale);
+}
+__device__ inline float from_fixed(unsigned long long a, double inv) {
+    return (float)((double)(long long)a * inv);
+}
+
 template <int STORAGE>
 __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const float4* __restrict__ pix,
                                                            FuseConsts fc, const double* __restrict__ Twc) {
-    __shared__ float aS[kBlockVoxels];
-    __shared__ float aG[3][kBlockVoxels];
-    __shared__ float aW[kBlockVoxels];
+    // per-voxel sums of the frame in 32.32 fixed point: integer additions
+    // are associative, so the sums (and the map) do not depend on the order
+    // in which the work-group's threads add their updates
+    __shared__ unsigned long long aS[kBlockVoxels];
+    __shared__ unsigned long long aG[3][kBlockVoxels];
+    __shared__ unsigned long long aW[kBlockVoxels];
     __shared__ BlockBox box;
+    __shared__ uint32_t q_pix[kFuseChunk];
+    __shared__ uint32_t q_k[kFuseChunk];
+    __shared__ int q_count;
 
     double R[9], t[3];
 #pragma unroll
@@ -225,18 +249,21 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
     int n_blocks = M.counters[kNumBlocks];
     n_blocks = n_blocks < M.max_blocks ? n_blocks : M.max_blocks;
     unsigned long long my_updates = 0, my_visits = 0, my_voxels = 0, my_blocks = 0;
-
-    for (int slot = blockIdx.x; slot < n_blocks; slot += gridDim.x) {
+    // The newest blocks (highest slots: usually nearest the camera, with
+    // the largest boxes) are taken first, so the longest work-groups do not
+    // start last.
+    for (int item = blockIdx.x; item < n_blocks; item += gridDim.x) {
+        const int slot = n_blocks - 1 - item;
         if (M.touched_flag[slot] == 0) continue;   // uniform across the work-group
         ++my_blocks;
         int bx, by, bz;
         unpack_key(M.block_keys[slot], &bx, &by, &bz);
         for (int c = threadIdx.x; c < kBlockVoxels; c += kFuseBlock) {
-            aS[c] = 0.0f;
-            aG[0][c] = 0.0f;
-            aG[1][c] = 0.0f;
-            aG[2][c] = 0.0f;
-            aW[c] = 0.0f;
+            aS[c] = 0ull;
+            aG[0][c] = 0ull;
+            aG[1][c] = 0ull;
+            aG[2][c] = 0ull;
+            aW[c] = 0ull;
         }
         if (threadIdx.x == 0) block_box(fc, R, t, bx, by, bz, &box);
         __syncthreads();
@@ -244,130 +271,175 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
         const int bw = box.u1 - box.u0 + 1;
         const int bh = box.v1 - box.v0 + 1;
         const int npx = (bw > 0 && bh > 0) ? bw * bh : 0;
-        // lane-major order: the 64 lanes of a wave take pixels npx/64 apart,
-        // so their samples fall in different voxels and the LDS atomics of
-        // one instruction rarely collide
-        const int lane_stride = (npx + 63) / 64;
         const float inv_bw = box.inv_bw;
         // the depth band [D - T, D + T] must reach the box's depth range
         const float zreach_lo = box.zmin - fc.band.Tf - fc.band.Df;
         const float zreach_hi = box.zmax + fc.band.Tf + fc.band.Df;
-        for (int p = threadIdx.x; p < lane_stride * 64; p += kFuseBlock) {
-            const int q = (p & 63) * lane_stride + (p >> 6);
-            if (q >= npx) continue;
-            // row and column without an integer division (q < 2^24 is exact)
-            int row = (int)(((float)q + 0.5f) * inv_bw);
-            int col = q - row * bw;
-            if (col < 0) {
-                --row;
-                col += bw;
-            } else if (col >= bw) {
-                ++row;
-                col -= bw;
-            }
-            const int u = box.u0 + col;
-            const int v = box.v0 + row;
-            const float4 px = pix[(size_t)v * fc.W + u];
-            const float D = px.w;
-            if (!(D > 0.0f)) continue;
-            if (D < zreach_lo || D > zreach_hi) continue;
-            ++my_visits;
-            // clip the pixel's ray z * (R ray) to the block's box (the box's
-            // margin absorbs the approximate reciprocals)
-            const float xr = pixel_xr(br, u);
-            const float yr = pixel_yr(br, v);
-            float zin = 0.0f, zout = 3.0e38f;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const float dir = Rf[3 * i] * xr + Rf[3 * i + 1] * yr + Rf[3 * i + 2];
-                if (fabsf(dir) < 1e-20f) {
-                    if (box.lo[i] > 0.0f || box.hi[i] < 0.0f) zout = -1.0f;
-                } else {
-                    const float id = __builtin_amdgcn_rcpf(dir);
-                    const float a = box.lo[i] * id, b = box.hi[i] * id;
-                    zin = fmaxf(zin, fminf(a, b));
-                    zout = fminf(zout, fmaxf(a, b));
-                }
-            }
-            // samples inside the box widened by kBoxMargin: no other sample can
-            // land in a voxel of this block (binary32 rounding of a sample's
-            // position is far below the margin), so the run structure of the
-            // consecutive-repeat rule inside the block is the same as over
-            // the whole band
-            const float zb0 = D - fc.band.Tf;  // first band sample
-            if (!(zin <= zout)) continue;
-            const float last = (float)(fc.band.nsamples - 1);
-            const float inv_df = fc.inv_df;
-            const int k0 = (int)fmaxf(0.0f, ceilf(fminf((zin - zb0) * inv_df, last + 1.0f)));
-            const int k1 = (int)fminf(last, floorf(fmaxf((zout - zb0) * inv_df, -1.0f)));
-            if (k0 > k1) continue;
+        const float last = (float)(fc.band.nsamples - 1);
+        const float inv_df = fc.inv_df;
 
-            // observed point as an offset from a nearby voxel: formed in
-            // float64 for FP32 storage; camera-relative float32 for 16-bit
-            // storage (q - v_s m_c = R x + t_r, |t_r| < v_s)
-            int mref[3];
-            float prel[3];
-            if (STORAGE == GSDF_FP32) {
-                const double Dd = (double)D;
-                const double x0 = Dd * (((double)u - fc.cx_d) * fc.ifx_d);
-                const double x1 = Dd * (((double)v - fc.cy_d) * fc.ify_d);
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    const double q = R[3 * i] * x0 + R[3 * i + 1] * x1 + R[3 * i + 2] * Dd + t[i];
-                    mref[i] = (int)floor(q * fc.inv_vs_d + 0.5);
-                    prel[i] = (float)(q - fc.vs_d * (double)mref[i]);
+        // The box is gathered in chunks of kFuseChunk pixels, each in two
+        // phases.  Scan: every thread tests pixels of the chunk against the
+        // block (depth reach, ray/box slab, band samples inside) and the
+        // survivors go to an LDS queue with their sample range.  Fuse: the
+        // queue is worked densely, so the sample loop and the LDS atomics run
+        // with most lanes busy (a thread-per-pixel loop over the box leaves
+        // three lanes in four idle).
+        for (int c0 = 0; c0 < npx; c0 += kFuseChunk) {
+            const int cn = min(kFuseChunk, npx - c0);
+            if (threadIdx.x == 0) q_count = 0;
+            __syncthreads();
+            for (int p = threadIdx.x; p < cn; p += kFuseBlock) {
+                const int q = c0 + p;
+                // row and column without an integer division (q < 2^24 is exact)
+                int row = (int)(((float)q + 0.5f) * inv_bw);
+                int col = q - row * bw;
+                if (col < 0) {
+                    --row;
+                    col += bw;
+                } else if (col >= bw) {
+                    ++row;
+                    col -= bw;
                 }
-            } else {
-                const float x0 = D * (((float)u - fc.rcx) / fc.fxf);
-                const float x1 = D * (((float)v - fc.rcy) / fc.fyf);
+                const int u = box.u0 + col;
+                const int v = box.v0 + row;
+                const float D = pix[(size_t)v * fc.W + u].w;
+                bool keep = D > 0.0f && D >= zreach_lo && D <= zreach_hi;
+                int k0 = 0, k1 = -1;
+                if (keep) {
+                    ++my_visits;
+                    // clip the pixel's ray z * (R ray) to the block's box (the
+                    // box's margin absorbs the approximate reciprocals)
+                    const float xr = pixel_xr(br, u);
+                    const float yr = pixel_yr(br, v);
+                    float zin = 0.0f, zout = 3.0e38f;
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    const float qc = Rf[3 * i] * x0 + Rf[3 * i + 1] * x1 + Rf[3 * i + 2] * D + trf[i];
-                    const int dm = (int)floorf(qc * ivsf + 0.5f);
-                    mref[i] = mc[i] + dm;
-                    prel[i] = qc - fc.vs_f * (float)dm;
+                    for (int i = 0; i < 3; ++i) {
+                        const float dir = Rf[3 * i] * xr + Rf[3 * i + 1] * yr + Rf[3 * i + 2];
+                        if (fabsf(dir) < 1e-20f) {
+                            if (box.lo[i] > 0.0f || box.hi[i] < 0.0f) zout = -1.0f;
+                        } else {
+                            const float id = __builtin_amdgcn_rcpf(dir);
+                            const float a = box.lo[i] * id, b = box.hi[i] * id;
+                            zin = fmaxf(zin, fminf(a, b));
+                            zout = fminf(zout, fmaxf(a, b));
+                        }
+                    }
+                    // samples inside the box widened by kBoxMargin: no other
+                    // sample can land in a voxel of this block (binary32
+                    // rounding of a sample's position is far below the
+                    // margin), so the run structure of the consecutive-repeat
+                    // rule inside the block is the same as over the whole band
+                    const float zb0 = D - fc.band.Tf;  // first band sample
+                    keep = zin <= zout;
+                    if (keep) {
+                        k0 = (int)fmaxf(0.0f, ceilf(fminf((zin - zb0) * inv_df, last + 1.0f)));
+                        k1 = (int)fminf(last, floorf(fmaxf((zout - zb0) * inv_df, -1.0f)));
+                        keep = k0 <= k1;
+                    }
+                }
+                // wave-level compaction into the queue
+                const unsigned long long ballot = __ballot(keep);
+                if (ballot) {
+                    const int lane = threadIdx.x & 63;
+                    const int n_wave = __popcll(ballot);
+                    int base = 0;
+                    if (lane == __ffsll((long long)ballot) - 1) base = atomicAdd(&q_count, n_wave);
+                    base = __shfl(base, __ffsll((long long)ballot) - 1);
+                    if (keep) {
+                        const int slot_q = base + __popcll(ballot & ((1ull << lane) - 1ull));
+                        q_pix[slot_q] = (uint32_t)(v * fc.W + u);
+                        q_k[slot_q] = (uint32_t)(k0 | (k1 << 16));
+                    }
                 }
             }
-            int pm[3] = {INT_MIN, INT_MIN, INT_MIN};
-            for (int k = k0; k <= k1; ++k) {
-                int m[3];
-                if (!band_sample(br, xr, yr, D, k, m)) continue;
-                if (m[0] == pm[0] && m[1] == pm[1] && m[2] == pm[2]) continue;
-                pm[0] = m[0];
-                pm[1] = m[1];
-                pm[2] = m[2];
-                if (block_of(m[0]) != bx || block_of(m[1]) != by || block_of(m[2]) != bz) continue;
-                float off[3];
+            __syncthreads();
+            const int nq = q_count;
+            // lane-major order over the queue: the lanes of a wave take
+            // entries nq/64 apart (different rows of the box), so the LDS
+            // atomics of one instruction rarely hit the same voxel
+            const int lane_stride = (nq + 63) / 64;
+            for (int p = threadIdx.x; p < lane_stride * 64; p += kFuseBlock) {
+                const int e = (p & 63) * lane_stride + (p >> 6);
+                if (e >= nq) continue;
+                const uint32_t pi = q_pix[e];
+                const int k0 = (int)(q_k[e] & 0xffffu), k1 = (int)(q_k[e] >> 16);
+                const int v = (int)(pi / (uint32_t)fc.W);
+                const int u = (int)pi - v * fc.W;
+                const float4 px = pix[pi];
+                const float D = px.w;
+                const float xr = pixel_xr(br, u);
+                const float yr = pixel_yr(br, v);
+                // observed point as an offset from a nearby voxel: formed in
+                // float64 for FP32 storage; camera-relative float32 for 16-bit
+                // storage (q - v_s m_c = R x + t_r, |t_r| < v_s)
+                int mref[3];
+                float prel[3];
+                if (STORAGE == GSDF_FP32) {
+                    const double Dd = (double)D;
+                    const double x0 = Dd * (((double)u - fc.cx_d) * fc.ifx_d);
+                    const double x1 = Dd * (((double)v - fc.cy_d) * fc.ify_d);
 #pragma unroll
-                for (int i = 0; i < 3; ++i) off[i] = fc.vs_f * (float)(m[i] - mref[i]) - prel[i];
-                float d = px.x * off[0] + px.y * off[1] + px.z * off[2];
-                d = fminf(fc.T_f, fmaxf(-fc.T_f, d));
-                const float w = linear_weight(d, fc.eps, fc.T_f);
-                if (!(w > 0.0f)) continue;
-                const int c = morton9(m[0] & 7, m[1] & 7, m[2] & 7);
-                atomicAdd(&aS[c], w * d);
-                atomicAdd(&aG[0][c], w * px.x);
-                atomicAdd(&aG[1][c], w * px.y);
-                atomicAdd(&aG[2][c], w * px.z);
-                atomicAdd(&aW[c], w);
-                ++my_updates;
+                    for (int i = 0; i < 3; ++i) {
+                        const double q = R[3 * i] * x0 + R[3 * i + 1] * x1 + R[3 * i + 2] * Dd + t[i];
+                        mref[i] = (int)floor(q * fc.inv_vs_d + 0.5);
+                        prel[i] = (float)(q - fc.vs_d * (double)mref[i]);
+                    }
+                } else {
+                    const float x0 = D * (((float)u - fc.rcx) / fc.fxf);
+                    const float x1 = D * (((float)v - fc.rcy) / fc.fyf);
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const float qc = Rf[3 * i] * x0 + Rf[3 * i + 1] * x1 + Rf[3 * i + 2] * D + trf[i];
+                        const int dm = (int)floorf(qc * ivsf + 0.5f);
+                        mref[i] = mc[i] + dm;
+                        prel[i] = qc - fc.vs_f * (float)dm;
+                    }
+                }
+                int pm[3] = {INT_MIN, INT_MIN, INT_MIN};
+                for (int k = k0; k <= k1; ++k) {
+                    int m[3];
+                    if (!band_sample(br, xr, yr, D, k, m)) continue;
+                    if (m[0] == pm[0] && m[1] == pm[1] && m[2] == pm[2]) continue;
+                    pm[0] = m[0];
+                    pm[1] = m[1];
+                    pm[2] = m[2];
+                    if (block_of(m[0]) != bx || block_of(m[1]) != by || block_of(m[2]) != bz) continue;
+                    float off[3];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) off[i] = fc.vs_f * (float)(m[i] - mref[i]) - prel[i];
+                    float d = px.x * off[0] + px.y * off[1] + px.z * off[2];
+                    d = fminf(fc.T_f, fmaxf(-fc.T_f, d));
+                    const float w = linear_weight(d, fc.eps, fc.T_f);
+                    if (!(w > 0.0f)) continue;
+                    const int c = morton9(m[0] & 7, m[1] & 7, m[2] & 7);
+                    atomicAdd(&aS[c], to_fixed(w * d, fc.fix_scale));
+                    atomicAdd(&aG[0][c], to_fixed(w * px.x, fc.fix_scale));
+                    atomicAdd(&aG[1][c], to_fixed(w * px.y, fc.fix_scale));
+                    atomicAdd(&aG[2][c], to_fixed(w * px.z, fc.fix_scale));
+                    atomicAdd(&aW[c], to_fixed(w, fc.fix_scale));
+                    ++my_updates;
+                }
             }
+            __syncthreads();
         }
-        __syncthreads();
 
         // write the voxels this frame changed: this work-group owns the block
         for (int c = threadIdx.x; c < kBlockVoxels; c += kFuseBlock) {
-            const float sw = aW[c];
+            const float sw = from_fixed(aW[c], fc.fix_inv);
             if (!(sw > 0.0f)) continue;
+            const float sS = from_fixed(aS[c], fc.fix_inv);
+            const float sG[3] = {from_fixed(aG[0][c], fc.fix_inv), from_fixed(aG[1][c], fc.fix_inv),
+                                 from_fixed(aG[2][c], fc.fix_inv)};
             ++my_voxels;
             const int64_t vi = (int64_t)slot * kBlockVoxels + c;
             if (STORAGE == GSDF_FP32) {
                 float4* rec = reinterpret_cast<float4*>(M.vox) + vi;
                 float4 r = *rec;
-                r.x += aS[c];
-                r.y += aG[0][c];
-                r.z += aG[1][c];
-                r.w += aG[2][c];
+                r.x += sS;
+                r.y += sG[0];
+                r.z += sG[1];
+                r.w += sG[2];
                 *rec = r;
                 M.weight[vi] += sw;
             } else {
@@ -375,10 +447,10 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
                 const ushort4 p = *rec;
                 const float Wold = M.weight[vi];
                 const float Wn = Wold + sw;
-                const float psi = (Wold * unpack16(p.x, STORAGE) * M.truncation + aS[c]) / Wn;
-                const float g0 = (Wold * unpack16(p.y, STORAGE) + aG[0][c]) / Wn;
-                const float g1 = (Wold * unpack16(p.z, STORAGE) + aG[1][c]) / Wn;
-                const float g2 = (Wold * unpack16(p.w, STORAGE) + aG[2][c]) / Wn;
+                const float psi = (Wold * unpack16(p.x, STORAGE) * M.truncation + sS) / Wn;
+                const float g0 = (Wold * unpack16(p.y, STORAGE) + sG[0]) / Wn;
+                const float g1 = (Wold * unpack16(p.z, STORAGE) + sG[1]) / Wn;
+                const float g2 = (Wold * unpack16(p.w, STORAGE) + sG[2]) / Wn;
                 *rec = make_ushort4(pack16(psi / M.truncation, STORAGE), pack16(g0, STORAGE),
                                     pack16(g1, STORAGE), pack16(g2, STORAGE));
                 M.weight[vi] = Wn;
@@ -399,6 +471,20 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
         add_stat(M, kStatFusedVoxels, x_s);
         add_stat(M, kStatFusedBlocks, my_blocks);
     }
+}
+
+// Fraction bits of the fixed-point voxel sums.  A pixel's band meets a voxel
+// at most once and contributes |w d| <= T, |w n| <= 1, w <= 1, so a frame's
+// sum is bounded by max(1, T) times the pixels whose rays can cross the
+// voxel: its footprint, at most (f v_s sqrt(3) / z + 2)^2 pixels at the
+// nearest depth z = max(zmin - T, v_s) a voxel of the band can have.  The
+// bits are chosen to keep that bound below 2^62.
+inline int fix_bits(const gsdf_camera& cam, double vs, double T) {
+    const double z = std::max((double)cam.zmin - T, vs);
+    const double side = std::max(cam.fx, cam.fy) * vs * std::sqrt(3.0) / z + 2.0;
+    const double bound = side * side * std::max(1.0, T);
+    const int f = (int)std::floor(62.0 - std::log2(bound));
+    return std::min(56, std::max(24, f));
 }
 
 inline FuseConsts fuse_consts(const gsdf_map& map, const gsdf_camera& cam, const gsdf_fuse_params& p) {
@@ -425,6 +511,9 @@ inline FuseConsts fuse_consts(const gsdf_map& map, const gsdf_camera& cam, const
     fc.inv_df = (float)(2.0 / map.desc.voxel_size);
     fc.W = cam.width;
     fc.H = cam.height;
+    const int f = fix_bits(cam, map.desc.voxel_size, map.desc.truncation);
+    fc.fix_scale = std::ldexp(1.0f, f);
+    fc.fix_inv = std::ldexp(1.0, -f);
     return fc;
 }
 
