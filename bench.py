@@ -46,12 +46,13 @@ B_ALLOC_PAIR = 16.0        # hash entry per distinct (tile, block) probe
 # figure is reported only while the kernel's sources still hash to the
 # values they had when the counters were taken.
 MEASURED_TRAFFIC = {
-    "track": {"bytes": (13749.0 * 2.0 + 1111.3) * 1024,
-              "sources": {"gsdf_track.hip": "95f3afd2eb2ce8c3b7b9f12d2ec0f64625a50df6947bc0f4b99f6d4f80aa83d4",
+    "track": {"bytes": (13443.3 * 1.9998 + 806.0 * 1.0000) * 1024,
+              "sources": {"gsdf_track.hip": "7a9c891f708bc608da746830c1cf5d103cb6f196ed2cbd1010df8fb7be8965f6",
+                          "gsdf_common.hpp": "accfd9a487ef21d1dc41374aca70c29fa5bd8d073cea674d16d78099d8a35574",
+                          "gsdf_se3.hpp": "13c15ea94701e1129da7175cf338be9aa9cc57bf8857172577cef813f6209733"}},
+    "fuse_blocks": {"bytes": (20496.1 * 1.9998 + 11863.4 * 1.0000) * 1024,
+              "sources": {"gsdf_fuse.hip": "905fa2c99f7e89fb72200c6befddf00fab0edfd32c95014c08b7900d95020b0f",
                           "gsdf_common.hpp": "accfd9a487ef21d1dc41374aca70c29fa5bd8d073cea674d16d78099d8a35574"}},
-    "fuse_blocks": {"bytes": (20546.1 * 2.0 + 11865.1) * 1024,
-                    "sources": {"gsdf_fuse.hip": "d8f43ab934dc8395440fcdc5bf253025b40818b93c1ead3af4f0fe581c302c85",
-                                "gsdf_common.hpp": "accfd9a487ef21d1dc41374aca70c29fa5bd8d073cea674d16d78099d8a35574"}},
 }
 
 

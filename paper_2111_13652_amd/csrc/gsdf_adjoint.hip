@@ -213,30 +213,42 @@ __global__ __launch_bounds__(kAdjBlock) void k_keyframe_loss(MapView M, AdjArgs 
     }
 }
 
-// One work-group per keyframe: fixed-order sum of the partials, then
-// loss_out[kf] and (when asked) dxi = Jl(xi)^T (pose sums).
-__global__ __launch_bounds__(64) void k_keyframe_finish(AdjArgs a, const double* __restrict__ xi,
-                                                        const double* __restrict__ partials,
-                                                        double* __restrict__ loss_out, double* __restrict__ dxi_out,
-                                                        double* __restrict__ count_out) {
-    __shared__ double s_sum[kAdjPart];
+// One work-group per keyframe: fixed-order sum of the partials (256 threads
+// stride over the work-groups, then a tree in LDS), then loss_out[kf] and
+// (when asked) dxi = Jl(xi)^T (pose sums).
+__global__ __launch_bounds__(256) void k_keyframe_finish(AdjArgs a, const double* __restrict__ xi,
+                                                         const double* __restrict__ partials,
+                                                         double* __restrict__ loss_out, double* __restrict__ dxi_out,
+                                                         double* __restrict__ count_out) {
+    __shared__ double s_part[kAdjPart][256];
     const int kf = blockIdx.x;
-    if (threadIdx.x < kAdjPart) {
-        double x = 0.0;
-        for (int g = 0; g < a.groups; ++g) x += partials[((size_t)kf * a.groups + g) * kAdjPart + threadIdx.x];
-        s_sum[threadIdx.x] = x;
+    double x[kAdjPart];
+#pragma unroll
+    for (int k = 0; k < kAdjPart; ++k) x[k] = 0.0;
+    for (int g = threadIdx.x; g < a.groups; g += 256) {
+        const double* p = partials + ((size_t)kf * a.groups + g) * kAdjPart;
+#pragma unroll
+        for (int k = 0; k < kAdjPart; ++k) x[k] += p[k];
     }
+#pragma unroll
+    for (int k = 0; k < kAdjPart; ++k) s_part[k][threadIdx.x] = x[k];
     __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < kAdjPart; ++k) s_part[k][threadIdx.x] += s_part[k][threadIdx.x + w];
+        __syncthreads();
+    }
     if (threadIdx.x != 0) return;
-    if (loss_out) loss_out[kf] = s_sum[0];
-    if (count_out) count_out[kf] = s_sum[7];
+    if (loss_out) loss_out[kf] = s_part[0][0];
+    if (count_out) count_out[kf] = s_part[7][0];
     if (dxi_out) {
         double Jl[36];
         se3_left_jacobian(xi + 6 * kf, Jl);
         for (int c = 0; c < 6; ++c) {
-            double x = 0.0;
-            for (int r = 0; r < 6; ++r) x += Jl[6 * r + c] * s_sum[1 + r];
-            dxi_out[6 * kf + c] = x;
+            double v = 0.0;
+            for (int r = 0; r < 6; ++r) v += Jl[6 * r + c] * s_part[1 + r][0];
+            dxi_out[6 * kf + c] = v;
         }
     }
 }
@@ -352,7 +364,7 @@ int gsdf_keyframe_loss(const gsdf_map* map, const float* depth_dev, int32_t n_ke
             make_view(*map), a, depth_dev, T0_dev, xi_dev, reinterpret_cast<const float4*>(params_dev), nullptr,
             assoc_dev, nullptr, (double*)scratch);
     }
-    k_keyframe_finish<<<n_keyframes, 64, 0, s>>>(a, xi_dev, (const double*)scratch, loss_dev, nullptr, count_dev);
+    k_keyframe_finish<<<n_keyframes, 256, 0, s>>>(a, xi_dev, (const double*)scratch, loss_dev, nullptr, count_dev);
     return launch_status();
 }
 
@@ -373,7 +385,7 @@ int gsdf_keyframe_backward(const gsdf_map* map, const float* depth_dev, int32_t 
             make_view(*map), a, depth_dev, T0_dev, xi_dev, reinterpret_cast<const float4*>(params_dev),
             grad_loss_dev, assoc_dev, dparams_dev, (double*)scratch);
     }
-    k_keyframe_finish<<<n_keyframes, 64, 0, s>>>(a, xi_dev, (const double*)scratch, loss_dev, dxi_dev, nullptr);
+    k_keyframe_finish<<<n_keyframes, 256, 0, s>>>(a, xi_dev, (const double*)scratch, loss_dev, dxi_dev, nullptr);
     return launch_status();
 }
 
