@@ -85,6 +85,7 @@ def _load():
         "orc_round_storage": (_D, [_D, _I]),
         "orc_photo_loss_grad": (_D, [_P, _I, _P, _P, _P, _P, _P, _P, _I64, _P, _D, _D, _P, _P, _P, _P, _P]),
         "orc_mean_color": (None, [_P, _I, _P, _P, _P, _P, _P, _P, _I64, _P, _P]),
+        "orc_photo_energy": (_D, [_P, _I, _P, _P, _P, _P, _P, _P, _I64, _D, _D, _I, _P, _P, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -280,6 +281,23 @@ class OracleMap:
                                _ptr(_c(T0, np.float64)), _ptr(_c(xi, np.float64)), _ptr(keys), nk, _ptr(col),
                                _ptr(cnt))
         return col, cnt
+
+    def photo_energy(self, depths: np.ndarray, rgb: np.ndarray, cam, T0, xi, delta: float, lam: float = 1.0,
+                     coupled: bool = True, keys: Optional[np.ndarray] = None, want_grads: bool = True):
+        """Implicit photometric BA energy against each voxel's own mean colour
+        (Eq. (17) coupled, Eq. (20) decoupled).  Returns (loss per keyframe,
+        dpsi, dxi)."""
+        K = depths.shape[0]
+        c = cam_struct(cam)
+        keys = self.keys() if keys is None else _c(keys, np.int32).reshape(-1, 3)
+        nk = len(keys)
+        loss = np.zeros(K)
+        dpsi = np.zeros((nk, 512)) if want_grads else None
+        dxi = np.zeros((K, 6)) if want_grads else None
+        _load().orc_photo_energy(self._h, K, _ptr(_c(depths, np.float64)), _ptr(_c(rgb, np.float64)), C.byref(c),
+                                 _ptr(_c(T0, np.float64)), _ptr(_c(xi, np.float64)), _ptr(keys), nk, float(delta),
+                                 float(lam), 1 if coupled else 0, _ptr(loss), _ptr(dpsi), _ptr(dxi))
+        return loss, dpsi, dxi
 
     def render_taylor(self, cam, T, smin: float = 0.05, smax: float = 10.0) -> np.ndarray:
         out = np.zeros((cam.height, cam.width))

@@ -1196,3 +1196,107 @@ void orc_mean_color(const OrcMap* M, int K, const double* depth, const double* r
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Implicit photometric bundle-adjustment energy (Sec. 4.2 Eq. (17)-(21)),
+// without stored colour: each surface voxel's residuals are taken against
+// the mean of its own samples over the keyframes that see it,
+//   E = lambda sum_{i,j,c} nu_ij Phi(I_ij^c - (1/N_j) sum_k nu_kj I_kj^c),
+// Phi the Huber penalty, surface points, visibility and samples as in
+// orc_photo_loss_grad.  coupled = 1 differentiates through the mean
+// (Eq. (17)); coupled = 0 holds the mean fixed (the decoupled Eq. (20)).
+// With Phi' the Huber derivative, sample (i, j) contributes with weight
+// Phi'(r_ij) - [coupled] (1/N_j) sum_k Phi'(r_kj) on dI_ij.  loss_kf gets
+// each keyframe's share; gradients (optional, overwritten) as
+// orc_photo_loss_grad (dpsi per keys order, dxi through Jl^T).
+// ---------------------------------------------------------------------------
+extern "C" double orc_photo_energy(const OrcMap* M, int K, const double* depth, const double* rgb,
+                                   const OrcCam* cam, const double* T0, const double* xi, const int32_t* keys,
+                                   int64_t nkeys, double delta, double lambda, int coupled, double* loss_kf,
+                                   double* dpsi, double* dxi) {
+    const size_t npx = (size_t)cam->width * cam->height;
+    std::vector<double> T((size_t)12 * K), gl((size_t)6 * K, 0.0);
+    for (int i = 0; i < K; ++i) {
+        double E[12];
+        se3_exp(xi + 6 * i, E);
+        std::memcpy(&T[12 * i], T0 + 12 * i, 12 * sizeof(double));
+        compose_left(E, &T[12 * i]);
+        loss_kf[i] = 0.0;
+    }
+    if (dpsi) std::fill(dpsi, dpsi + nkeys * kBV, 0.0);
+    struct Sample {
+        int i;
+        PhotoSample S;
+        double I[3], dIu[3], dIv[3];
+    };
+    std::vector<Sample> smp;
+    for (int64_t b = 0; b < nkeys; ++b) {
+        const Block* B = find_block(M, keys[3 * b], keys[3 * b + 1], keys[3 * b + 2]);
+        if (!B) continue;
+        for (int c = 0; c < kBV; ++c) {
+            const Voxel& V = B->v[c];
+            double gh[3];
+            if (!photo_surface(V, M->vs, gh)) continue;
+            int m[3] = {8 * keys[3 * b] + c % 8, 8 * keys[3 * b + 1] + (c / 8) % 8, 8 * keys[3 * b + 2] + c / 64};
+            double p[3];
+            for (int k = 0; k < 3; ++k) p[k] = M->vs * m[k] - V.psi * gh[k];
+            smp.clear();
+            for (int i = 0; i < K; ++i) {
+                Sample s;
+                s.i = i;
+                if (!photo_visible(*cam, depth + i * npx, &T[12 * i], p, gh, M->T, &s.S)) continue;
+                bilinear3(rgb + 3 * i * npx, *cam, s.S.u, s.S.v, s.I, s.dIu, s.dIv);
+                smp.push_back(s);
+            }
+            const double N = (double)smp.size();
+            if (smp.empty()) continue;
+            double mean[3] = {0, 0, 0};
+            for (const Sample& s : smp)
+                for (int ch = 0; ch < 3; ++ch) mean[ch] += s.I[ch];
+            for (int ch = 0; ch < 3; ++ch) mean[ch] /= N;
+            double mphi[3] = {0, 0, 0};   // mean of Phi' over the samples, per channel
+            for (const Sample& s : smp)
+                for (int ch = 0; ch < 3; ++ch) {
+                    double r = s.I[ch] - mean[ch];
+                    mphi[ch] += huber_weight(r, delta) * r / N;
+                }
+            for (const Sample& s : smp) {
+                double eu = 0, ev = 0;
+                for (int ch = 0; ch < 3; ++ch) {
+                    double r = s.I[ch] - mean[ch];
+                    loss_kf[s.i] += lambda * huber_rho(r, delta);
+                    double wgt = lambda * (huber_weight(r, delta) * r - (coupled ? mphi[ch] : 0.0));
+                    eu += wgt * s.dIu[ch];
+                    ev += wgt * s.dIv[ch];
+                }
+                const double* Ti = &T[12 * s.i];
+                double gx[3] = {eu * cam->fx / s.S.z, ev * cam->fy / s.S.z,
+                                -(eu * cam->fx * s.S.x[0] + ev * cam->fy * s.S.x[1]) / (s.S.z * s.S.z)};
+                double a[3];
+                for (int r = 0; r < 3; ++r) a[r] = Ti[4 * r] * gx[0] + Ti[4 * r + 1] * gx[1] + Ti[4 * r + 2] * gx[2];
+                if (dpsi) dpsi[b * kBV + c] -= a[0] * gh[0] + a[1] * gh[1] + a[2] * gh[2];
+                double* g6 = &gl[6 * s.i];
+                g6[0] -= a[0];
+                g6[1] -= a[1];
+                g6[2] -= a[2];
+                g6[3] += a[1] * p[2] - a[2] * p[1];
+                g6[4] += a[2] * p[0] - a[0] * p[2];
+                g6[5] += a[0] * p[1] - a[1] * p[0];
+            }
+        }
+    }
+    if (dxi) {
+        for (int i = 0; i < K; ++i) {
+            double Jl[36];
+            se3_left_jacobian(xi + 6 * i, Jl);
+            for (int q = 0; q < 6; ++q) {
+                double s = 0;
+                for (int k = 0; k < 6; ++k) s += Jl[6 * k + q] * gl[6 * i + k];
+                dxi[6 * i + q] = s;
+            }
+        }
+    }
+    double L = 0;
+    for (int i = 0; i < K; ++i) L += loss_kf[i];
+    return L;
+}

@@ -152,3 +152,59 @@ def test_photometric_gradients_match_central_differences(setup):
         B.set_voxels(keys, pm, g, W)
         fd = (f(mm=A) - f(mm=B)) / (2 * h)
         assert dpsi[b, j] == pytest.approx(fd, rel=1e-5, abs=1e-9)
+
+
+def test_implicit_energy_is_the_stored_colour_loss_at_the_mean(setup):
+    """Eq. (17) against each voxel's mean (Eq. (21)) equals the stored-colour
+    loss evaluated at the mean colours; for the quadratic penalty the
+    coupled (Eq. (17)) and decoupled (Eq. (20)) gradients coincide, because
+    a voxel's residuals about their own mean sum to zero."""
+    st, M = setup
+    keys = M.keys()
+    idx = [3, 4, 5]
+    D, I = st.depth[idx].astype(np.float64), st.rgb[idx].astype(np.float64)
+    xi = np.random.default_rng(7).standard_normal((3, 6)) * 1e-3
+    mean, _ = M.mean_color(D, I, CAM, st.poses[idx], xi, keys)
+    for delta in (0.02, 1e6):
+        Le, _, _ = M.photo_energy(D, I, CAM, st.poses[idx], xi, delta, 0.5, True, keys, want_grads=False)
+        Ls = M.photo_loss_grad(D, I, CAM, st.poses[idx], xi, mean, delta, 0.5, keys, want_grads=False)[0]
+        np.testing.assert_allclose(Le, Ls, rtol=1e-12)
+    _, pc, xc = M.photo_energy(D, I, CAM, st.poses[idx], xi, 1e6, 1.0, True, keys)
+    _, pd, xd = M.photo_energy(D, I, CAM, st.poses[idx], xi, 1e6, 1.0, False, keys)
+    np.testing.assert_allclose(xc, xd, rtol=1e-9, atol=1e-12 * np.abs(xd).max())
+    np.testing.assert_allclose(pc, pd, rtol=1e-9, atol=1e-12 * np.abs(pd).max())
+    # with the Huber penalty the mean's own dependence matters
+    _, pc, xc = M.photo_energy(D, I, CAM, st.poses[idx], xi, 0.005, 1.0, True, keys)
+    _, pd, xd = M.photo_energy(D, I, CAM, st.poses[idx], xi, 0.005, 1.0, False, keys)
+    assert np.abs(xc - xd).max() > 1e-6 * np.abs(xd).max()
+
+
+def test_coupled_energy_gradients_match_central_differences(setup):
+    st, M = setup
+    keys = M.keys()
+    idx = [3, 5]
+    D, I = st.depth[idx].astype(np.float64), st.rgb[idx].astype(np.float64)
+    xi = np.random.default_rng(8).standard_normal((2, 6)) * 1e-3
+    delta = 0.005
+    _, dpsi, dxi = M.photo_energy(D, I, CAM, st.poses[idx], xi, delta, 1.0, True, keys)
+    f = lambda x=xi, mm=M: mm.photo_energy(D, I, CAM, st.poses[idx], x, delta, 1.0, True, keys,
+                                           want_grads=False)[0].sum()
+    h = 1e-7   # bilinear samples and the Huber penalty are only piecewise smooth
+    for i in range(2):
+        for k in range(6):
+            e = np.zeros_like(xi)
+            e[i, k] = h
+            fd = (f(x=xi + e) - f(x=xi - e)) / (2 * h)
+            assert dxi[i, k] == pytest.approx(fd, rel=1e-5, abs=1e-6 * np.abs(dxi).max())
+    psi, g, W, _ = M.voxels(keys)
+    h = 1e-6
+    for b, j in np.argwhere(np.abs(dpsi) > 1e-3 * np.abs(dpsi).max())[:4]:
+        pp, pm = psi.copy(), psi.copy()
+        pp[b, j] += h
+        pm[b, j] -= h
+        A = oracle.OracleMap(VS, TR)
+        A.set_voxels(keys, pp, g, W)
+        B = oracle.OracleMap(VS, TR)
+        B.set_voxels(keys, pm, g, W)
+        fd = (f(mm=A) - f(mm=B)) / (2 * h)
+        assert dpsi[b, j] == pytest.approx(fd, rel=1e-5, abs=1e-9)
