@@ -303,6 +303,29 @@ int gsdf_mean_color(const gsdf_map* map, const float* depth_dev, const float* rg
                     const float* params_dev, int64_t param_blocks, float* colors_out_dev,
                     float* count_out_dev, void* scratch_dev, size_t scratch_bytes, void* stream);
 
+/* Adjoint of gsdf_mean_color (Sec. 4.2 Eq. (21) differentiated, g^ held
+ * fixed): given the upstream gradient G_j of the mean colours
+ * (grad_colors_dev, param_blocks x 512 x 3) and the view counts N_j of the
+ * forward call (counts_dev, param_blocks x 512), each view (i, j) adds
+ * (G_j / N_j) . dI_ij: to dparams[j].psi (+=, one writer per voxel) and to
+ * dxi_dev[i] (K x 6 float64, overwritten, through Jl(xi_i)^T).  Composed
+ * with gsdf_photometric_backward at the mean colours this gives the
+ * gradient of the coupled bundle-adjustment energy of Sec. 4.2 Eq. (17). */
+int gsdf_mean_color_backward(const gsdf_map* map, const float* depth_dev, const float* rgb_dev,
+                             int32_t n_keyframes, const gsdf_camera* cam, const double* T0_dev,
+                             const double* xi_dev, const float* params_dev, int64_t param_blocks,
+                             const float* grad_colors_dev, const float* counts_dev, float* dparams_dev,
+                             double* dxi_dev, void* scratch_dev, size_t scratch_bytes, void* stream);
+
+/* Regulariser of the bundle adjustment (Sec. 5 experiments): loss_dev (one
+ * float64) = weight * sum over observed voxels of (psi_j - psi0_j)^2, with
+ * params and params0 as for gsdf_export_params; dparams_dev (optional) gets
+ * 2 weight (psi_j - psi0_j) added to its psi entries.  scratch_dev holds at
+ * least param_blocks float64. */
+int gsdf_psi_regulariser(const gsdf_map* map, const float* params_dev, const float* params0_dev,
+                         int64_t param_blocks, float weight, double* loss_dev, float* dparams_dev,
+                         void* scratch_dev, size_t scratch_bytes, void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* Inspection, import (used for parity checks and checkpoints)             */
 /* ---------------------------------------------------------------------- */

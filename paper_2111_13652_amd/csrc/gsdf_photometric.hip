@@ -115,7 +115,10 @@ __device__ inline void bilinear3(const float* __restrict__ img, int W, double u,
     }
 }
 
-// MODE 0: loss only; 1: loss and gradients; 2: mean colour (Eq. (21)).
+// MODE 0: loss only; 1: loss and gradients; 2: mean colour (Eq. (21));
+// 3: adjoint of the mean colour: with the upstream gradient G_j (in
+// `colors`) and the view counts N_j (in `counts`), each sample adds
+// (G_j / N_j) . dI_ij to the psi and pose gradients (g^ held fixed).
 template <int MODE>
 __global__ __launch_bounds__(kPhotoBlock) void k_photometric(MapView M, PhotoArgs a, const float* __restrict__ depth,
                                                             const float* __restrict__ rgb,
@@ -126,6 +129,7 @@ __global__ __launch_bounds__(kPhotoBlock) void k_photometric(MapView M, PhotoArg
                                                             float* __restrict__ dparams, float* __restrict__ dcolors,
                                                             float* __restrict__ out_colors,
                                                             float* __restrict__ out_count,
+                                                            const float* __restrict__ counts,
                                                             double* __restrict__ partials) {
     __shared__ double s_red[kPhotoPart][kPhotoBlock / 64];
     __shared__ int s_any;
@@ -135,6 +139,16 @@ __global__ __launch_bounds__(kPhotoBlock) void k_photometric(MapView M, PhotoArg
     for (int h = 0; h < 2; ++h) {
         V[h].ok = false;
         if (slot < nb) photo_voxel(M, a, params, MODE == 2 ? nullptr : colors, slot, threadIdx.x + h * kPhotoBlock, &V[h]);
+        if (MODE == 3 && V[h].ok) {
+            // upstream gradient per sample of the mean: G_j / N_j
+            const float n = counts[slot * kBlockVoxels + threadIdx.x + h * kPhotoBlock];
+            if (n > 0.0f) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) V[h].rho[c] /= n;
+            } else {
+                V[h].ok = false;
+            }
+        }
     }
     if (threadIdx.x == 0) s_any = 0;
     __syncthreads();
@@ -168,8 +182,15 @@ __global__ __launch_bounds__(kPhotoBlock) void k_photometric(MapView M, PhotoArg
                     continue;
                 }
                 float eu = 0.0f, ev = 0.0f;
+                if (MODE == 3) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
+                    for (int c = 0; c < 3; ++c) {
+                        eu += V[h].rho[c] * dIu[c];
+                        ev += V[h].rho[c] * dIv[c];
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 3 && MODE != 3; ++c) {
                     const float r = I[c] - V[h].rho[c];
                     const float ar = fabsf(r);
                     const bool quad = ar <= a.delta;
@@ -181,7 +202,7 @@ __global__ __launch_bounds__(kPhotoBlock) void k_photometric(MapView M, PhotoArg
                         ev += rp * dIv[c];
                     }
                 }
-                if (MODE == 1) {
+                if (MODE == 1 || MODE == 3) {
                     const float iz = (float)(1.0 / P.z);
                     const float fx = (float)a.fx, fy = (float)a.fy;
                     const float x0 = (float)P.x[0], x1 = (float)P.x[1];
@@ -229,6 +250,8 @@ __global__ __launch_bounds__(kPhotoBlock) void k_photometric(MapView M, PhotoArg
             dparams[4 * vi] += gpsi[h];
 #pragma unroll
             for (int c = 0; c < 3; ++c) dcolors[3 * vi + c] += grho[h][c];
+        } else if (MODE == 3 && V[h].ok) {
+            dparams[4 * vi] += gpsi[h];
         }
     }
 }
@@ -334,7 +357,8 @@ static void photo_launch(int mode, const gsdf_map* map, const float* depth, cons
                          const gsdf_camera* cam, const double* T0, const double* xi, const float* params,
                          const float* colors, int64_t param_blocks, float delta, float lambda, const float* gscale,
                          float* dparams, float* dcolors, float* out_colors, float* out_count, double* loss_out,
-                         double* count_out, double* dxi_out, void* scratch, hipStream_t s) {
+                         double* count_out, double* dxi_out, void* scratch, hipStream_t s,
+                         const float* counts = nullptr) {
     const PhotoArgs a = photo_args(*map, *cam, K, param_blocks, delta, lambda);
     const PhotoScratch L = photo_scratch(param_blocks, K);
     double* poses = (double*)((char*)scratch + L.poses);
@@ -346,16 +370,57 @@ static void photo_launch(int mode, const gsdf_map* map, const float* depth, cons
         TimedLaunch tl(GSDF_K_PHOTOMETRIC, s);
         if (mode == 0)
             k_photometric<0><<<(unsigned)param_blocks, kPhotoBlock, 0, s>>>(
-                M, a, depth, rgb, poses, P, colors, nullptr, nullptr, nullptr, nullptr, nullptr, partials);
+                M, a, depth, rgb, poses, P, colors, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, partials);
         else if (mode == 1)
             k_photometric<1><<<(unsigned)param_blocks, kPhotoBlock, 0, s>>>(
-                M, a, depth, rgb, poses, P, colors, gscale, dparams, dcolors, nullptr, nullptr, partials);
-        else
+                M, a, depth, rgb, poses, P, colors, gscale, dparams, dcolors, nullptr, nullptr, nullptr, partials);
+        else if (mode == 2)
             k_photometric<2><<<(unsigned)param_blocks, kPhotoBlock, 0, s>>>(
-                M, a, depth, rgb, poses, P, nullptr, nullptr, nullptr, nullptr, out_colors, out_count, partials);
+                M, a, depth, rgb, poses, P, nullptr, nullptr, nullptr, nullptr, out_colors, out_count, nullptr,
+                partials);
+        else
+            k_photometric<3><<<(unsigned)param_blocks, kPhotoBlock, 0, s>>>(
+                M, a, depth, rgb, poses, P, colors, nullptr, dparams, nullptr, nullptr, nullptr, counts, partials);
     }
     if (mode != 2)
         k_photometric_finish<<<K, 256, 0, s>>>(a, xi, partials, loss_out, count_out, dxi_out);
+}
+
+// Quadratic regulariser of the distances towards reference values
+// (lambda sum_j (psi_j - psi0_j)^2 over observed voxels), used with the
+// bundle-adjustment energy; one work-group per map block.
+__global__ __launch_bounds__(256) void k_psi_regulariser(MapView M, int64_t param_blocks, const float4* __restrict__ params,
+                                                         const float4* __restrict__ params0, float lambda,
+                                                         float* __restrict__ dparams, double* __restrict__ partials) {
+    __shared__ double s_red[4];
+    const int64_t slot = blockIdx.x;
+    const int32_t nb = M.counters[kNumBlocks] < M.max_blocks ? M.counters[kNumBlocks] : M.max_blocks;
+    double e = 0.0;
+    for (int c = threadIdx.x; c < kBlockVoxels; c += 256) {
+        const int64_t vi = slot * kBlockVoxels + c;
+        if (slot >= nb || !(M.weight[vi] > 0.0f)) continue;
+        const float d = params[vi].x - params0[vi].x;
+        e += (double)(lambda * d * d);
+        if (dparams) dparams[4 * vi] += 2.0f * lambda * d;
+    }
+    for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[slot] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partials, int64_t n,
+                                                      double* __restrict__ out) {
+    __shared__ double s[256];
+    double x = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) x += partials[i];
+    s[threadIdx.x] = x;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
 }
 
 int gsdf_photometric_loss(const gsdf_map* map, const float* depth_dev, const float* rgb_dev, int32_t n_keyframes,
@@ -388,6 +453,39 @@ int gsdf_photometric_backward(const gsdf_map* map, const float* depth_dev, const
     photo_launch(1, map, depth_dev, rgb_dev, n_keyframes, cam, T0_dev, xi_dev, params_dev, colors_dev,
                  param_blocks, huber_delta, weight, grad_loss_dev, dparams_dev, dcolors_dev, nullptr, nullptr,
                  loss_dev, nullptr, dxi_dev, scratch_dev, (hipStream_t)stream);
+    return launch_status();
+}
+
+int gsdf_mean_color_backward(const gsdf_map* map, const float* depth_dev, const float* rgb_dev,
+                             int32_t n_keyframes, const gsdf_camera* cam, const double* T0_dev,
+                             const double* xi_dev, const float* params_dev, int64_t param_blocks,
+                             const float* grad_colors_dev, const float* counts_dev, float* dparams_dev,
+                             double* dxi_dev, void* scratch_dev, size_t scratch_bytes, void* stream) {
+    int rc = photo_check(map, depth_dev, rgb_dev, n_keyframes, cam, T0_dev, xi_dev, params_dev, param_blocks,
+                         scratch_dev, scratch_bytes);
+    if (rc != GSDF_OK) return rc;
+    if (!grad_colors_dev || !counts_dev || !dparams_dev || !dxi_dev) return GSDF_EINVAL;
+    photo_launch(3, map, depth_dev, rgb_dev, n_keyframes, cam, T0_dev, xi_dev, params_dev, grad_colors_dev,
+                 param_blocks, 1.0f, 1.0f, nullptr, dparams_dev, nullptr, nullptr, nullptr, nullptr, nullptr,
+                 dxi_dev, scratch_dev, (hipStream_t)stream, counts_dev);
+    return launch_status();
+}
+
+int gsdf_psi_regulariser(const gsdf_map* map, const float* params_dev, const float* params0_dev,
+                         int64_t param_blocks, float weight, double* loss_dev, float* dparams_dev,
+                         void* scratch_dev, size_t scratch_bytes, void* stream) {
+    if (!valid_map(map) || !params_dev || !params0_dev || !loss_dev || param_blocks < 0 ||
+        param_blocks > map->desc.max_blocks || !(weight >= 0.0f) || !scratch_dev ||
+        scratch_bytes < (size_t)(param_blocks > 0 ? param_blocks : 1) * sizeof(double))
+        return GSDF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    double* partials = (double*)scratch_dev;
+    if (param_blocks > 0)
+        k_psi_regulariser<<<(unsigned)param_blocks, 256, 0, s>>>(make_view(*map), param_blocks,
+                                                                 reinterpret_cast<const float4*>(params_dev),
+                                                                 reinterpret_cast<const float4*>(params0_dev),
+                                                                 weight, dparams_dev, partials);
+    k_sum_partials<<<1, 256, 0, s>>>(partials, param_blocks, loss_dev);
     return launch_status();
 }
 

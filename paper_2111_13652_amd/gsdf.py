@@ -424,6 +424,125 @@ class PhotometricLoss(torch.autograd.Function):
                 dxi if ctx.needs_input_grad[2] else None, None, None, None, None, None, None, None)
 
 
+class MeanColor(torch.autograd.Function):
+    """Mean colour of every surface voxel over the keyframes that see it
+    (Eq. (21)), differentiable in psi (params[..., 0], g^ held fixed) and the
+    twists xi; also returns the view counts N_j (not differentiable).
+
+        colors, counts = MeanColor.apply(params, xi, gmap, depth, rgb, cam, T0)
+    """
+
+    @staticmethod
+    def forward(ctx, params, xi, gmap, depth, rgb, cam, T0):
+        col, cnt = mean_color(gmap, params, xi, depth, rgb, cam, T0)
+        ctx.save_for_backward(params, xi, cnt)
+        ctx.rest = (gmap, depth, rgb, cam, T0)
+        ctx.mark_non_differentiable(cnt)
+        return col, cnt
+
+    @staticmethod
+    def backward(ctx, grad_col, grad_cnt):
+        params, xi, cnt = ctx.saved_tensors
+        gmap, depth, rgb, cam, T0 = ctx.rest
+        c, K, scratch = _photo_args(gmap, depth, rgb, cam, T0, xi, params, None)
+        g = grad_col.to(torch.float32).contiguous() if grad_col is not None else torch.zeros(
+            (params.shape[0], 512, 3), dtype=torch.float32, device=params.device)
+        dparams = torch.zeros_like(params)
+        dxi = torch.empty_like(xi)
+        _lib.check(_lib.load().gsdf_mean_color_backward(
+            C.byref(gmap._map), _ptr(depth), _ptr(rgb), K, C.byref(c), _ptr(T0), _ptr(xi.detach().contiguous()),
+            _ptr(params.detach().contiguous()), int(params.shape[0]), _ptr(g), _ptr(cnt), _ptr(dparams), _ptr(dxi),
+            _ptr(scratch), scratch.numel(), _stream()), "mean_color_backward")
+        return (dparams if ctx.needs_input_grad[0] else None, dxi if ctx.needs_input_grad[1] else None,
+                None, None, None, None, None)
+
+
+def implicit_photometric_loss(gmap: GsdfMap, params: torch.Tensor, xi: torch.Tensor, depth: torch.Tensor,
+                              rgb: torch.Tensor, cam, T0: torch.Tensor, delta: float = 0.1, weight: float = 1.0,
+                              coupled: bool = True) -> torch.Tensor:
+    """Bundle-adjustment energy of Sec. 4.2 without stored colour: every
+    surface voxel's residuals are taken against its own mean colour.
+    coupled=True differentiates through the mean (Eq. (17)); coupled=False
+    holds it fixed (the decoupled per-pose energies of Eq. (20)).  Returns
+    the per-keyframe shares (K float64)."""
+    if coupled:
+        col, _ = MeanColor.apply(params, xi, gmap, depth, rgb, cam, T0)
+    else:
+        col, _ = mean_color(gmap, params.detach(), xi.detach(), depth, rgb, cam, T0)
+    return PhotometricLoss.apply(params, col, xi, gmap, depth, rgb, cam, T0, delta, weight)
+
+
+class PsiRegulariser(torch.autograd.Function):
+    """weight * sum_j (psi_j - psi0_j)^2 over observed voxels (scalar)."""
+
+    @staticmethod
+    def forward(ctx, params, params0, gmap, weight):
+        n = int(params.shape[0])
+        scratch = torch.empty(max(n, 1), dtype=torch.float64, device=params.device)
+        loss = torch.empty((), dtype=torch.float64, device=params.device)
+        _lib.check(_lib.load().gsdf_psi_regulariser(C.byref(gmap._map), _ptr(params.detach().contiguous()),
+                                                     _ptr(params0), n, float(weight), _ptr(loss), None,
+                                                     _ptr(scratch), scratch.numel() * 8, _stream()), "psi_regulariser")
+        ctx.save_for_backward(params, params0)
+        ctx.rest = (gmap, weight)
+        return loss
+
+    @staticmethod
+    def backward(ctx, grad):
+        params, params0 = ctx.saved_tensors
+        gmap, weight = ctx.rest
+        n = int(params.shape[0])
+        scratch = torch.empty(max(n, 1), dtype=torch.float64, device=params.device)
+        loss = torch.empty((), dtype=torch.float64, device=params.device)
+        dparams = torch.zeros_like(params)
+        _lib.check(_lib.load().gsdf_psi_regulariser(C.byref(gmap._map), _ptr(params.detach().contiguous()),
+                                                     _ptr(params0), n, float(weight), _ptr(loss), _ptr(dparams),
+                                                     _ptr(scratch), scratch.numel() * 8, _stream()), "psi_regulariser")
+        return dparams * grad.to(torch.float32), None, None, None
+
+
+def photometric_ba(gmap: GsdfMap, depth: torch.Tensor, rgb: torch.Tensor, cam, T0: torch.Tensor, steps: int = 50,
+                   delta: float = 0.1, coupled: bool = True, optimise_psi: bool = True,
+                   reg_weight: float = 100.0, lr_pose: float = 2e-3, lr_psi: float = 2e-5,
+                   fix_first: bool = True, write_back: bool = False):
+    """Implicit photometric bundle adjustment (Sec. 4.2): Adam on the
+    keyframe poses (camera-frame variables) and, unless optimise_psi is
+    False (the pose-only variant), on the distances psi, minimising the
+    Eq. (17) (coupled) or Eq. (20) (decoupled) energy plus
+    reg_weight sum_j (psi_j - psi0_j)^2 (100 m^-2 = 0.01 cm^-2).  The energy
+    compares the keyframes with each other, so a motion common to all of
+    them is (nearly) free: with fix_first the first keyframe anchors the
+    gauge and keeps its pose.  Returns (poses (K,3,4), params, losses)."""
+    K = depth.shape[0]
+    params0 = gmap.export_params().detach()
+    params = params0.clone().requires_grad_(optimise_psi)
+    ad = adjoint_se3(T0)
+    xc = torch.zeros((K, 6), dtype=torch.float64, device=depth.device, requires_grad=True)
+    mask = torch.ones((K, 1), dtype=torch.float64, device=depth.device)
+    if fix_first:
+        mask[0] = 0.0
+    groups = [{"params": [xc], "lr": lr_pose}]
+    if optimise_psi:
+        groups.append({"params": [params], "lr": lr_psi})
+    opt = torch.optim.Adam(groups)
+    sched = torch.optim.lr_scheduler.CosineAnnealingLR(opt, steps)
+    losses = []
+    for _ in range(steps):
+        opt.zero_grad(set_to_none=True)
+        xi = (ad @ (mask * xc).unsqueeze(-1)).squeeze(-1)
+        loss = implicit_photometric_loss(gmap, params, xi, depth, rgb, cam, T0, delta, 1.0, coupled).sum()
+        if optimise_psi and reg_weight > 0:
+            loss = loss + PsiRegulariser.apply(params, params0, gmap, reg_weight)
+        loss.backward()
+        opt.step()
+        sched.step()
+        losses.append(loss.detach())
+    poses = compose_left((ad @ (mask * xc.detach()).unsqueeze(-1)).squeeze(-1), T0)
+    if write_back:
+        gmap.import_params(params.detach())
+    return poses, params.detach(), torch.stack(losses).cpu().numpy()
+
+
 def refine_joint(gmap: GsdfMap, depth: torch.Tensor, rgb: torch.Tensor, cam, T0: torch.Tensor,
                  steps: int = 50, delta: float = 0.01, photo_delta: float = 0.1, photo_weight: float = 0.01,
                  lr_psi: float = 2e-5, lr_color: float = 1e-2, pose_solver: str = "gn", lr_pose: float = 4e-3,
