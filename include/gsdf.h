@@ -327,6 +327,26 @@ int gsdf_psi_regulariser(const gsdf_map* map, const float* params_dev, const flo
                          void* scratch_dev, size_t scratch_bytes, void* stream);
 
 /* ---------------------------------------------------------------------- */
+/* Surface extraction                                                       */
+/* ---------------------------------------------------------------------- */
+
+/* Scratch bytes of gsdf_extract_surfels for this map. */
+size_t gsdf_surfel_scratch_bytes(const gsdf_map* map);
+
+/* Oriented point cloud (Sec. 4.3): every observed voxel whose surface point
+ * v - psi g^ lies in its cell (|psi g^_k| <= v_s/2 for each axis) gives that
+ * point with normal -g^ (level 0); level 1 splits each voxel into 2x2x2
+ * subvoxels, takes their distance from the Taylor expansion
+ * psi + g^ . (s - v) and keeps those with |psi(s) g^_k| <= v_s/4.  Order:
+ * block slot, voxel lx + 8 ly + 64 lz, subvoxel sx + 2 sy + 4 sz.  Writes
+ * min(count, capacity) surfels: points_dev / normals_dev (n x 3 float32),
+ * ids_dev (n x 4 int32: voxel coordinates and subvoxel), and the full count
+ * to *count_dev (int64, device); capacity 0 only counts. */
+int gsdf_extract_surfels(const gsdf_map* map, int32_t level, float* points_dev, float* normals_dev,
+                         int32_t* ids_dev, int64_t capacity, int64_t* count_dev, void* scratch_dev,
+                         size_t scratch_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Inspection, import (used for parity checks and checkpoints)             */
 /* ---------------------------------------------------------------------- */
 

@@ -85,6 +85,7 @@ def _load():
         "orc_round_storage": (_D, [_D, _I]),
         "orc_photo_loss_grad": (_D, [_P, _I, _P, _P, _P, _P, _P, _P, _I64, _P, _D, _D, _P, _P, _P, _P, _P]),
         "orc_mean_color": (None, [_P, _I, _P, _P, _P, _P, _P, _P, _I64, _P, _P]),
+        "orc_extract_surfels": (_I64, [_P, _P, _I64, _I, _P, _P, _P, _I64]),
         "orc_photo_energy": (_D, [_P, _I, _P, _P, _P, _P, _P, _P, _I64, _D, _D, _I, _P, _P, _P]),
     }
     for name, (res, args) in sig.items():
@@ -298,6 +299,18 @@ class OracleMap:
                                  _ptr(_c(T0, np.float64)), _ptr(_c(xi, np.float64)), _ptr(keys), nk, float(delta),
                                  float(lam), 1 if coupled else 0, _ptr(loss), _ptr(dpsi), _ptr(dxi))
         return loss, dpsi, dxi
+
+    def surfels(self, level: int = 0, keys: Optional[np.ndarray] = None):
+        """Oriented point cloud of Sec. 4.3 (level 1: 2x2x2 upsampled).
+        Returns (points (n,3), normals (n,3), ids (n,4): voxel + subvoxel)."""
+        keys = self.keys() if keys is None else _c(keys, np.int32).reshape(-1, 3)
+        lib = _load()
+        n = int(lib.orc_extract_surfels(self._h, _ptr(keys), len(keys), int(level), None, None, None, 0))
+        pts = np.zeros((n, 3))
+        nrm = np.zeros((n, 3))
+        ids = np.zeros((n, 4), np.int32)
+        lib.orc_extract_surfels(self._h, _ptr(keys), len(keys), int(level), _ptr(pts), _ptr(nrm), _ptr(ids), n)
+        return pts, nrm, ids
 
     def render_taylor(self, cam, T, smin: float = 0.05, smax: float = 10.0) -> np.ndarray:
         out = np.zeros((cam.height, cam.width))

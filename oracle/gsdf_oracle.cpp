@@ -1300,3 +1300,59 @@ extern "C" double orc_photo_energy(const OrcMap* M, int K, const double* depth, 
     for (int i = 0; i < K; ++i) L += loss_kf[i];
     return L;
 }
+
+// ---------------------------------------------------------------------------
+// Oriented point cloud (Sec. 4.3): every observed voxel whose surface point
+// lies inside its cell, |psi_j gh_jk| <= v_s/2 for k = x, y, z, gives the
+// point v_j - psi_j gh_j with normal -gh_j (outwards: gh points into the
+// solid).  Upsampled (level 1): each voxel is split into 2x2x2 subvoxels
+// with centres s = v_j + (v_s/4)(+-1, +-1, +-1); the Taylor expansion
+// psi(s) = psi_j + gh_j . (s - v_j) gives their distance, and subvoxels with
+// |psi(s) gh_jk| <= v_s/4 give s - psi(s) gh_j.  Subvoxel index
+// sx + 2 sy + 4 sz (s? = 1 for the + side).  Output in the order of `keys`,
+// voxel lx + 8 ly + 64 lz, then subvoxel; returns the count (arrays of
+// capacity `cap`; ids: voxel coordinates and subvoxel, 4 int32 each).
+// ---------------------------------------------------------------------------
+extern "C" int64_t orc_extract_surfels(const OrcMap* M, const int32_t* keys, int64_t nkeys, int level,
+                                       double* points, double* normals, int32_t* ids, int64_t cap) {
+    int64_t n = 0;
+    const double vs = M->vs;
+    for (int64_t b = 0; b < nkeys; ++b) {
+        const Block* B = find_block(M, keys[3 * b], keys[3 * b + 1], keys[3 * b + 2]);
+        if (!B) continue;
+        for (int c = 0; c < kBV; ++c) {
+            const Voxel& V = B->v[c];
+            const double ng = std::sqrt(V.g[0] * V.g[0] + V.g[1] * V.g[1] + V.g[2] * V.g[2]);
+            if (!(V.W > 0.0) || !(ng > 0.0)) continue;
+            const double gh[3] = {V.g[0] / ng, V.g[1] / ng, V.g[2] / ng};
+            const int m[3] = {8 * keys[3 * b] + c % 8, 8 * keys[3 * b + 1] + (c / 8) % 8, 8 * keys[3 * b + 2] + c / 64};
+            const double v[3] = {vs * m[0], vs * m[1], vs * m[2]};
+            const int nsub = level == 0 ? 1 : 8;
+            for (int sub = 0; sub < nsub; ++sub) {
+                double s[3], psi = V.psi, half = vs / 2;
+                if (level == 0) {
+                    for (int k = 0; k < 3; ++k) s[k] = v[k];
+                } else {
+                    half = vs / 4;
+                    for (int k = 0; k < 3; ++k) s[k] = v[k] + ((sub >> k) & 1 ? vs / 4 : -vs / 4);
+                    psi = V.psi + gh[0] * (s[0] - v[0]) + gh[1] * (s[1] - v[1]) + gh[2] * (s[2] - v[2]);
+                }
+                bool inside = true;
+                for (int k = 0; k < 3; ++k) inside = inside && std::fabs(psi * gh[k]) <= half;
+                if (!inside) continue;
+                if (n < cap) {
+                    for (int k = 0; k < 3; ++k) {
+                        points[3 * n + k] = s[k] - psi * gh[k];
+                        normals[3 * n + k] = -gh[k];
+                    }
+                    ids[4 * n] = m[0];
+                    ids[4 * n + 1] = m[1];
+                    ids[4 * n + 2] = m[2];
+                    ids[4 * n + 3] = level == 0 ? 0 : sub;
+                }
+                ++n;
+            }
+        }
+    }
+    return n;
+}

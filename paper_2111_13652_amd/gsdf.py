@@ -197,6 +197,27 @@ class GsdfMap:
             self._scratch[key] = torch.empty(int(n), dtype=torch.uint8, device=self.device)
         return self._scratch[key]
 
+    # ---- surface extraction ----
+    def surfels(self, level: int = 0):
+        """Oriented point cloud of Sec. 4.3 (level 1: 2x2x2 upsampled):
+        (points (n,3), normals (n,3)) float32 and ids (n,4) int32 (voxel
+        coordinates, subvoxel), device tensors."""
+        lib = _lib.load()
+        n_scr = lib.gsdf_surfel_scratch_bytes(C.byref(self._map))
+        scratch = torch.empty(int(n_scr), dtype=torch.uint8, device=self.device)
+        count = torch.zeros(1, dtype=torch.int64, device=self.device)
+        _lib.check(lib.gsdf_extract_surfels(C.byref(self._map), int(level), None, None, None, 0, _ptr(count),
+                                            _ptr(scratch), scratch.numel(), _stream()), "extract_surfels")
+        n = int(count.item())
+        pts = torch.empty((max(n, 1), 3), dtype=torch.float32, device=self.device)
+        nrm = torch.empty((max(n, 1), 3), dtype=torch.float32, device=self.device)
+        ids = torch.empty((max(n, 1), 4), dtype=torch.int32, device=self.device)
+        if n:
+            _lib.check(lib.gsdf_extract_surfels(C.byref(self._map), int(level), _ptr(pts), _ptr(nrm), _ptr(ids), n,
+                                                _ptr(count), _ptr(scratch), scratch.numel(), _stream()),
+                       "extract_surfels")
+        return pts[:n], nrm[:n], ids[:n]
+
     # ---- inspection ----
     def num_blocks(self) -> int:
         n = torch.zeros(1, dtype=torch.int32, device=self.device)
