@@ -346,6 +346,20 @@ int gsdf_extract_surfels(const gsdf_map* map, int32_t level, float* points_dev, 
                          int32_t* ids_dev, int64_t capacity, int64_t* count_dev, void* scratch_dev,
                          size_t scratch_bytes, void* stream);
 
+/* Gradient quality against a known union of spheres (Sec. 5.2, App. A).
+ * spheres_dev: n_spheres x (cx, cy, cz, r) float64, device, 1 <= n_spheres
+ * <= 64.  Per observed voxel (W > 0, g != 0) the nearest sphere surface
+ * minimises | |v - c| - r | and the true gradient of the distance is
+ * (c - v)/|c - v|.  out_dev (device, float32) receives 5 planes of `stride`
+ * values at index slot * 512 + lx + 8 ly + 64 lz: [0] distance to that
+ * surface, [1] angle (degrees) of the stored gradient, [2]-[4] angles of the
+ * forward, backward and central differences of the stored distance (step
+ * v_s; they need the six face neighbours observed); NaN where undefined.
+ * Blocks with slot >= stride / 512 are skipped; stride must be a multiple of
+ * 512.  GSDF_EINVAL on bad arguments. */
+int gsdf_gradient_quality(const gsdf_map* map, const double* spheres_dev, int32_t n_spheres, float* out_dev,
+                          int64_t stride, void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* Inspection, import (used for parity checks and checkpoints)             */
 /* ---------------------------------------------------------------------- */

@@ -86,6 +86,8 @@ def _load():
         "orc_photo_loss_grad": (_D, [_P, _I, _P, _P, _P, _P, _P, _P, _I64, _P, _D, _D, _P, _P, _P, _P, _P]),
         "orc_mean_color": (None, [_P, _I, _P, _P, _P, _P, _P, _P, _I64, _P, _P]),
         "orc_extract_surfels": (_I64, [_P, _P, _I64, _I, _P, _P, _P, _I64]),
+        "orc_fd_gradients": (None, [_P, _P, _I64, _P, _P, _P, _P]),
+        "orc_gradient_quality": (None, [_P, _P, _I64, _P, _I, _P]),
         "orc_photo_energy": (_D, [_P, _I, _P, _P, _P, _P, _P, _P, _I64, _D, _D, _I, _P, _P, _P]),
     }
     for name, (res, args) in sig.items():
@@ -311,6 +313,28 @@ class OracleMap:
         ids = np.zeros((n, 4), np.int32)
         lib.orc_extract_surfels(self._h, _ptr(keys), len(keys), int(level), _ptr(pts), _ptr(nrm), _ptr(ids), n)
         return pts, nrm, ids
+
+    def fd_gradients(self, keys: Optional[np.ndarray] = None):
+        """Forward, backward and central differences of the stored distance
+        (each (n, 512, 3)) and their validity (n, 512) bool, per voxel of
+        ``keys``, voxel order lx + 8 ly + 64 lz."""
+        keys = self.keys() if keys is None else _c(keys, np.int32).reshape(-1, 3)
+        n = len(keys)
+        f, b, c = (np.zeros((n, 512, 3)) for _ in range(3))
+        ok = np.zeros((n, 512), np.uint8)
+        _load().orc_fd_gradients(self._h, _ptr(keys), n, _ptr(f), _ptr(b), _ptr(c), _ptr(ok))
+        return f, b, c, ok.astype(bool)
+
+    def gradient_quality(self, spheres: np.ndarray, keys: Optional[np.ndarray] = None) -> np.ndarray:
+        """(5, n, 512): distance to the nearest sphere surface, then the
+        angles in degrees of the stored gradient and of the forward, backward
+        and central differences against the true gradient; NaN where
+        undefined."""
+        keys = self.keys() if keys is None else _c(keys, np.int32).reshape(-1, 3)
+        sp = _c(spheres, np.float64).reshape(-1, 4)
+        out = np.zeros((5, len(keys), 512))
+        _load().orc_gradient_quality(self._h, _ptr(keys), len(keys), _ptr(sp), len(sp), _ptr(out))
+        return out
 
     def render_taylor(self, cam, T, smin: float = 0.05, smax: float = 10.0) -> np.ndarray:
         out = np.zeros((cam.height, cam.width))

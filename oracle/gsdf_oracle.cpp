@@ -47,6 +47,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <unordered_map>
 #include <vector>
@@ -1355,4 +1356,111 @@ extern "C" int64_t orc_extract_surfels(const OrcMap* M, const int32_t* keys, int
         }
     }
     return n;
+}
+
+// ---------------------------------------------------------------------------
+// Gradient quality (Sec. 5.2, App. A): the stored gradient and finite
+// differences of the stored distance, each against the gradient of a known
+// union of spheres.
+//
+// Finite differences of psi at voxel m with step v_s along axis k:
+//   forward  (psi(m + e_k) - psi(m)) / v_s
+//   backward (psi(m) - psi(m - e_k)) / v_s
+//   central  (psi(m + e_k) - psi(m - e_k)) / (2 v_s)
+// defined when the voxel and its six face neighbours are observed (W > 0).
+// Output per voxel in the order of `keys`, voxel lx + 8 ly + 64 lz: three
+// doubles per scheme, valid[i] = 1 where defined (vectors zero elsewhere).
+// ---------------------------------------------------------------------------
+extern "C" void orc_fd_gradients(const OrcMap* M, const int32_t* keys, int64_t nkeys, double* fwd, double* bwd,
+                                 double* cen, uint8_t* valid) {
+    const double vs = M->vs;
+    for (int64_t b = 0; b < nkeys; ++b) {
+        for (int c = 0; c < kBV; ++c) {
+            const int64_t i = b * kBV + c;
+            const I3 m = {8 * keys[3 * b] + c % 8, 8 * keys[3 * b + 1] + (c / 8) % 8, 8 * keys[3 * b + 2] + c / 64};
+            valid[i] = 0;
+            for (int k = 0; k < 3; ++k) fwd[3 * i + k] = bwd[3 * i + k] = cen[3 * i + k] = 0.0;
+            const Voxel* V = find_voxel(M, m);
+            if (!V || !(V->W > 0.0)) continue;
+            const Voxel* P[3];
+            const Voxel* N[3];
+            bool ok = true;
+            for (int k = 0; k < 3; ++k) {
+                I3 p = m, n = m;
+                (k == 0 ? p.x : k == 1 ? p.y : p.z) += 1;
+                (k == 0 ? n.x : k == 1 ? n.y : n.z) -= 1;
+                P[k] = find_voxel(M, p);
+                N[k] = find_voxel(M, n);
+                ok = ok && P[k] && P[k]->W > 0.0 && N[k] && N[k]->W > 0.0;
+            }
+            if (!ok) continue;
+            valid[i] = 1;
+            for (int k = 0; k < 3; ++k) {
+                fwd[3 * i + k] = (P[k]->psi - V->psi) / vs;
+                bwd[3 * i + k] = (V->psi - N[k]->psi) / vs;
+                cen[3 * i + k] = (P[k]->psi - N[k]->psi) / (2.0 * vs);
+            }
+        }
+    }
+}
+
+namespace {
+
+// Angle between two vectors in degrees, atan2(|a x b|, a . b).
+double angle_deg(const double a[3], const double b[3]) {
+    const double x[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+    const double s = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    const double d = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+    return std::atan2(s, d) * (180.0 / M_PI);
+}
+
+}  // namespace
+
+// Per observed voxel v (W > 0, g != 0) of the map against spheres
+// (cx, cy, cz, r) x ns: the nearest sphere surface is the one minimising
+// | |v - c| - r |, the true gradient of the distance (positive inside) is
+// (c - v)/|c - v|.  out is 5 planes of nkeys*512 doubles:
+//   out[0] distance to that surface, out[1] angle of the stored gradient,
+//   out[2..4] angles of the forward, backward and central differences;
+// NaN where undefined (unobserved voxel, or a missing neighbour for [2..4]).
+extern "C" void orc_gradient_quality(const OrcMap* M, const int32_t* keys, int64_t nkeys, const double* spheres,
+                                     int ns, double* out) {
+    const int64_t nv = nkeys * kBV;
+    std::vector<double> f(3 * nv), bk(3 * nv), ce(3 * nv);
+    std::vector<uint8_t> ok(nv);
+    orc_fd_gradients(M, keys, nkeys, f.data(), bk.data(), ce.data(), ok.data());
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    const double vs = M->vs;
+    for (int64_t b = 0; b < nkeys; ++b) {
+        const Block* B = find_block(M, keys[3 * b], keys[3 * b + 1], keys[3 * b + 2]);
+        for (int c = 0; c < kBV; ++c) {
+            const int64_t i = b * kBV + c;
+            for (int q = 0; q < 5; ++q) out[q * nv + i] = nan;
+            if (!B) continue;
+            const Voxel& V = B->v[c];
+            if (!(V.W > 0.0) || !(V.g[0] != 0.0 || V.g[1] != 0.0 || V.g[2] != 0.0) || ns <= 0) continue;
+            const double v[3] = {vs * (8 * keys[3 * b] + c % 8), vs * (8 * keys[3 * b + 1] + (c / 8) % 8),
+                                 vs * (8 * keys[3 * b + 2] + c / 64)};
+            int best = 0;
+            double bd = std::numeric_limits<double>::infinity();
+            for (int s = 0; s < ns; ++s) {
+                const double* S = spheres + 4 * s;
+                const double r = std::sqrt((v[0] - S[0]) * (v[0] - S[0]) + (v[1] - S[1]) * (v[1] - S[1]) +
+                                           (v[2] - S[2]) * (v[2] - S[2]));
+                if (std::fabs(r - S[3]) < bd) {
+                    bd = std::fabs(r - S[3]);
+                    best = s;
+                }
+            }
+            const double* S = spheres + 4 * best;
+            const double gt[3] = {S[0] - v[0], S[1] - v[1], S[2] - v[2]};
+            out[i] = bd;
+            out[nv + i] = angle_deg(V.g, gt);
+            if (ok[i]) {
+                out[2 * nv + i] = angle_deg(&f[3 * i], gt);
+                out[3 * nv + i] = angle_deg(&bk[3 * i], gt);
+                out[4 * nv + i] = angle_deg(&ce[3 * i], gt);
+            }
+        }
+    }
 }

@@ -198,6 +198,29 @@ __device__ inline bool block_allowed(const MapView& M, int bx, int by, int bz) {
            bz >= M.bmin[2] && bz < M.bmax[2];
 }
 
+// Stored values of voxel vi (pool index slot*512 + morton): returns W and
+// sets psi (sum w d / W for the float32 record, psi/T times T for the
+// 16-bit pack, both in binary32) and the gradient record g (accumulated
+// normals, or their weighted mean).  psi and g are left unset when W <= 0.
+__device__ inline float load_voxel(const MapView& M, int storage, int64_t vi, float* psi, float g[3]) {
+    const float Wv = M.weight[vi];
+    if (!(Wv > 0.0f)) return Wv;
+    if (storage == GSDF_FP32) {
+        const float4 r = reinterpret_cast<const float4*>(M.vox)[vi];
+        *psi = r.x / Wv;
+        g[0] = r.y;
+        g[1] = r.z;
+        g[2] = r.w;
+    } else {
+        const ushort4 r = reinterpret_cast<const ushort4*>(M.vox)[vi];
+        *psi = unpack16(r.x, storage) * M.truncation;
+        g[0] = unpack16(r.y, storage);
+        g[1] = unpack16(r.z, storage);
+        g[2] = unpack16(r.w, storage);
+    }
+    return Wv;
+}
+
 // Pool slot of block (bx,by,bz), or -1.  Linear probing; an empty slot ends
 // the search.  Only valid after the kernel that inserted the key finished.
 __device__ inline int32_t hash_find(const MapView& M, int bx, int by, int bz) {

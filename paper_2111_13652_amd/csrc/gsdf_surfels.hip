@@ -26,27 +26,11 @@ constexpr int kSurfBlock = 256;
 
 // Stored distance and unit gradient of voxel vi; false when unobserved.
 __device__ inline bool stored_voxel(const MapView& M, int storage, int64_t vi, double* psi, double gh[3]) {
-    const float Wv = M.weight[vi];
-    if (!(Wv > 0.0f)) return false;
-    float p, g0, g1, g2;
-    if (storage == GSDF_FP32) {
-        const float4 r = reinterpret_cast<const float4*>(M.vox)[vi];
-        p = r.x / Wv;
-        g0 = r.y;
-        g1 = r.z;
-        g2 = r.w;
-    } else {
-        const ushort4 r = reinterpret_cast<const ushort4*>(M.vox)[vi];
-        p = unpack16(r.x, storage) * M.truncation;
-        g0 = unpack16(r.y, storage);
-        g1 = unpack16(r.z, storage);
-        g2 = unpack16(r.w, storage);
-    }
-    const double ng = sqrt((double)g0 * g0 + (double)g1 * g1 + (double)g2 * g2);
+    float p, g[3];
+    if (!(load_voxel(M, storage, vi, &p, g) > 0.0f)) return false;
+    const double ng = sqrt((double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2]);
     if (!(ng > 0.0)) return false;
-    gh[0] = g0 / ng;
-    gh[1] = g1 / ng;
-    gh[2] = g2 / ng;
+    for (int k = 0; k < 3; ++k) gh[k] = g[k] / ng;
     *psi = p;
     return true;
 }

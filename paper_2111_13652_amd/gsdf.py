@@ -218,6 +218,19 @@ class GsdfMap:
                        "extract_surfels")
         return pts[:n], nrm[:n], ids[:n]
 
+    def gradient_quality(self, spheres) -> "torch.Tensor":
+        """Angles of the stored gradients and of forward / backward / central
+        differences against a union of spheres (Sec. 5.2): (5, n_blocks, 512)
+        float32 on the device, planes distance to the nearest surface, then
+        angles in degrees (stored, forward, backward, central); NaN where
+        undefined.  Voxel order lx + 8 ly + 64 lz."""
+        sp = torch.as_tensor(np.ascontiguousarray(spheres, np.float64).reshape(-1, 4), device=self.device)
+        n = self.num_blocks()
+        out = torch.empty((5, max(n, 1), 512), dtype=torch.float32, device=self.device)
+        _lib.check(_lib.load().gsdf_gradient_quality(C.byref(self._map), _ptr(sp), sp.shape[0], _ptr(out),
+                                                     n * 512, _stream()), "gradient_quality")
+        return out[:, :n]
+
     # ---- inspection ----
     def num_blocks(self) -> int:
         n = torch.zeros(1, dtype=torch.int32, device=self.device)
@@ -647,3 +660,24 @@ def run_stream(m: GsdfMap, depth: torch.Tensor, cam, pose0: torch.Tensor, levels
         m.track(depth[f], cam, poses_out[f], levels=levels, iters=iters, delta=delta, damping=damping)
         m.fuse(depth[f], cam, poses_out[f])
     return poses_out
+
+
+def angle_statistics(quality, voxel_size: float, within=range(1, 11)):
+    """Mean, median and 95th percentile of each angle plane of
+    ``GsdfMap.gradient_quality`` over the voxels closer than x voxels to the
+    surface, for each x in ``within``, on the voxels where all four angles
+    are defined (a reporting helper on host copies).  Returns {x: {name:
+    (mean, median, p95)}} with names stored / forward / backward / central,
+    plus the voxel count under "n"."""
+    q = quality.detach().float().cpu().numpy().reshape(5, -1) if hasattr(quality, "detach") else \
+        np.asarray(quality, np.float64).reshape(5, -1)
+    ok = np.isfinite(q).all(axis=0)
+    out = {}
+    for x in within:
+        sel = ok & (q[0] < x * voxel_size)
+        row = {"n": int(sel.sum())}
+        for k, name in enumerate(("stored", "forward", "backward", "central")):
+            a = q[1 + k][sel]
+            row[name] = (float(a.mean()), float(np.median(a)), float(np.percentile(a, 95))) if a.size else None
+        out[x] = row
+    return out

@@ -34,7 +34,8 @@ __all__ = [
     "depth_noise_sigma", "add_depth_noise", "smooth_trajectory",
     "look_at", "perturb_pose", "rotation_about", "Stream", "make_stream",
     "render_ids", "Albedo", "make_albedo", "surface_normal", "shade", "render_rgbd", "make_rgbd_stream",
-    "CONFIG_SPHERE", "CONFIG_ROOM", "CONFIG_ROOM_HD",
+    "CONFIG_SPHERE", "CONFIG_ROOM", "CONFIG_ROOM_HD", "spheres_scene", "orbit_views",
+    "make_spheres_stream", "CONFIG_SPHERES",
 ]
 
 
@@ -160,6 +161,40 @@ def room_scene(seed: int, cam_centres: np.ndarray, n_objects: int = 20,
 # --------------------------------------------------------------------------
 # Ray casting (exact)
 # --------------------------------------------------------------------------
+def spheres_scene(seed: int, n: int = 5, radius_range=(0.12, 0.35), half_extent: float = 0.8,
+                  min_gap: float = 0.25) -> Scene:
+    """``n`` spheres of random radii around the origin, no room: centres
+    uniform in the cube of half-size ``half_extent``, radii uniform in
+    ``radius_range``, every pair at least ``min_gap`` apart surface to
+    surface (so each voxel's nearest surface is unambiguous within the
+    truncation band)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out: List[np.ndarray] = []
+    while len(out) < n:
+        c = rng.uniform(-half_extent, half_extent, size=3)
+        r = rng.uniform(*radius_range)
+        if all(np.linalg.norm(c - o[:3]) >= r + o[3] + min_gap for o in out):
+            out.append(np.array([*c, r]))
+    return Scene(spheres=np.array(out, np.float64), boxes=np.zeros((0, 7)), room=None)
+
+
+def orbit_views(seed: int, n_frames: int, distance=(1.8, 2.6), elevation_deg=(-40.0, 60.0),
+                jitter: float = 0.1) -> np.ndarray:
+    """Random viewpoints around the origin, each looking at the origin
+    (plus a small random offset): (n_frames, 3, 4) camera-to-world poses.
+    Azimuth uniform, elevation uniform in ``elevation_deg``, distance
+    uniform in ``distance``."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(n_frames):
+        az = rng.uniform(0.0, 2 * math.pi)
+        el = math.radians(rng.uniform(*elevation_deg))
+        d = rng.uniform(*distance)
+        c = d * np.array([math.cos(el) * math.cos(az), math.cos(el) * math.sin(az), math.sin(el)])
+        out.append(look_at(c, rng.uniform(-jitter, jitter, size=3)))
+    return np.stack(out)
+
+
 def _ray_sphere(o, d, s):
     """Nearest positive hit of rays ``o + t d`` (d: (N, 3)) with a sphere."""
     oc = o - s[:3]
@@ -470,6 +505,10 @@ CONFIG_ROOM = dict(cam=Camera(525.0, 525.0, 319.5, 239.5, 640, 480, 0.4, 4.0),
 CONFIG_ROOM_HD = dict(cam=Camera(920.0, 920.0, 639.5, 359.5, 1280, 720, 0.4, 4.0),
                       voxel_size=0.005, truncation=0.025)
 
+# Gradient-quality experiment: 1 cm voxels, truncation 10 voxels.
+CONFIG_SPHERES = dict(cam=Camera(525.0, 525.0, 319.5, 239.5, 640, 480, 0.4, 4.0),
+                      voxel_size=0.01, truncation=0.10)
+
 
 @dataclasses.dataclass
 class Stream:
@@ -523,3 +562,19 @@ def make_rgbd_stream(cam: Camera, n_frames: int, scene_seed: int = 1, traj_seed:
         depth[i] = to_depth_image(z, cam)
         rgb[i] = col
     return Stream(cam=cam, depth=depth, poses=poses, scene=scene, rgb=rgb, albedo=alb)
+
+
+def make_spheres_stream(cam: Camera, n_frames: int, scene_seed: int = 11, view_seed: int = 12,
+                        noise_seed: Optional[int] = 13) -> Stream:
+    """Five random spheres seen from random viewpoints with axial depth
+    noise (the synthetic setup of the gradient-quality experiment)."""
+    scene = spheres_scene(scene_seed)
+    poses = orbit_views(view_seed, n_frames)
+    kids = np.random.SeedSequence(noise_seed).spawn(n_frames) if noise_seed is not None else None
+    depth = np.empty((n_frames, cam.height, cam.width), np.float32)
+    for i in range(n_frames):
+        z = render_depth(scene, cam, poses[i])
+        if kids is not None:
+            z = add_depth_noise(z, np.random.Generator(np.random.PCG64(kids[i])))
+        depth[i] = to_depth_image(z, cam)
+    return Stream(cam=cam, depth=depth, poses=poses, scene=scene)

@@ -1,0 +1,136 @@
+"""Pins of the oracle's gradient-quality functions (Sec. 5.2, App. A).
+
+Finite differences are pinned on a quadratic distance field, where the
+forward, backward and central differences have closed forms and a swapped
+axis, sign or neighbour shows at once; validity against a brute-force
+neighbour search.  Angles are pinned on gradients rotated by known angles
+away from the true sphere gradient, and distances against the analytic
+scene distance of the generator.  The last test reproduces the paper's
+finding in kind on a small noisy five-sphere stream."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2111_13652_amd import synth
+
+VS = 0.01
+
+
+def _coords(keys):
+    c = np.arange(512)
+    loc = np.stack([c % 8, (c // 8) % 8, c // 64], -1)
+    return keys[:, None, :] * 8 + loc[None]          # (n, 512, 3) voxel indices
+
+
+def test_fd_gradients_of_a_quadratic_field():
+    rng = np.random.default_rng(0)
+    keys = np.array([[bx, by, bz] for bx in (-1, 0, 1) for by in (-1, 0) for bz in (0, 1)], np.int32)
+    m = _coords(keys)
+    v = m * VS
+    a = np.array([0.3, -0.7, 0.5])
+    c = np.array([2.0, -3.0, 5.0])
+    psi = v @ a + 0.5 * (c * v * v).sum(-1) + 0.02
+    W = np.ones(psi.shape)
+    W[rng.random(W.shape) < 0.03] = 0.0                # unobserved holes
+    g = np.zeros(v.shape)
+    g[..., 2] = 1.0
+    O = oracle.OracleMap(VS, 0.1)
+    O.set_voxels(keys, psi, g, W)
+    f, b, ce, ok = O.fd_gradients(keys)
+
+    seen = {tuple(x) for x in m[W > 0]}
+    steps = [np.eye(3, dtype=int)[k] * s for k in range(3) for s in (1, -1)]
+    want = np.array([[W[i, j] > 0 and all(tuple(m[i, j] + e) in seen for e in steps)
+                      for j in range(512)] for i in range(len(keys))])
+    np.testing.assert_array_equal(ok, want)
+    assert want.sum() > 3000 and (~want).sum() > 1000
+
+    grad = a + c * v                                   # exact gradient at v
+    half = c * VS / 2
+    np.testing.assert_allclose(ce[ok], grad[ok], atol=1e-9, rtol=0)
+    np.testing.assert_allclose(f[ok], (grad + half)[ok], atol=1e-9, rtol=0)
+    np.testing.assert_allclose(b[ok], (grad - half)[ok], atol=1e-9, rtol=0)
+    assert not f[~ok].any() and not b[~ok].any() and not ce[~ok].any()
+
+
+def _rotated_away(u, theta, rng):
+    """Unit vectors at angle theta (radians) from the unit rows of u."""
+    r = rng.standard_normal(u.shape)
+    p = r - (r * u).sum(-1, keepdims=True) * u
+    p /= np.linalg.norm(p, axis=-1, keepdims=True)
+    return np.cos(theta)[..., None] * u + np.sin(theta)[..., None] * p
+
+
+def _band_map(scene, keys, rng, theta, scale_g):
+    m = _coords(keys)
+    v = m * VS
+    sdf = scene.sdf(v)                                 # positive inside
+    # the true gradient of the distance: towards the centre of the nearest sphere
+    d = np.stack([np.abs(np.linalg.norm(v - s[:3], axis=-1) - s[3]) for s in scene.spheres])
+    near = scene.spheres[np.argmin(d, axis=0)]
+    u = near[..., :3] - v
+    u /= np.linalg.norm(u, axis=-1, keepdims=True)
+    W = np.where(np.abs(sdf) < 0.1, 2.0, 0.0)
+    g = _rotated_away(u, theta, rng) * scale_g
+    return m, v, sdf, u, W, g
+
+
+def test_angles_and_distances_against_two_spheres():
+    rng = np.random.default_rng(1)
+    scene = synth.Scene(spheres=np.array([[0.003, -0.002, 0.001, 0.25], [0.7, 0.1, -0.05, 0.15]]),
+                        boxes=np.zeros((0, 7)))
+    keys = np.array([[bx, by, bz] for bx in range(-5, 12) for by in range(-5, 5) for bz in range(-5, 5)],
+                    np.int32)
+    theta = rng.uniform(0.0, np.radians(170.0), size=(len(keys), 512))
+    m, v, sdf, u, W, g = _band_map(scene, keys, rng, theta, rng.uniform(0.1, 5.0, size=(len(keys), 512, 1)))
+    O = oracle.OracleMap(VS, 0.1)
+    O.set_voxels(keys, sdf, g, W)
+    q = O.gradient_quality(scene.spheres, keys)
+    obs = W > 0
+    assert obs.sum() > 50000
+    np.testing.assert_allclose(q[0][obs], np.abs(sdf[obs]), atol=1e-12, rtol=0)
+    np.testing.assert_allclose(q[1][obs], np.degrees(theta[obs]), atol=1e-9, rtol=0)
+    assert np.isnan(q[:, ~obs]).all()
+
+
+def test_fd_angles_on_an_exact_sphere_distance():
+    """psi = r - |v - c| exactly: the central difference errs by O(h^2/rho^2),
+    the one-sided ones by O(h/rho); forward + backward = 2 central."""
+    rng = np.random.default_rng(2)
+    scene = synth.Scene(spheres=np.array([[0.013, -0.021, 0.007, 0.3]]), boxes=np.zeros((0, 7)))
+    keys = np.array([[bx, by, bz] for bx in range(-6, 6) for by in range(-6, 6) for bz in range(-6, 6)],
+                    np.int32)
+    m, v, sdf, u, W, g = _band_map(scene, keys, rng, np.zeros((len(keys), 512)), 1.0)
+    O = oracle.OracleMap(VS, 0.1)
+    O.set_voxels(keys, sdf, g, W)
+    q = O.gradient_quality(scene.spheres, keys)
+    f, b, ce, ok = O.fd_gradients(keys)
+    np.testing.assert_allclose(f[ok] + b[ok], 2 * ce[ok], atol=1e-12)
+    assert ok.sum() > 100000
+    assert np.nanmax(q[1]) < 1e-6                     # stored gradient = truth
+    rho = np.linalg.norm(v - scene.spheres[0, :3], axis=-1)[ok]
+    # central: per-axis error h^2/6 |f'''| <= h^2/rho^2 in gradient norm units
+    assert np.all(np.radians(q[4][ok]) <= 2 * (VS / rho) ** 2)
+    # one-sided: error h/2 |f''| <= h/(2 rho) per axis (curvature 1/rho)
+    for k in (2, 3):
+        assert np.all(np.radians(q[k][ok]) <= 2 * VS / rho)
+    assert np.median(q[2][ok]) > 20 * np.median(q[4][ok])
+
+
+def test_stored_gradients_beat_central_differences_in_kind():
+    """Sec. 5.2: on noisy spheres fused with true poses the stored gradients
+    deviate from the truth far less than central differences (the paper
+    reports 5.07 vs 9.49 degrees mean within 10 voxels)."""
+    cam = synth.Camera(262.0, 262.0, 159.5, 119.5, 320, 240, 0.4, 4.0)
+    st = synth.make_spheres_stream(cam, 30)
+    O = oracle.OracleMap(0.01, 0.10)
+    for f in range(30):
+        O.allocate(st.depth[f], cam, st.poses[f])
+        O.integrate(st.depth[f], cam, st.poses[f])
+    q = O.gradient_quality(st.scene.spheres).reshape(5, -1)
+    sel = (q[0] < 0.10) & np.isfinite(q[4])
+    assert sel.sum() > 100000
+    stored, central = q[1][sel].mean(), q[4][sel].mean()
+    assert stored < 0.7 * central
+    assert np.median(q[1][sel]) < np.median(q[4][sel])
+    assert np.percentile(q[1][sel], 95) < np.percentile(q[4][sel], 95)
