@@ -116,16 +116,13 @@ def main():
 
     def step(f, src=None):
         d = depth[f] if src is None else src
-        est[f].copy_(est[f - 1])
-        m.track(d, cam, est[f], levels=levels, iters=iters, delta=delta)
-        m.allocate(d, cam, est[f])
-        m.integrate(d, cam, est[f])
+        m.track(d, cam, est[f], levels=levels, iters=iters, delta=delta, init=est[f - 1])
+        m.fuse(d, cam, est[f])
 
     def start():
         m.reset()
         est[0].copy_(gt[0])
-        m.allocate(depth[0], cam, est[0])
-        m.integrate(depth[0], cam, est[0])
+        m.fuse(depth[0], cam, est[0])
         for f in range(1, 1 + args.warmup):
             step(f)
         torch.cuda.synchronize()
@@ -164,8 +161,7 @@ def main():
     kernels = {}
     if timing:
         for name, kid in (("track", _lib.K_TRACK), ("fuse_blocks", _lib.K_INTEGRATE),
-                          ("normals", _lib.K_NORMALS), ("allocate", _lib.K_ALLOCATE),
-                          ("pyramid", _lib.K_PYRAMID)):
+                          ("alloc_normals", _lib.K_ALLOC_NORMALS), ("pyramid", _lib.K_PYRAMID)):
             tot = C.c_double()
             n = C.c_int64()
             lib.gsdf_timing_read(kid, C.byref(tot), C.byref(n))
@@ -182,14 +178,13 @@ def main():
     fuse_bytes = 2.0 * rec * work[0]
     normals_bytes = B_FUSE_PIXEL * npx * K
     alloc_bytes = B_ALLOC_PIXEL * npx * K + B_ALLOC_PAIR * work[4]
-    per_kernel_bytes = {"track": track_bytes, "fuse_blocks": fuse_bytes, "normals": normals_bytes,
-                        "allocate": alloc_bytes}
+    per_kernel_bytes = {"track": track_bytes, "fuse_blocks": fuse_bytes, "alloc_normals": alloc_bytes + normals_bytes}
     total_bytes = track_bytes + fuse_bytes + normals_bytes + alloc_bytes
     eff_gbs = total_bytes / (ms / 1e3) / 1e9
 
     roofline = None
     if kernels:
-        dom = max(("track", "fuse_blocks", "allocate", "normals"), key=lambda k: kernels[k]["total_ms"])
+        dom = max(("track", "fuse_blocks", "alloc_normals"), key=lambda k: kernels[k]["total_ms"])
         launches = max(1, kernels[dom]["launches"])
         avg_s = kernels[dom]["total_ms"] / 1e3 / launches
         bytes_per_launch = per_kernel_bytes[dom] / launches

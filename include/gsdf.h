@@ -159,6 +159,16 @@ int gsdf_integrate_frame(gsdf_map* map, const float* depth_dev, const gsdf_camer
                          void* scratch_dev, size_t scratch_bytes, int32_t* status_dev,
                          void* stream);
 
+/* allocate_blocks followed by integrate_frame for one frame (Sec. 5.3),
+ * with the same results as the two calls in sequence, in two launches: the
+ * allocation of each 16x16 pixel tile and the tile's normal fits share one
+ * launch (neither reads what the other writes), then the per-block fusion.
+ * Arguments as for gsdf_integrate_frame (scratch_dev: at least
+ * gsdf_integrate_scratch_bytes(cam) bytes). */
+int gsdf_fuse_frame(gsdf_map* map, const float* depth_dev, const gsdf_camera* cam, const double* T_wc_dev,
+                    const gsdf_fuse_params* params, void* scratch_dev, size_t scratch_bytes,
+                    int32_t* status_dev, void* stream);
+
 /* Scratch bytes gsdf_track_frame / gsdf_normal_equations need for `cam`. */
 size_t gsdf_track_scratch_bytes(const gsdf_camera* cam, int32_t levels);
 
@@ -166,14 +176,15 @@ size_t gsdf_track_scratch_bytes(const gsdf_camera* cam, int32_t levels);
  * Gauss-Newton on E = sum_k rho_delta(r_k), r_k = psi_j + g^_j . (T x_k - v_j)
  * with j the voxel nearest to T x_k, Jacobian [g^ ; (T x) x g^] for a left
  * perturbation in the world frame, and a damped 6x6 Cholesky solve in
- * float64 on the device; T <- exp(dxi) T.  T_wc_inout_dev (device, 12 f64)
- * holds the initial pose and receives the estimate.  stats_dev (device,
- * optional) receives 2 floats per iteration in execution order: the energy
- * and the number of pixels used at that linearisation.  scratch_dev must
- * hold gsdf_track_scratch_bytes(cam, levels) bytes. */
+ * float64 on the device; T <- exp(dxi) T.  T_init_dev (device, 12 f64) holds
+ * the initial pose and T_wc_out_dev (device, 12 f64) receives the estimate;
+ * they may be the same buffer.  stats_dev (device, optional) receives 2
+ * floats per iteration in execution order: the energy and the number of
+ * pixels used at that linearisation.  scratch_dev must hold
+ * gsdf_track_scratch_bytes(cam, levels) bytes. */
 int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, const gsdf_camera* cam,
-                     const gsdf_track_params* params, double* T_wc_inout_dev, float* stats_dev,
-                     void* scratch_dev, size_t scratch_bytes, int32_t* status_dev, void* stream);
+                     const gsdf_track_params* params, const double* T_init_dev, double* T_wc_out_dev,
+                     float* stats_dev, void* scratch_dev, size_t scratch_bytes, int32_t* status_dev, void* stream);
 
 /* One linearisation of the tracking energy at T_wc_dev on the full-resolution
  * image (Eq. (5), (14)-(16)): out29_dev (device, 29 float64) = the 21 upper-
@@ -401,6 +412,7 @@ enum {
     GSDF_K_BACKWARD = 5,
     GSDF_K_LOSS = 6,
     GSDF_K_PHOTOMETRIC = 7,
+    GSDF_K_ALLOC_NORMALS = 8,
     GSDF_K_COUNT = 16
 };
 

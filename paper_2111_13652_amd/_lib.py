@@ -13,7 +13,8 @@ LIB_PATH = os.path.join(_HERE, "libgsdf.so")
 
 OK, EINVAL, ECAPACITY, EHIP, ENOTPD, ELOST = 0, -1, -2, -3, -4, -5
 FP32, BF16, FP16 = 0, 1, 2
-K_ALLOCATE, K_INTEGRATE, K_TRACK, K_PYRAMID, K_NORMALS, K_BACKWARD, K_LOSS, K_PHOTOMETRIC = range(8)
+(K_ALLOCATE, K_INTEGRATE, K_TRACK, K_PYRAMID, K_NORMALS, K_BACKWARD, K_LOSS, K_PHOTOMETRIC,
+ K_ALLOC_NORMALS) = range(9)
 
 
 class MapDesc(C.Structure):
@@ -56,9 +57,11 @@ _SIGNATURES = {
     "gsdf_integrate_scratch_bytes": (_SZ, [C.POINTER(Camera)]),
     "gsdf_integrate_frame": (_I, [C.POINTER(Map), _P, C.POINTER(Camera), _P, C.POINTER(FuseParams), _P,
                                   _SZ, _P, _P]),
+    "gsdf_fuse_frame": (_I, [C.POINTER(Map), _P, C.POINTER(Camera), _P, C.POINTER(FuseParams), _P,
+                             _SZ, _P, _P]),
     "gsdf_map_counters": (_I, [C.POINTER(Map), _P, _P]),
     "gsdf_track_scratch_bytes": (_SZ, [C.POINTER(Camera), _I32]),
-    "gsdf_track_frame": (_I, [C.POINTER(Map), _P, C.POINTER(Camera), C.POINTER(TrackParams), _P, _P, _P,
+    "gsdf_track_frame": (_I, [C.POINTER(Map), _P, C.POINTER(Camera), C.POINTER(TrackParams), _P, _P, _P, _P,
                               _SZ, _P, _P]),
     "gsdf_normal_equations": (_I, [C.POINTER(Map), _P, C.POINTER(Camera), _P, C.c_float, _P, _P, _SZ, _P]),
     "gsdf_export_keys": (_I, [C.POINTER(Map), _P, _P, _P]),

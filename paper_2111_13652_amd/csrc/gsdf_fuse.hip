@@ -3,7 +3,8 @@
 // Gradient-SDF (Sec. 3.1, 3.2), driven by depth pixels as in the Sec. 5.3
 // setup.
 //
-// Two kernels.
+// Two kernels (the frame path runs the first together with allocation, as
+// k_alloc_normals).
 //  1. k_pixel_normals: one work-group per 16x16 pixel tile with its 2-pixel
 //     halo staged in LDS; every pixel gets its world-frame normal and depth
 //     (float4), or zeros when it fails the window or the angle test.
@@ -29,6 +30,7 @@
 
 #include <climits>
 
+#include "gsdf_alloc.hpp"
 #include "gsdf_common.hpp"
 #include "gsdf_host.hpp"
 
@@ -65,14 +67,15 @@ __device__ inline float linear_weight(float d, float eps, float T) {
 // ---------------------------------------------------------------------------
 // 1. Normals
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_pixel_normals(const float* __restrict__ depth, FuseConsts fc,
-                                                       const double* __restrict__ Twc,
-                                                       float4* __restrict__ pix) {
-    __shared__ float tile[kTileH][kTileH + 1];
+// Tile (tu, tv) of 16x16 pixels; every thread of the 256-thread work-group
+// must call it (it synchronises); tile is kTileH x (kTileH + 1) floats of LDS.
+__device__ inline void normals_tile(const float* __restrict__ depth, const FuseConsts& fc,
+                                    const double* __restrict__ Twc, float4* __restrict__ pix, int tu, int tv,
+                                    float (*tile)[kTileH + 1]) {
     const int tx = threadIdx.x & (kTile - 1);
     const int ty = threadIdx.x / kTile;
-    const int u0 = blockIdx.x * kTile - kHalo;
-    const int v0 = blockIdx.y * kTile - kHalo;
+    const int u0 = tu * kTile - kHalo;
+    const int v0 = tv * kTile - kHalo;
     for (int i = threadIdx.x; i < kTileH * kTileH; i += blockDim.x) {
         const int ly = i / kTileH, lx = i % kTileH;
         const int uu = u0 + lx, vv = v0 + ly;
@@ -82,9 +85,9 @@ __global__ __launch_bounds__(256) void k_pixel_normals(const float* __restrict__
     }
     __syncthreads();
 
-    const int u = blockIdx.x * kTile + tx;
-    const int v = blockIdx.y * kTile + ty;
-    if (u >= fc.W || v >= fc.H) return;
+    const int u = tu * kTile + tx;
+    const int v = tv * kTile + ty;
+    if (u >= fc.W || v >= fc.H) return;  // no barrier follows
     float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
     const float Dc = tile[ty + kHalo][tx + kHalo];
     if (u >= kHalo && v >= kHalo && u < fc.W - kHalo && v < fc.H - kHalo &&
@@ -130,6 +133,28 @@ __global__ __launch_bounds__(256) void k_pixel_normals(const float* __restrict__
         }
     }
     pix[(size_t)v * fc.W + u] = out;
+}
+
+__global__ __launch_bounds__(256) void k_pixel_normals(const float* __restrict__ depth, FuseConsts fc,
+                                                       const double* __restrict__ Twc,
+                                                       float4* __restrict__ pix) {
+    __shared__ float tile[kTileH][kTileH + 1];
+    normals_tile(depth, fc, Twc, pix, blockIdx.x, blockIdx.y, tile);
+}
+
+// The frame path's allocation and normals in one launch: both work on the
+// same 16x16 tiles of the same depth image and pose and are independent of
+// each other (allocation never reads a normal), so each work-group runs the
+// tile's allocation and then its normals.
+__global__ __launch_bounds__(256) void k_alloc_normals(MapView M, const float* __restrict__ depth, FuseConsts fc,
+                                                       const double* __restrict__ Twc, float4* __restrict__ pix,
+                                                       int32_t* status) {
+    __shared__ unsigned long long s_keys[kAllocSet];
+    __shared__ unsigned long long red[4];
+    __shared__ float tile[kTileH][kTileH + 1];
+    allocate_tile(M, depth, fc.W, fc.H, fc.zmin, fc.zmax, fc.band, Twc, status, blockIdx.x, blockIdx.y, s_keys,
+                  red);
+    normals_tile(depth, fc, Twc, pix, blockIdx.x, blockIdx.y, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -543,6 +568,33 @@ extern "C" int gsdf_integrate_frame(gsdf_map* map, const float* depth_dev, const
         TimedLaunch t(GSDF_K_NORMALS, s);
         dim3 grid(ceil_div(cam->width, kTile), ceil_div(cam->height, kTile));
         k_pixel_normals<<<grid, 256, 0, s>>>(depth_dev, fc, T_wc_dev, pix);
+    }
+    {
+        TimedLaunch t(GSDF_K_INTEGRATE, s);
+        switch (map->desc.storage) {
+            case GSDF_FP32: k_fuse_blocks<GSDF_FP32><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev); break;
+            case GSDF_BF16: k_fuse_blocks<GSDF_BF16><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev); break;
+            default: k_fuse_blocks<GSDF_FP16><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev); break;
+        }
+    }
+    return launch_status();
+}
+
+extern "C" int gsdf_fuse_frame(gsdf_map* map, const float* depth_dev, const gsdf_camera* cam,
+                               const double* T_wc_dev, const gsdf_fuse_params* params, void* scratch_dev,
+                               size_t scratch_bytes, int32_t* status_dev, void* stream) {
+    if (!valid_map(map) || !depth_dev || !valid_cam(cam) || !T_wc_dev || !params || !scratch_dev)
+        return GSDF_EINVAL;
+    if (!(params->eps_weight < map->desc.truncation)) return GSDF_EINVAL;
+    if (scratch_bytes < gsdf_integrate_scratch_bytes(cam)) return GSDF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const FuseConsts fc = fuse_consts(*map, *cam, *params);
+    const MapView M = make_view(*map);
+    float4* pix = (float4*)scratch_dev;
+    {
+        TimedLaunch t(GSDF_K_ALLOC_NORMALS, s);
+        dim3 grid(ceil_div(cam->width, kTile), ceil_div(cam->height, kTile));
+        k_alloc_normals<<<grid, 256, 0, s>>>(M, depth_dev, fc, T_wc_dev, pix, status_dev);
     }
     {
         TimedLaunch t(GSDF_K_INTEGRATE, s);

@@ -6,6 +6,7 @@
 #include <mutex>
 #include <vector>
 
+#include "gsdf_alloc.hpp"
 #include "gsdf_common.hpp"
 #include "gsdf_host.hpp"
 
@@ -82,70 +83,12 @@ __global__ void k_zero16(uint4* p, uint64_t n16) {
 // block keys of its pixels' ray bands in an LDS set (neighbouring pixels
 // share almost all of their blocks), then inserts each distinct key into
 // the global table once and records it as touched by this frame.
-constexpr int kAllocSet = 1024;  // LDS set capacity (keys) per tile
-
 __global__ __launch_bounds__(256) void k_allocate(MapView M, const float* __restrict__ depth, int W,
                                                   int H, float zmin, float zmax, BandConsts bc,
                                                   const double* __restrict__ Twc, int32_t* status) {
     __shared__ unsigned long long s_keys[kAllocSet];
-    for (int i = threadIdx.x; i < kAllocSet; i += blockDim.x) s_keys[i] = kEmptyKey;
-    __syncthreads();
-    const int u = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int v = blockIdx.y * 16 + (threadIdx.x >> 4);
-    const float D = (u < W && v < H) ? depth[(size_t)v * W + u] : 0.0f;
-    if (depth_ok(D, zmin, zmax)) {
-        const BandRule br = make_band_rule(Twc, bc.ifx, bc.ify, bc.cxf, bc.cyf, bc.invvs, bc.Tf,
-                                           bc.Df, bc.nsamples);
-        const float xr = pixel_xr(br, u);
-        const float yr = pixel_yr(br, v);
-        int pm[3] = {INT_MIN, INT_MIN, INT_MIN};
-        int pb[3] = {INT_MIN, INT_MIN, INT_MIN};
-        for (int k = 0; k < br.nsamples; ++k) {
-            int m[3];
-            if (!band_sample(br, xr, yr, D, k, m)) continue;
-            if (m[0] == pm[0] && m[1] == pm[1] && m[2] == pm[2]) continue;
-            pm[0] = m[0];
-            pm[1] = m[1];
-            pm[2] = m[2];
-            const int bx = block_of(m[0]), by = block_of(m[1]), bz = block_of(m[2]);
-            if (bx == pb[0] && by == pb[1] && bz == pb[2]) continue;
-            pb[0] = bx;
-            pb[1] = by;
-            pb[2] = bz;
-            if (!block_allowed(M, bx, by, bz)) continue;
-            const unsigned long long key = pack_key(bx, by, bz);
-            unsigned h = (unsigned)mix64(key) & (kAllocSet - 1);
-            bool placed = false;
-            for (int probe = 0; probe < kAllocSet; ++probe) {
-                const unsigned long long old = atomicCAS(&s_keys[h], kEmptyKey, key);
-                if (old == kEmptyKey || old == key) {
-                    placed = true;
-                    break;
-                }
-                h = (h + 1) & (kAllocSet - 1);
-            }
-            if (!placed) {  // set full: go to the global table directly
-                int created;
-                const int32_t slot = hash_insert(M, bx, by, bz, status, &created);
-                if (slot >= 0) mark_touched(M, slot);
-            }
-        }
-    }
-    __syncthreads();
-    unsigned long long probes = 0;
-    for (int i = threadIdx.x; i < kAllocSet; i += blockDim.x) {
-        const unsigned long long key = s_keys[i];
-        if (key == kEmptyKey) continue;
-        int bx, by, bz, created;
-        unpack_key(key, &bx, &by, &bz);
-        // the inserting thread marks a new block; others mark known slots
-        const int32_t slot = hash_insert(M, bx, by, bz, status, &created);
-        if (slot >= 0) mark_touched(M, slot);
-        ++probes;
-    }
     __shared__ unsigned long long red[4];
-    probes = block_sum_u64(probes, red);
-    if (threadIdx.x == 0) add_stat(M, kStatAllocPairs, probes);
+    allocate_tile(M, depth, W, H, zmin, zmax, bc, Twc, status, blockIdx.x, blockIdx.y, s_keys, red);
 }
 
 __global__ void k_sum_stats(MapView M, unsigned long long* out) {

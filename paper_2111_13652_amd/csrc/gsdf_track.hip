@@ -9,14 +9,15 @@
 // set of pixels and accumulates, in float32 registers, the 21 upper entries
 // of H = sum w J J^T, the 6 of b = sum w J r, the energy, the count of
 // pixels used and the count of valid pixels.  From there every sum is
-// float64: cross-lane shuffles, then LDS across the waves of a work-group,
-// then one partial per work-group.  The last work-group to arrive (a
-// device-scope ticket) adds the partials, solves, writes the new pose and
-// bumps a generation counter; the others wait for it (a bounded spin, so
-// every wave exits even if something went wrong) and start the next
-// iteration with the new pose.  Float64 partial sums keep the rounding noise
-// of b far below what a rank-deficient H (a lone sphere) would amplify
-// through the damping.
+// float64: LDS across the waves of a work-group, then one partial per
+// work-group, then one sum per leaf of kLeaf work-groups (added by the last
+// of them to arrive, a device-scope ticket).  Every work-group then reads
+// the leaf sums, adds them in the same fixed order and solves the 6x6
+// system itself, so all of them hold the bit-identical new pose without a
+// round trip through a publisher; work-group 0 writes the final pose.
+// Waits are bounded spins, so every wave exits even if something went
+// wrong.  Float64 partial sums keep the rounding noise of b far below what a
+// rank-deficient H (a lone sphere) would amplify through the damping.
 #include <hip/hip_runtime.h>
 
 #include "gsdf_common.hpp"
@@ -465,9 +466,11 @@ __device__ inline void complete_device_stores() { __builtin_amdgcn_s_waitcnt(0);
 // Sync words in the scratch buffer.  Arrival is a two-level tree of tickets
 // (device-scope atomics on one address serialise, so a single ticket for
 // hundreds of work-groups would cost tens of microseconds): kLeaf
-// work-groups share a leaf ticket, the last of each leaf takes the root
-// ticket.  Two ticket sets alternate between iterations.  Then the
-// published generation and an abort flag.
+// work-groups share a leaf ticket; two ticket sets alternate between
+// iterations.  Single-launch reductions (the normal equations) close the
+// tree with a root ticket; the tracking kernel instead counts published leaf
+// sums in a monotonic done word that every work-group polls.  Then an abort
+// flag.
 constexpr int kLeaf = 16;
 constexpr int kMaxLeaves = kMaxGroups / kLeaf;
 // one set of partials: a partial per work-group, then one per leaf
@@ -475,8 +478,8 @@ constexpr size_t kPartsPerSet = (size_t)(kMaxGroups + kMaxLeaves) * kPartStride;
 enum {
     kSyncLeaf = 0,                          // [2][kMaxLeaves]
     kSyncRoot = kSyncLeaf + 2 * kMaxLeaves,  // [2]
-    kSyncGen = kSyncRoot + 2,
-    kSyncAbort = kSyncGen + 1,
+    kSyncDone = kSyncRoot + 2,
+    kSyncAbort = kSyncDone + 1,
     kSyncWords = kSyncAbort + 1
 };
 
@@ -554,12 +557,38 @@ __device__ inline bool reduce_tree(const float acc[kNE], const float cmp[kNE], d
     return true;
 }
 
-// Wait (thread 0 only) until the published generation reaches `target`;
-// device-scope polling with a short sleep.  Returns false on timeout or when
-// another work-group aborted.
-__device__ inline bool wait_generation(unsigned* sync, unsigned target) {
+// A participant's share of an iteration: store the work-group partial and
+// take the leaf ticket; the last work-group of the leaf adds the leaf's
+// partials, stores the leaf sum (device scope) and, once those stores have
+// completed, counts it in the done word.
+template <bool COMP>
+__device__ inline void contribute(const float acc[kNE], const float cmp[kNE], double* part, double* leafpart,
+                                  unsigned* sync, int par, int groups, ReduceLds& r, int* s_flag) {
+    store_partial<COMP>(acc, cmp, part + (size_t)blockIdx.x * kPartStride, r);
+    if (threadIdx.x == 0) *s_flag = leaf_arrive(sync, par, groups) ? 1 : 0;
+    __syncthreads();
+    if (!*s_flag) return;
+    const int leaf = blockIdx.x / kLeaf;
+    const int leaf_size = min(kLeaf, groups - leaf * kLeaf);
+    double lsum[kNE];
+    total_partials<COMP>(part + (size_t)leaf * kLeaf * kPartStride, leaf_size, lsum, r);
+    // r.tot holds the leaf sum in every thread; lanes of wave 0 store it
+    if (threadIdx.x < kNE)
+        __hip_atomic_store(&leafpart[(size_t)leaf * kPartStride + threadIdx.x], r.tot[threadIdx.x],
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        complete_device_stores();
+        __hip_atomic_fetch_add(&sync[kSyncDone], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Wait (thread 0 only) until `target` leaf sums have been published in
+// total; device-scope polling with a short sleep.  Returns false on timeout
+// or when another work-group aborted.
+__device__ inline bool wait_done(unsigned* sync, unsigned target) {
     unsigned spins = 0;
-    while (__hip_atomic_load(&sync[kSyncGen], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(&sync[kSyncDone], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         if (++spins > kSpinLimit ||
             __hip_atomic_load(&sync[kSyncAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             return false;
@@ -583,49 +612,62 @@ __device__ inline int level_groups(const TrackLevel& L, int G) {
 }
 
 // The whole coarse-to-fine Gauss-Newton of one frame (cooperative launch).
+// Buffer reuse: partials and leaf sums alternate between two sets by
+// iteration parity.  A work-group writes set (gi & 1) again at gi + 2 only
+// after it has seen every leaf sum of gi + 1, and each of those was
+// published after its leaf's work-groups had finished reading the sums of
+// gi, so no set is overwritten while it is still read.
 template <int STORAGE>
-__global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArgs a, double* pose,
-                                                              double* partials, unsigned* sync,
+__global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArgs a, const double* pose_in,
+                                                              double* pose_out, double* partials, unsigned* sync,
                                                               float* stats, int32_t* status) {
     __shared__ double s_pose[12];
-    __shared__ int s_last, s_ok;
+    __shared__ int s_flag, s_ok;
     __shared__ ReduceLds red;
     __shared__ float s_depth[kTrackBatch * kTrackBlock];
+    constexpr bool COMP = STORAGE != GSDF_FP32;
     const int G = gridDim.x;
-    int gi = 0;  // global iteration index
+    // a work-group that takes part in no level holds nothing anyone needs
+    int span = 1;
+    for (int l = 0; l < a.levels; ++l)
+        if (a.iters[l] > 0) span = max(span, level_groups(a.lv[l], G));
+    if ((int)blockIdx.x >= span) return;
+    // pose_in may be pose_out: every work-group still running reads it here,
+    // before its first contribution, and work-group 0 writes the result only
+    // after the last iteration, which needs all of those contributions
+    if (threadIdx.x < 12) s_pose[threadIdx.x] = pose_in[threadIdx.x];
+    __syncthreads();
+    int gi = 0;           // global iteration index
+    unsigned target = 0;  // leaf sums published once iteration gi is complete
     for (int l = a.levels - 1; l >= 0; --l) {
         const TrackLevel L = a.lv[l];
         const int Gl = level_groups(L, G);
-        if ((int)blockIdx.x >= Gl) {
-            // no pixels at this level: skip to the end of its iterations
-            gi += a.iters[l];
-            continue;
-        }
-        // this work-group's pixels are the same in every iteration of the
-        // level: the depths of each thread's first batch are loaded once,
-        // before the first wait, and kept in LDS
+        const int nleaf = (Gl + kLeaf - 1) / kLeaf;
+        const bool member = (int)blockIdx.x < Gl;
+        // a member's pixels are the same in every iteration of the level:
+        // the depths of each thread's first batch are loaded once and kept
+        // in LDS (each thread reads back only what it wrote)
         const int first = blockIdx.x * kTrackBlock + threadIdx.x;
+        if (member) {
 #pragma unroll
-        for (int j = 0; j < kTrackBatch; ++j) {
-            const int i = first + j * Gl * kTrackBlock;
-            s_depth[j * kTrackBlock + threadIdx.x] = i < L.W * L.H ? L.depth[i] : 0.0f;
+            for (int j = 0; j < kTrackBatch; ++j) {
+                const int i = first + j * Gl * kTrackBlock;
+                s_depth[j * kTrackBlock + threadIdx.x] = i < L.W * L.H ? L.depth[i] : 0.0f;
+            }
         }
         for (int it = 0; it < a.iters[l]; ++it, ++gi) {
-            // ---- wait for the pose of iteration gi
-            if (threadIdx.x == 0) {
-                const bool ok = gi == 0 || wait_generation(sync, (unsigned)gi);
-                if (ok) {
-                    // the pose was stored (device scope) before the
-                    // generation; twelve device-scope loads issued back to back
-                    double v[12];
+            double* part = partials + (size_t)(gi & 1) * kPartsPerSet;
+            double* leafpart = part + (size_t)kMaxGroups * kPartStride;
+            if (member) {
+                double P[12];
 #pragma unroll
-                    for (int k = 0; k < 12; ++k)
-                        v[k] = __hip_atomic_load(&pose[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) s_pose[k] = v[k];
-                }
-                s_ok = ok ? 1 : 0;
+                for (int k = 0; k < 12; ++k) P[k] = s_pose[k];
+                float acc[kNE], cmp[kNE];
+                accumulate<STORAGE>(M, L, a, P, first, Gl * kTrackBlock, s_depth, acc, cmp);
+                contribute<COMP>(acc, cmp, part, leafpart, sync, gi & 1, Gl, red, &s_flag);
             }
+            target += (unsigned)nleaf;
+            if (threadIdx.x == 0) s_ok = wait_done(sync, target) ? 1 : 0;
             __syncthreads();
             if (!s_ok) {
                 if (threadIdx.x == 0) {
@@ -634,47 +676,31 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
                 }
                 return;
             }
-            double P[12];
-#pragma unroll
-            for (int k = 0; k < 12; ++k) P[k] = s_pose[k];
-            float acc[kNE], cmp[kNE];
-            accumulate<STORAGE>(M, L, a, P, first, Gl * kTrackBlock, s_depth, acc, cmp);
-
-            double* part = partials + (size_t)(gi & 1) * kPartsPerSet;
-            double* leafpart = part + (size_t)kMaxGroups * kPartStride;
+            // every work-group: the same sum of the leaf sums, the same solve
             double ne[kNE];
-            if (!reduce_tree<STORAGE != GSDF_FP32>(acc, cmp, part, leafpart, sync, gi & 1, Gl, ne, red, &s_last))
-                continue;
-
-            // ---- the work-group holding the total: solve, publish
+            total_partials<COMP>(leafpart, nleaf, ne, red);
             if (threadIdx.x == 0) {
                 double Pn[12];
                 for (int k = 0; k < 12; ++k) Pn[k] = s_pose[k];
-                if (solve_and_update(ne, a.damping, Pn)) {
-                    for (int k = 0; k < 12; ++k)
-                        __hip_atomic_store(&pose[k], Pn[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                } else {
-                    raise_status(status, GSDF_ENOTPD);
+                const bool solved = solve_and_update(ne, a.damping, Pn);
+                if (solved)
+                    for (int k = 0; k < 12; ++k) s_pose[k] = Pn[k];
+                if (blockIdx.x == 0) {
+                    if (!solved) raise_status(status, GSDF_ENOTPD);
+                    if (l == 0 && it == a.iters[0] - 1 && ne[28] < (double)a.min_inlier_frac * ne[29])
+                        raise_status(status, GSDF_ELOST);
+                    if (stats) {
+                        stats[2 * gi] = (float)ne[27];
+                        stats[2 * gi + 1] = (float)ne[28];
+                    }
+                    add_stat(M, kStatTrackValid, (unsigned long long)ne[29]);
+                    add_stat(M, kStatTrackUsed, (unsigned long long)ne[28]);
                 }
-                if (l == 0 && it == a.iters[0] - 1 && ne[28] < (double)a.min_inlier_frac * ne[29])
-                    raise_status(status, GSDF_ELOST);
-                complete_device_stores();
-                __hip_atomic_store(&sync[kSyncGen], (unsigned)(gi + 1), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                // bookkeeping after the publish, off the critical path
-                if (stats) {
-                    stats[2 * gi] = (float)ne[27];
-                    stats[2 * gi + 1] = (float)ne[28];
-                }
-                add_stat(M, kStatTrackValid, (unsigned long long)ne[29]);
-                add_stat(M, kStatTrackUsed, (unsigned long long)ne[28]);
             }
             __syncthreads();
         }
     }
-    // Every work-group leaves only after the last pose is published, so the
-    // pose read by the next kernel on the stream is final.
-    if (threadIdx.x == 0 && gi > 0 && !wait_generation(sync, (unsigned)gi)) raise_status(status, GSDF_EHIP);
+    if (blockIdx.x == 0 && threadIdx.x < 12) pose_out[threadIdx.x] = s_pose[threadIdx.x];
 }
 
 // One linearisation (gsdf_normal_equations): a single launch whose last
@@ -807,13 +833,13 @@ int coop_groups() {
 }
 
 template <int STORAGE>
-int launch_track_frame(hipStream_t s, const MapView& M, const TrackArgs& a, double* pose,
-                       double* partials, unsigned* sync, float* stats, int32_t* status) {
+int launch_track_frame(hipStream_t s, const MapView& M, const TrackArgs& a, const double* pose_in,
+                       double* pose_out, double* partials, unsigned* sync, float* stats, int32_t* status) {
     const int g = coop_groups<STORAGE>();
     if (g <= 0) return GSDF_EHIP;
     MapView Mv = M;
     TrackArgs av = a;
-    void* args[] = {&Mv, &av, &pose, &partials, &sync, &stats, &status};
+    void* args[] = {&Mv, &av, &pose_in, &pose_out, &partials, &sync, &stats, &status};
     TimedLaunch tl(GSDF_K_TRACK, s);
     if (hipLaunchCooperativeKernel((const void*)k_track_frame<STORAGE>, dim3(g), dim3(kTrackBlock), args, 0,
                                    s) != hipSuccess)
@@ -856,10 +882,11 @@ extern "C" size_t gsdf_track_scratch_bytes(const gsdf_camera* cam, int32_t level
 }
 
 extern "C" int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, const gsdf_camera* cam,
-                                const gsdf_track_params* params, double* T_wc_inout_dev,
+                                const gsdf_track_params* params, const double* T_init_dev, double* T_wc_out_dev,
                                 float* stats_dev, void* scratch_dev, size_t scratch_bytes,
                                 int32_t* status_dev, void* stream) {
-    if (!valid_map(map) || !depth_dev || !valid_cam(cam) || !params || !T_wc_inout_dev || !scratch_dev)
+    if (!valid_map(map) || !depth_dev || !valid_cam(cam) || !params || !T_init_dev || !T_wc_out_dev ||
+        !scratch_dev)
         return GSDF_EINVAL;
     const int levels = params->levels;
     if (levels < 1 || levels > 4) return GSDF_EINVAL;
@@ -905,9 +932,9 @@ extern "C" int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, con
     const MapView M = make_view(*map);
     int rc;
     switch (map->desc.storage) {
-        case GSDF_FP32: rc = launch_track_frame<GSDF_FP32>(s, M, a, T_wc_inout_dev, partials, sync, stats_dev, status_dev); break;
-        case GSDF_BF16: rc = launch_track_frame<GSDF_BF16>(s, M, a, T_wc_inout_dev, partials, sync, stats_dev, status_dev); break;
-        default: rc = launch_track_frame<GSDF_FP16>(s, M, a, T_wc_inout_dev, partials, sync, stats_dev, status_dev); break;
+        case GSDF_FP32: rc = launch_track_frame<GSDF_FP32>(s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
+        case GSDF_BF16: rc = launch_track_frame<GSDF_BF16>(s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
+        default: rc = launch_track_frame<GSDF_FP16>(s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
     }
     if (rc != GSDF_OK) return rc;
     return launch_status();

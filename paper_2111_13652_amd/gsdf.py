@@ -133,18 +133,32 @@ class GsdfMap:
                                                      scratch.numel(), _ptr(self.status), _stream()),
                    "integrate_frame")
 
-    def fuse(self, depth: torch.Tensor, cam, pose: torch.Tensor, **kw) -> None:
-        self.allocate(depth, cam, pose)
-        self.integrate(depth, cam, pose, **kw)
-
-    def track(self, depth: torch.Tensor, cam, pose: torch.Tensor, levels: int = 3,
-              iters: Sequence[int] = (4, 5, 10), delta: float = 0.01, damping: float = 1e-6,
-              min_inlier_frac: float = 0.1, stats: Optional[torch.Tensor] = None) -> None:
-        """Coarse-to-fine tracking; ``pose`` (3x4 float64, device) is updated
-        in place.  ``iters[l]`` iterations at level l (0 = finest)."""
+    def fuse(self, depth: torch.Tensor, cam, pose: torch.Tensor, eps: Optional[float] = None,
+             cos_max_angle: float = COS_75) -> None:
+        """allocate + integrate in two launches (gsdf_fuse_frame); the same
+        result as the two calls in sequence."""
         c = camera(cam)
         _need(depth, torch.float32, (c.height, c.width), "depth")
         _need(pose, torch.float64, (3, 4), "pose")
+        p = _lib.FuseParams(float(self.voxel_size if eps is None else eps), float(cos_max_angle))
+        scratch = self._fuse_scratch_for(c)
+        _lib.check(_lib.load().gsdf_fuse_frame(C.byref(self._map), _ptr(depth), C.byref(c), _ptr(pose),
+                                                C.byref(p), _ptr(scratch), scratch.numel(), _ptr(self.status),
+                                                _stream()), "fuse_frame")
+
+    def track(self, depth: torch.Tensor, cam, pose: torch.Tensor, levels: int = 3,
+              iters: Sequence[int] = (4, 5, 10), delta: float = 0.01, damping: float = 1e-6,
+              min_inlier_frac: float = 0.1, stats: Optional[torch.Tensor] = None,
+              init: Optional[torch.Tensor] = None) -> None:
+        """Coarse-to-fine tracking; ``pose`` (3x4 float64, device) receives
+        the estimate, starting from ``init`` (default: ``pose`` itself, updated
+        in place).  ``iters[l]`` iterations at level l (0 = finest)."""
+        c = camera(cam)
+        _need(depth, torch.float32, (c.height, c.width), "depth")
+        _need(pose, torch.float64, (3, 4), "pose")
+        if init is None:
+            init = pose
+        _need(init, torch.float64, (3, 4), "init")
         it = list(iters) + [0] * (4 - len(iters))
         if stats is not None:
             _need(stats, torch.float32, None, "stats")
@@ -154,7 +168,7 @@ class GsdfMap:
                              float(min_inlier_frac), 0)
         scratch = self._scratch_for(c, levels)
         _lib.check(_lib.load().gsdf_track_frame(C.byref(self._map), _ptr(depth), C.byref(c),
-                                                 C.byref(p), _ptr(pose), _ptr(stats), _ptr(scratch),
+                                                 C.byref(p), _ptr(init), _ptr(pose), _ptr(stats), _ptr(scratch),
                                                  scratch.numel(), _ptr(self.status), _stream()),
                    "track_frame")
 
@@ -656,8 +670,8 @@ def run_stream(m: GsdfMap, depth: torch.Tensor, cam, pose0: torch.Tensor, levels
     poses_out[start].copy_(pose0)
     m.fuse(depth[start], cam, poses_out[start])
     for f in range(start + 1, stop):
-        poses_out[f].copy_(poses_out[f - 1])
-        m.track(depth[f], cam, poses_out[f], levels=levels, iters=iters, delta=delta, damping=damping)
+        m.track(depth[f], cam, poses_out[f], levels=levels, iters=iters, delta=delta, damping=damping,
+                init=poses_out[f - 1])
         m.fuse(depth[f], cam, poses_out[f])
     return poses_out
 

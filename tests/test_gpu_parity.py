@@ -234,3 +234,26 @@ def test_ragged_image_and_repeat_allocation(torch_mod):
     dr, dt = pose_diff(Pg.cpu().numpy(), To)
     log(f"  GPU vs oracle: {dr:.2e} rad, {dt:.2e} m")
     assert dr < 1e-5 and dt < 1e-5
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+def test_fuse_frame_equals_allocate_then_integrate(torch_mod, room_stream, storage):
+    """gsdf_fuse_frame (allocation and normals in one launch) leaves exactly
+    the map that gsdf_allocate_blocks + gsdf_integrate_frame leave."""
+    st = room_stream
+    A = _gpu_map(0.01, 0.05, storage=storage)
+    B = _gpu_map(0.01, 0.05, storage=storage)
+    for f in range(len(st.depth)):
+        log(f"case: fuse_frame vs allocate + integrate, room frame {f}, {storage}")
+        D, P = dev(st.depth[f]), dev(st.poses[f])
+        A.allocate(D, st.cam, P)
+        A.integrate(D, st.cam, P)
+        B.fuse(D, st.cam, P)
+    ka, kb = A.keys(), B.keys()
+    oa, ob = np.lexsort(ka.T[::-1]), np.lexsort(kb.T[::-1])
+    np.testing.assert_array_equal(ka[oa], kb[ob])
+    va, vb = A.voxels(len(ka)), B.voxels(len(kb))
+    for xa, xb in zip(va, vb):
+        np.testing.assert_array_equal(xa[oa], xb[ob])
+    np.testing.assert_array_equal(A.counters(), B.counters())
+    assert A.status_flags() == [] and B.status_flags() == []
