@@ -175,8 +175,9 @@ size_t gsdf_track_scratch_bytes(const gsdf_camera* cam, int32_t levels);
 /* track_frame (Sec. 4.1 Eq. (5), (14)-(16); Sec. 5.1): coarse-to-fine
  * Gauss-Newton on E = sum_k rho_delta(r_k), r_k = psi_j + g^_j . (T x_k - v_j)
  * with j the voxel nearest to T x_k, Jacobian [g^ ; (T x) x g^] for a left
- * perturbation in the world frame, and a damped 6x6 Cholesky solve in
- * float64 on the device; T <- exp(dxi) T.  T_init_dev (device, 12 f64) holds
+ * perturbation in the world frame, and a damped 6x6 Cholesky solve (its
+ * square-root-free LDL^T form) in float64 on the device; T <- exp(dxi) T.
+ * T_init_dev (device, 12 f64) holds
  * the initial pose and T_wc_out_dev (device, 12 f64) receives the estimate;
  * they may be the same buffer.  stats_dev (device, optional) receives 2
  * floats per iteration in execution order: the energy and the number of

@@ -1,6 +1,6 @@
 // track_frame: direct SDF tracking with one voxel lookup per pixel
 // (Gradient-SDF Sec. 4.1, Eq. (5) and (14)-(16)), Huber-weighted
-// Gauss-Newton, and the damped 6x6 Cholesky solve with a left SE(3) update
+// Gauss-Newton, and the damped 6x6 Cholesky solve (LDL^T form) with a left SE(3) update
 // (Sec. 5.1), all on the device.
 //
 // A frame is two launches: one kernel builds every pyramid level, and one
@@ -406,47 +406,111 @@ __device__ inline void total_partials(const double* partials, int groups, double
         for (int k = 0; k < kNE; ++k) ne[k] = r.tot[k];
 }
 
-// Cholesky solve of the damped 6x6 system and left update of the pose.
-__device__ bool solve_and_update(const double* ne, double damping, double* pose) {
-    double H[36];
-    int k = 0;
-    for (int i = 0; i < 6; ++i)
-        for (int j = i; j < 6; ++j) {
-            H[6 * i + j] = ne[k];
-            H[6 * j + i] = ne[k];
-            ++k;
-        }
-    double tr = 0;
-    for (int i = 0; i < 6; ++i) tr += H[7 * i];
+// The damped 6x6 solve and the left pose update, by one wave.
+//
+// Lane i < 6 holds row i of [H + mu I | -b] (mu = damping tr(H)/6).
+// Gaussian elimination without pivoting: H + mu I is symmetric positive
+// definite, so every pivot is positive and this is its LDL^T factorisation
+// (the same solution as a Cholesky solve, with no square roots).  The pivot
+// row is broadcast with readlane, each lane below it eliminates its own
+// entry, and back substitution broadcasts each unknown as it is found.  Then
+// lane k < 12 forms entry k = 4 i + j of exp(x^) T from row i of R and V
+// (the closed forms of se3_exp) and column j of T.  ne is the float64 sum
+// (21 upper entries of H row by row, then b) in LDS; pose is the 3x4 pose in
+// LDS, replaced in place.  Every lane returns the same flag: false when a
+// pivot is not positive, with the pose unchanged.
+
+__device__ inline double bcast_lane(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// 1/p to within an ulp: hardware reciprocal and one Newton step.
+__device__ inline double recip(double p) {
+    double r = __builtin_amdgcn_rcp(p);
+    const double e = fma(-p, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ inline int upper_index(int i, int j) { return i * 6 - (i * (i - 1)) / 2 + (j - i); }  // i <= j
+
+__device__ inline bool solve_update_wave(const double* ne, double damping, double* pose) {
+    const int lane = threadIdx.x & 63;
+    const int i = lane < 6 ? lane : 5;  // lanes 6.. shadow row 5; their values are never read
+    double tr = 0.0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) tr += ne[upper_index(d, d)];
     const double mu = damping * tr / 6.0;
-    for (int i = 0; i < 6; ++i) H[7 * i] += mu;
-    double L[36], inv_d[6];
-    for (int i = 0; i < 36; ++i) L[i] = 0.0;
+    double row[7];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const double h = ne[i <= c ? upper_index(i, c) : upper_index(c, i)];
+        row[c] = c == i ? h + mu : h;
+    }
+    row[6] = -ne[21 + i];
+    double inv_piv[6];
+    bool ok = true;
+#pragma unroll
     for (int j = 0; j < 6; ++j) {
-        double s = H[7 * j];
-        for (int q = 0; q < j; ++q) s -= L[6 * j + q] * L[6 * j + q];
-        if (!(s > 0.0)) return false;
-        const double d = sqrt(s);
-        L[7 * j] = d;
-        inv_d[j] = 1.0 / d;
-        for (int i = j + 1; i < 6; ++i) {
-            double t = H[6 * i + j];
-            for (int q = 0; q < j; ++q) t -= L[6 * i + q] * L[6 * j + q];
-            L[6 * i + j] = t * inv_d[j];
+        double pr[7];
+#pragma unroll
+        for (int c = j; c < 7; ++c) pr[c] = bcast_lane(row[c], j);
+        ok = ok && pr[j] > 0.0;
+        inv_piv[j] = recip(pr[j]);
+        const double f = lane > j ? row[j] * inv_piv[j] : 0.0;
+#pragma unroll
+        for (int c = j + 1; c < 7; ++c) row[c] = fma(-f, pr[c], row[c]);
+    }
+    if (!ok) return false;
+    double x[6];
+    double rhs = row[6];
+#pragma unroll
+    for (int c = 5; c >= 0; --c) {
+        x[c] = bcast_lane(rhs * inv_piv[c], c);
+        rhs = fma(-row[c], x[c], rhs);
+    }
+    // exp of the twist (rho, phi) = (x[0..2], x[3..5]); coefficients as in se3_exp
+    const double p0 = x[3], p1 = x[4], p2 = x[5];
+    const double th2 = p0 * p0 + p1 * p1 + p2 * p2;
+    const double th = sqrt(th2);
+    double A, B, C;
+    if (th < 0.02) {
+        const double t4 = th2 * th2, t6 = t4 * th2, t8 = t4 * t4;
+        A = 1.0 - th2 / 6.0 + t4 / 120.0 - t6 / 5040.0 + t8 / 362880.0;
+        B = 0.5 - th2 / 24.0 + t4 / 720.0 - t6 / 40320.0 + t8 / 3628800.0;
+        C = 1.0 / 6.0 - th2 / 120.0 + t4 / 5040.0 - t6 / 362880.0 + t8 / 39916800.0;
+    } else {
+        const double sn = sin(th), cs = cos(th);
+        A = sn / th;
+        B = (1.0 - cs) / th2;
+        C = (th - sn) / (th2 * th);
+    }
+    if (lane < 12) {
+        const int r = lane >> 2, col = lane & 3;
+        // row r of K = phi^ and of K^2 = phi phi^T - th2 I
+        const double pr_ = r == 0 ? p0 : (r == 1 ? p1 : p2);
+        const double k0 = r == 0 ? 0.0 : (r == 1 ? p2 : -p1);
+        const double k1 = r == 0 ? -p2 : (r == 1 ? 0.0 : p0);
+        const double k2 = r == 0 ? p1 : (r == 1 ? -p0 : 0.0);
+        const double q0 = pr_ * p0 - (r == 0 ? th2 : 0.0);
+        const double q1 = pr_ * p1 - (r == 1 ? th2 : 0.0);
+        const double q2 = pr_ * p2 - (r == 2 ? th2 : 0.0);
+        const double R0 = (r == 0 ? 1.0 : 0.0) + A * k0 + B * q0;
+        const double R1 = (r == 1 ? 1.0 : 0.0) + A * k1 + B * q1;
+        const double R2 = (r == 2 ? 1.0 : 0.0) + A * k2 + B * q2;
+        double out = R0 * pose[col] + R1 * pose[4 + col] + R2 * pose[8 + col];
+        if (col == 3) {
+            const double V0 = (r == 0 ? 1.0 : 0.0) + B * k0 + C * q0;
+            const double V1 = (r == 1 ? 1.0 : 0.0) + B * k1 + C * q1;
+            const double V2 = (r == 2 ? 1.0 : 0.0) + B * k2 + C * q2;
+            out += V0 * x[0] + V1 * x[1] + V2 * x[2];
         }
+        // every lane's reads of the pose above precede this store (the store
+        // depends on them, and the wave issues LDS operations in order)
+        pose[lane] = out;
     }
-    double y[6], x[6];
-    for (int i = 0; i < 6; ++i) {
-        double s = -ne[21 + i];
-        for (int q = 0; q < i; ++q) s -= L[6 * i + q] * y[q];
-        y[i] = s * inv_d[i];
-    }
-    for (int i = 5; i >= 0; --i) {
-        double s = y[i];
-        for (int q = i + 1; q < 6; ++q) s -= L[6 * q + i] * x[q];
-        x[i] = s * inv_d[i];
-    }
-    se3_apply_left(x, pose);   // twist (rho, phi) = (x[0..2], x[3..5])
     return true;
 }
 
@@ -604,7 +668,7 @@ __device__ inline bool wait_done(unsigned* sync, unsigned target) {
 // grid-wide reduction, which falls with fewer groups until the per-thread
 // pixel chains and the arrival contention take over.
 constexpr int kPixPerGroup = 1024;
-constexpr int kMinGroups = 72;
+constexpr int kMinGroups = 128;
 __device__ inline int level_groups(const TrackLevel& L, int G) {
     int g = (L.W * L.H + kPixPerGroup - 1) / kPixPerGroup;
     g = g < kMinGroups ? kMinGroups : g;
@@ -679,22 +743,19 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
             // every work-group: the same sum of the leaf sums, the same solve
             double ne[kNE];
             total_partials<COMP>(leafpart, nleaf, ne, red);
-            if (threadIdx.x == 0) {
-                double Pn[12];
-                for (int k = 0; k < 12; ++k) Pn[k] = s_pose[k];
-                const bool solved = solve_and_update(ne, a.damping, Pn);
-                if (solved)
-                    for (int k = 0; k < 12; ++k) s_pose[k] = Pn[k];
-                if (blockIdx.x == 0) {
+            if (threadIdx.x < 64) {
+                const bool solved = solve_update_wave(red.tot, a.damping, s_pose);
+                if (blockIdx.x == 0 && threadIdx.x == 0) {
+                    const double* t = red.tot;
                     if (!solved) raise_status(status, GSDF_ENOTPD);
-                    if (l == 0 && it == a.iters[0] - 1 && ne[28] < (double)a.min_inlier_frac * ne[29])
+                    if (l == 0 && it == a.iters[0] - 1 && t[28] < (double)a.min_inlier_frac * t[29])
                         raise_status(status, GSDF_ELOST);
                     if (stats) {
-                        stats[2 * gi] = (float)ne[27];
-                        stats[2 * gi + 1] = (float)ne[28];
+                        stats[2 * gi] = (float)t[27];
+                        stats[2 * gi + 1] = (float)t[28];
                     }
-                    add_stat(M, kStatTrackValid, (unsigned long long)ne[29]);
-                    add_stat(M, kStatTrackUsed, (unsigned long long)ne[28]);
+                    add_stat(M, kStatTrackValid, (unsigned long long)t[29]);
+                    add_stat(M, kStatTrackUsed, (unsigned long long)t[28]);
                 }
             }
             __syncthreads();
@@ -814,7 +875,7 @@ inline int normal_eq_groups(int npx) {
     return g < 1 ? 1 : (g > kMaxGroups ? kMaxGroups : g);
 }
 
-// Co-resident work-group count for the cooperative kernel (cached per device).
+// Work-group count of the cooperative kernel (cached per device).
 template <int STORAGE>
 int coop_groups() {
     static int cached[64] = {0};
@@ -826,7 +887,9 @@ int coop_groups() {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_track_frame<STORAGE>, kTrackBlock, 0) !=
         hipSuccess)
         return 0;
-    int g = cus * (per_cu < 2 ? per_cu : 2);
+    // one work-group per CU: measured faster than two at 640x480 (the
+    // per-iteration reduction cost grows with the group count)
+    int g = per_cu > 0 ? cus : 0;
     if (g > kMaxGroups) g = kMaxGroups;
     cached[dev] = g;
     return g;
