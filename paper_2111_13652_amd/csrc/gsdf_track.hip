@@ -359,9 +359,9 @@ __device__ inline void store_partial(const float acc[kNE], const float cmp[kNE],
     __syncthreads();
 }
 
-// Sum of `groups` partials (called by the last arriver; device-scope loads
-// see every partial stored before its ticket).  Thread (k, p) adds entry k of
-// the partials p, p+8, ... with eight loads in flight.  Result in ne[] of
+// Sum of `groups` partials (device-scope loads, issued after the signal
+// that every one of them was stored).  Thread (k, p) adds entry k of the
+// partials p, p+8, ... in that order, with up to sixteen loads in flight.  Result in ne[] of
 // thread 0.
 template <bool COMP>
 __device__ inline void total_partials(const double* partials, int groups, double ne[kNE], ReduceLds& r) {
@@ -370,6 +370,17 @@ __device__ inline void total_partials(const double* partials, int groups, double
         double s = 0.0;
         Kahan ks;
         int b = p;
+        for (; b + 120 < groups; b += 128) {
+            double x[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                x[j] = __hip_atomic_load(&partials[(size_t)(b + 8 * j) * kPartStride + k], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (COMP) ks.add((float)x[j]); else s += x[j];
+            }
+        }
         for (; b + 56 < groups; b += 64) {
             double x[8];
 #pragma unroll
@@ -533,8 +544,9 @@ __device__ inline void complete_device_stores() { __builtin_amdgcn_s_waitcnt(0);
 // work-groups share a leaf ticket; two ticket sets alternate between
 // iterations.  Single-launch reductions (the normal equations) close the
 // tree with a root ticket; the tracking kernel instead counts published leaf
-// sums in a monotonic done word that every work-group polls.  Then an abort
-// flag.
+// sums in a monotonic done word that the work-groups of the level poll, and
+// publishes the pose at level boundaries for work-groups that join.  Then an
+// abort flag.
 constexpr int kLeaf = 16;
 constexpr int kMaxLeaves = kMaxGroups / kLeaf;
 // one set of partials: a partial per work-group, then one per leaf
@@ -543,7 +555,8 @@ enum {
     kSyncLeaf = 0,                          // [2][kMaxLeaves]
     kSyncRoot = kSyncLeaf + 2 * kMaxLeaves,  // [2]
     kSyncDone = kSyncRoot + 2,
-    kSyncAbort = kSyncDone + 1,
+    kSyncPub = kSyncDone + 1,               // iterations reflected by the published pose
+    kSyncAbort = kSyncPub + 1,
     kSyncWords = kSyncAbort + 1
 };
 
@@ -647,12 +660,12 @@ __device__ inline void contribute(const float acc[kNE], const float cmp[kNE], do
     }
 }
 
-// Wait (thread 0 only) until `target` leaf sums have been published in
-// total; device-scope polling with a short sleep.  Returns false on timeout
-// or when another work-group aborted.
-__device__ inline bool wait_done(unsigned* sync, unsigned target) {
+// Wait (thread 0 only) until the sync word `word` reaches `target`;
+// device-scope polling with a short sleep.  Returns false on timeout or when
+// another work-group aborted.
+__device__ inline bool wait_done(unsigned* sync, int word, unsigned target) {
     unsigned spins = 0;
-    while (__hip_atomic_load(&sync[kSyncDone], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(&sync[word], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         if (++spins > kSpinLimit ||
             __hip_atomic_load(&sync[kSyncAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             return false;
@@ -676,11 +689,18 @@ __device__ inline int level_groups(const TrackLevel& L, int G) {
 }
 
 // The whole coarse-to-fine Gauss-Newton of one frame (cooperative launch).
-// Buffer reuse: partials and leaf sums alternate between two sets by
-// iteration parity.  A work-group writes set (gi & 1) again at gi + 2 only
-// after it has seen every leaf sum of gi + 1, and each of those was
-// published after its leaf's work-groups had finished reading the sums of
-// gi, so no set is overwritten while it is still read.
+//
+// Only the members of a level (the first Gl work-groups) run its
+// iterations; a work-group that joins at a later level takes the pose that
+// work-group 0 publishes at the end of the previous level (it publishes only
+// when the next level has more members).  Buffer reuse: partials and leaf
+// sums alternate between two sets by iteration parity.  A member writes set
+// (gi & 1) again at gi + 2 only after it has seen every leaf sum of gi + 1;
+// each of those was published after its leaf's members had contributed to
+// gi + 1, which they do only after reading the sums of gi, so no member
+// reads a set while it is overwritten.  The published pose of a level
+// boundary is overwritten only at the next boundary, which needs the
+// contributions of the work-groups that joined and read it.
 template <int STORAGE>
 __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArgs a, const double* pose_in,
                                                               double* pose_out, double* partials, unsigned* sync,
@@ -691,6 +711,7 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
     __shared__ float s_depth[kTrackBatch * kTrackBlock];
     constexpr bool COMP = STORAGE != GSDF_FP32;
     const int G = gridDim.x;
+    double* pose_pub = partials + 2 * kPartsPerSet;
     // a work-group that takes part in no level holds nothing anyone needs
     int span = 1;
     for (int l = 0; l < a.levels; ++l)
@@ -702,36 +723,22 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
     if (threadIdx.x < 12) s_pose[threadIdx.x] = pose_in[threadIdx.x];
     __syncthreads();
     int gi = 0;           // global iteration index
+    int have = 0;         // iterations the pose in s_pose reflects
     unsigned target = 0;  // leaf sums published once iteration gi is complete
     for (int l = a.levels - 1; l >= 0; --l) {
+        if (a.iters[l] == 0) continue;
         const TrackLevel L = a.lv[l];
         const int Gl = level_groups(L, G);
         const int nleaf = (Gl + kLeaf - 1) / kLeaf;
-        const bool member = (int)blockIdx.x < Gl;
-        // a member's pixels are the same in every iteration of the level:
-        // the depths of each thread's first batch are loaded once and kept
-        // in LDS (each thread reads back only what it wrote)
-        const int first = blockIdx.x * kTrackBlock + threadIdx.x;
-        if (member) {
-#pragma unroll
-            for (int j = 0; j < kTrackBatch; ++j) {
-                const int i = first + j * Gl * kTrackBlock;
-                s_depth[j * kTrackBlock + threadIdx.x] = i < L.W * L.H ? L.depth[i] : 0.0f;
-            }
+        if ((int)blockIdx.x >= Gl) {
+            // not a member: skip the level
+            gi += a.iters[l];
+            target += (unsigned)(nleaf * a.iters[l]);
+            continue;
         }
-        for (int it = 0; it < a.iters[l]; ++it, ++gi) {
-            double* part = partials + (size_t)(gi & 1) * kPartsPerSet;
-            double* leafpart = part + (size_t)kMaxGroups * kPartStride;
-            if (member) {
-                double P[12];
-#pragma unroll
-                for (int k = 0; k < 12; ++k) P[k] = s_pose[k];
-                float acc[kNE], cmp[kNE];
-                accumulate<STORAGE>(M, L, a, P, first, Gl * kTrackBlock, s_depth, acc, cmp);
-                contribute<COMP>(acc, cmp, part, leafpart, sync, gi & 1, Gl, red, &s_flag);
-            }
-            target += (unsigned)nleaf;
-            if (threadIdx.x == 0) s_ok = wait_done(sync, target) ? 1 : 0;
+        if (have < gi) {
+            // joining: take the pose published at the end of the previous level
+            if (threadIdx.x == 0) s_ok = wait_done(sync, kSyncPub, (unsigned)gi) ? 1 : 0;
             __syncthreads();
             if (!s_ok) {
                 if (threadIdx.x == 0) {
@@ -740,7 +747,41 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
                 }
                 return;
             }
-            // every work-group: the same sum of the leaf sums, the same solve
+            if (threadIdx.x < 12)
+                s_pose[threadIdx.x] =
+                    __hip_atomic_load(&pose_pub[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            have = gi;
+        }
+        // a member's pixels are the same in every iteration of the level:
+        // the depths of each thread's first batch are loaded once and kept
+        // in LDS (each thread reads back only what it wrote)
+        const int first = blockIdx.x * kTrackBlock + threadIdx.x;
+#pragma unroll
+        for (int j = 0; j < kTrackBatch; ++j) {
+            const int i = first + j * Gl * kTrackBlock;
+            s_depth[j * kTrackBlock + threadIdx.x] = i < L.W * L.H ? L.depth[i] : 0.0f;
+        }
+        for (int it = 0; it < a.iters[l]; ++it, ++gi) {
+            double* part = partials + (size_t)(gi & 1) * kPartsPerSet;
+            double* leafpart = part + (size_t)kMaxGroups * kPartStride;
+            double P[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) P[k] = s_pose[k];
+            float acc[kNE], cmp[kNE];
+            accumulate<STORAGE>(M, L, a, P, first, Gl * kTrackBlock, s_depth, acc, cmp);
+            contribute<COMP>(acc, cmp, part, leafpart, sync, gi & 1, Gl, red, &s_flag);
+            target += (unsigned)nleaf;
+            if (threadIdx.x == 0) s_ok = wait_done(sync, kSyncDone, target) ? 1 : 0;
+            __syncthreads();
+            if (!s_ok) {
+                if (threadIdx.x == 0) {
+                    __hip_atomic_store(&sync[kSyncAbort], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    raise_status(status, GSDF_EHIP);
+                }
+                return;
+            }
+            // every member: the same sum of the leaf sums, the same solve
             double ne[kNE];
             total_partials<COMP>(leafpart, nleaf, ne, red);
             if (threadIdx.x < 64) {
@@ -759,6 +800,24 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
                 }
             }
             __syncthreads();
+        }
+        have = gi;
+        // publish for the work-groups that join at the next level
+        int next_groups = 0;
+        for (int n = l - 1; n >= 0; --n)
+            if (a.iters[n] > 0) {
+                next_groups = level_groups(a.lv[n], G);
+                break;
+            }
+        if (blockIdx.x == 0 && next_groups > Gl) {
+            if (threadIdx.x < 12)
+                __hip_atomic_store(&pose_pub[threadIdx.x], s_pose[threadIdx.x], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                complete_device_stores();
+                __hip_atomic_store(&sync[kSyncPub], (unsigned)gi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
     }
     if (blockIdx.x == 0 && threadIdx.x < 12) pose_out[threadIdx.x] = s_pose[threadIdx.x];
@@ -857,7 +916,7 @@ inline ScratchLayout scratch_layout(const gsdf_camera& c, int levels) {
     ScratchLayout s;
     size_t o = 0;
     s.sync = o;     o = align256(o + kSyncWords * 4);
-    s.partials = o; o = align256(o + 2 * kPartsPerSet * 8);
+    s.partials = o; o = align256(o + (2 * kPartsPerSet + 16) * 8);  // two sets, then the published pose
     int W = c.width, H = c.height;
     s.level[0] = 0;
     for (int l = 1; l < 4; ++l) {
