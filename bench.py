@@ -5,13 +5,17 @@ cx = 319.5, cy = 239.5), 1 cm voxels, 5 cm truncation, 8^3 blocks,
 3-level pyramid with 4/5/10 Gauss-Newton iterations (finest first), Huber
 delta 1 cm.  Depth noise sigma(z) = 0.0012 + 0.0019 (z - 0.4)^2, range
 0.4-4 m.  One step = one frame: track it against the map, then allocate and
-integrate it at the estimated pose.  Frame 0 is fused at its ground-truth
+integrate it at the estimated pose (gsdf_track_frame, gsdf_fuse_frame).  Frame 0 is fused at its ground-truth
 pose before the warm-up.  All depth frames are resident in HBM before the
 timed region starts.
 
 Prints one JSON line.  Extra fields: "roofline" (dominant kernel),
 "cpu_baseline" (the FP64 oracle on a bounded sample of the same stream),
-"kernels" (per-kernel event timing), "accuracy".
+"kernels" (per-kernel event timing), "accuracy".  Inside the timed region
+only the tracking kernel records events (two per frame; its duration feeds
+the roofline); "kernels" comes from a second pass over the same frames with
+every kernel timed, which is not part of "value" (events around every
+launch cost about 9 % of the frame rate).
 """
 from __future__ import annotations
 
@@ -46,13 +50,13 @@ B_ALLOC_PAIR = 16.0        # hash entry per distinct (tile, block) probe
 # figure is reported only while the kernel's sources still hash to the
 # values they had when the counters were taken.
 MEASURED_TRAFFIC = {
-    "track": {"bytes": (13443.3 * 1.9998 + 806.0 * 1.0000) * 1024,
-              "sources": {"gsdf_track.hip": "7a9c891f708bc608da746830c1cf5d103cb6f196ed2cbd1010df8fb7be8965f6",
-                          "gsdf_common.hpp": "accfd9a487ef21d1dc41374aca70c29fa5bd8d073cea674d16d78099d8a35574",
+    "track": {"bytes": (13772.5 * 1.9998 + 886.9 * 1.0000) * 1024,
+              "sources": {"gsdf_track.hip": "7d78d55c90b485ed473c91f79a033bff0356158c81ffe866089a189673cb07d9",
+                          "gsdf_common.hpp": "b1b85872a85ba22d8f1fb4f97babef87774323fbb1458396f354eee1e14379fa",
                           "gsdf_se3.hpp": "13c15ea94701e1129da7175cf338be9aa9cc57bf8857172577cef813f6209733"}},
-    "fuse_blocks": {"bytes": (20496.1 * 1.9998 + 11863.4 * 1.0000) * 1024,
-              "sources": {"gsdf_fuse.hip": "905fa2c99f7e89fb72200c6befddf00fab0edfd32c95014c08b7900d95020b0f",
-                          "gsdf_common.hpp": "accfd9a487ef21d1dc41374aca70c29fa5bd8d073cea674d16d78099d8a35574"}},
+    "fuse_blocks": {"bytes": (20661.9 * 1.9998 + 11862.7 * 1.0000) * 1024,
+              "sources": {"gsdf_fuse.hip": "c675cc9ade8009668dc68bea73242a66e0a03a56a0e6384fe883b5f3808aaa82",
+                          "gsdf_common.hpp": "b1b85872a85ba22d8f1fb4f97babef87774323fbb1458396f354eee1e14379fa"}},
 }
 
 
@@ -141,7 +145,9 @@ def main():
     lib = _lib.load()
     timing = not args.no_timing
     if timing:
-        lib.gsdf_timing_enable(1)
+        # inside the timed region only the roofline kernel (tracking) records
+        # events (two per frame); the per-kernel breakdown is a second pass
+        lib.gsdf_timing_select(1 << _lib.K_TRACK)
     first = 1 + args.warmup
     c0 = m.counters()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -158,15 +164,29 @@ def main():
     work = (c1 - c0).astype(np.float64)
     status = m.status_flags()
 
-    kernels = {}
-    if timing:
+    def read_kernels():
+        out = {}
         for name, kid in (("track", _lib.K_TRACK), ("fuse_blocks", _lib.K_INTEGRATE),
                           ("alloc_normals", _lib.K_ALLOC_NORMALS), ("pyramid", _lib.K_PYRAMID)):
             tot = C.c_double()
             n = C.c_int64()
             lib.gsdf_timing_read(kid, C.byref(tot), C.byref(n))
-            kernels[name] = {"total_ms": tot.value, "launches": n.value,
+            if n.value:
+                out[name] = {"total_ms": tot.value, "launches": n.value,
                              "avg_us": 1e3 * tot.value / max(1, n.value)}
+        return out
+
+    kernels = {}
+    track_live = None
+    if timing:
+        track_live = read_kernels().get("track")
+        # breakdown pass: the same frames again with every kernel timed
+        start()
+        lib.gsdf_timing_enable(1)
+        for f in range(first, first + args.steps):
+            step(f)
+        torch.cuda.synchronize()
+        kernels = read_kernels()
         lib.gsdf_timing_enable(0)
 
     # ---- algorithmic bytes, from the live work counters
@@ -185,8 +205,11 @@ def main():
     roofline = None
     if kernels:
         dom = max(("track", "fuse_blocks", "alloc_normals"), key=lambda k: kernels[k]["total_ms"])
-        launches = max(1, kernels[dom]["launches"])
-        avg_s = kernels[dom]["total_ms"] / 1e3 / launches
+        # the dominant kernel's duration from the timed region when it is the
+        # one timed there, else from the breakdown pass
+        live = track_live if dom == "track" and track_live else kernels[dom]
+        launches = max(1, live["launches"])
+        avg_s = live["total_ms"] / 1e3 / launches
         bytes_per_launch = per_kernel_bytes[dom] / launches
         achieved = bytes_per_launch / avg_s / 1e9
         roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,

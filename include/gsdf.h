@@ -421,6 +421,11 @@ enum {
  * clear the accumulated totals. */
 int gsdf_timing_enable(int32_t on);
 
+/* Event timing around the launches of the kernel ids whose bits are set in
+ * `mask` only (0 disables), clearing the accumulated totals; each timed
+ * launch records two events on its stream. */
+int gsdf_timing_select(uint32_t mask);
+
 /* Total milliseconds and launch count recorded for one kernel id since the
  * last enable; synchronises the recorded events. */
 int gsdf_timing_read(int32_t kernel_id, double* total_ms, int64_t* launches);

@@ -90,6 +90,7 @@ _SIGNATURES = {
     "gsdf_extract_surfels": (_I, [C.POINTER(Map), _I32, _P, _P, _P, C.c_int64, _P, _P, _SZ, _P]),
     "gsdf_gradient_quality": (_I, [C.POINTER(Map), _P, _I32, _P, C.c_int64, _P]),
     "gsdf_timing_enable": (_I, [_I32]),
+    "gsdf_timing_select": (_I, [C.c_uint32]),
     "gsdf_timing_read": (_I, [_I32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "gsdf_status_string": (C.c_char_p, [_I32]),
 }

@@ -13,7 +13,7 @@
 namespace gsdf {
 
 // ---- optional per-kernel event timing (see gsdf_timing_enable) ----
-bool timing_on();
+bool timing_on(int kernel_id);
 void timing_begin(int kernel_id, hipStream_t s);
 void timing_end(int kernel_id, hipStream_t s);
 
@@ -21,7 +21,7 @@ struct TimedLaunch {
     int id;
     hipStream_t s;
     bool on;
-    TimedLaunch(int kernel_id, hipStream_t stream) : id(kernel_id), s(stream), on(timing_on()) {
+    TimedLaunch(int kernel_id, hipStream_t stream) : id(kernel_id), s(stream), on(timing_on(kernel_id)) {
         if (on) timing_begin(id, s);
     }
     ~TimedLaunch() {

@@ -18,7 +18,7 @@ namespace gsdf {
 namespace {
 struct TimerState {
     std::mutex mu;
-    bool on = false;
+    uint32_t mask = 0;  // bit k: time kernel id k
     std::vector<std::pair<hipEvent_t, hipEvent_t>> done[GSDF_K_COUNT];
     hipEvent_t open[GSDF_K_COUNT] = {};
     std::vector<hipEvent_t> pool;
@@ -39,7 +39,7 @@ hipEvent_t take_event(TimerState& t) {
 }
 }  // namespace
 
-bool timing_on() { return timer().on; }
+bool timing_on(int id) { return (timer().mask >> id) & 1u; }
 
 void timing_begin(int id, hipStream_t s) {
     TimerState& t = timer();
@@ -273,7 +273,9 @@ int gsdf_import_blocks(gsdf_map* map, const int32_t* keys_dev, int32_t n, const 
     return launch_status();
 }
 
-int gsdf_timing_enable(int32_t on) {
+int gsdf_timing_enable(int32_t on) { return gsdf_timing_select(on ? 0xffffffffu : 0u); }
+
+int gsdf_timing_select(uint32_t mask) {
     TimerState& t = timer();
     std::lock_guard<std::mutex> g(t.mu);
     for (int k = 0; k < GSDF_K_COUNT; ++k) {
@@ -287,7 +289,7 @@ int gsdf_timing_enable(int32_t on) {
             t.open[k] = nullptr;
         }
     }
-    t.on = on != 0;
+    t.mask = mask;
     return GSDF_OK;
 }
 

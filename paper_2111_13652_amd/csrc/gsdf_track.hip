@@ -4,8 +4,8 @@
 // (Sec. 5.1), all on the device.
 //
 // A frame is two launches: one kernel builds every pyramid level, and one
-// cooperative (all work-groups co-resident) kernel runs every Gauss-Newton
-// iteration of every level.  In an iteration each thread walks a strided
+// kernel whose work-groups are all resident at once (one per CU) runs every
+// Gauss-Newton iteration of every level.  In an iteration each thread walks a strided
 // set of pixels and accumulates, in float32 registers, the 21 upper entries
 // of H = sum w J J^T, the 6 of b = sum w J r, the energy, the count of
 // pixels used and the count of valid pixels.  From there every sum is
@@ -688,7 +688,7 @@ __device__ inline int level_groups(const TrackLevel& L, int G) {
     return g > G ? G : g;
 }
 
-// The whole coarse-to-fine Gauss-Newton of one frame (cooperative launch).
+// The whole coarse-to-fine Gauss-Newton of one frame (one launch, one work-group per CU).
 //
 // Only the members of a level (the first Gl work-groups) run its
 // iterations; a work-group that joins at a later level takes the pose that
@@ -934,9 +934,16 @@ inline int normal_eq_groups(int npx) {
     return g < 1 ? 1 : (g > kMaxGroups ? kMaxGroups : g);
 }
 
-// Work-group count of the cooperative kernel (cached per device).
+// Work-group count of the tracking kernel (cached per device): one per CU.
+// The work-groups wait for each other, so all of them must be resident at
+// once.  The occupancy query confirms that a CU holds at least one; the
+// grid then fits the device with room to spare.  The kernel is launched
+// like any other on the stream (a cooperative launch costs about 15 us more
+// per frame in dispatch, measured on MI355X): on a device that other work
+// keeps partly busy the last work-groups start late, and every wait is
+// bounded, so the worst case is a frame that fails with GSDF_EHIP.
 template <int STORAGE>
-int coop_groups() {
+int track_groups() {
     static int cached[64] = {0};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
@@ -957,15 +964,10 @@ int coop_groups() {
 template <int STORAGE>
 int launch_track_frame(hipStream_t s, const MapView& M, const TrackArgs& a, const double* pose_in,
                        double* pose_out, double* partials, unsigned* sync, float* stats, int32_t* status) {
-    const int g = coop_groups<STORAGE>();
+    const int g = track_groups<STORAGE>();
     if (g <= 0) return GSDF_EHIP;
-    MapView Mv = M;
-    TrackArgs av = a;
-    void* args[] = {&Mv, &av, &pose_in, &pose_out, &partials, &sync, &stats, &status};
     TimedLaunch tl(GSDF_K_TRACK, s);
-    if (hipLaunchCooperativeKernel((const void*)k_track_frame<STORAGE>, dim3(g), dim3(kTrackBlock), args, 0,
-                                   s) != hipSuccess)
-        return GSDF_EHIP;
+    k_track_frame<STORAGE><<<g, kTrackBlock, 0, s>>>(M, a, pose_in, pose_out, partials, sync, stats, status);
     return GSDF_OK;
 }
 
