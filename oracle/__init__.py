@@ -69,6 +69,8 @@ def _load():
         "orc_normal_equations": (None, [_P, _P, _P, _P, _D, _P]),
         "orc_gn_level": (_I, [_P, _P, _P, _I, _D, _D, _P, _P]),
         "orc_track": (_I, [_P, _P, _P, _I, _P, _D, _D, _P, _P]),
+        "orc_track_model": (_I, [_P, _P, _P, _I, _P, _D, _D, _P, _P, _I]),
+        "orc_trilinear": (_I, [_P, _P, _P, _P]),
         "orc_cholesky_solve6": (_I, [_P, _P, _P]),
         "orc_se3_exp": (None, [_P, _P]),
         "orc_se3_left_jacobian": (None, [_P, _P]),
@@ -219,14 +221,25 @@ class OracleMap:
         return Tn, stats, int(failed)
 
     def track(self, depth: np.ndarray, cam, T, levels: int, iters: Sequence[int], delta: float,
-              damping: float = 1e-6):
+              damping: float = 1e-6, model: str = "taylor"):
+        """Coarse-to-fine tracking; model "taylor" (Eq. (14)-(16)) or
+        "trilinear" (Eq. (12)-(13)).  Returns (pose, stats, failed solves)."""
         Tn = _c(T, np.float64).copy()
         it = _c(list(iters)[:levels], np.int32)
         stats = np.zeros((int(it.sum()), 2))
         c = cam_struct(cam)
-        failed = _load().orc_track(self._h, _ptr(_c(depth, np.float32)), C.byref(c), int(levels),
-                                   _ptr(it), float(delta), float(damping), _ptr(Tn), _ptr(stats))
+        failed = _load().orc_track_model(self._h, _ptr(_c(depth, np.float32)), C.byref(c), int(levels),
+                                         _ptr(it), float(delta), float(damping), _ptr(Tn), _ptr(stats),
+                                         {"taylor": 0, "trilinear": 1}[model])
         return Tn, stats, int(failed)
+
+    def trilinear(self, q) -> Optional[tuple]:
+        """Tri-linear distance and gradient at world point q (Eq. (12)-(13)),
+        or None when one of the eight voxels is missing or unobserved."""
+        r = C.c_double()
+        g = np.zeros(3)
+        ok = _load().orc_trilinear(self._h, _ptr(_c(q, np.float64)), C.byref(r), _ptr(g))
+        return (r.value, g) if ok else None
 
     def taylor(self, q) -> Optional[tuple]:
         r = C.c_double()

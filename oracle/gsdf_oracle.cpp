@@ -435,11 +435,54 @@ bool taylor(const OrcMap* M, const double* q, double* r, double* gh, I3* mstar, 
     return true;
 }
 
+// Tri-linear distance at q (Sec. 4.1 Eq. (12)-(13)), the direct SDF tracking
+// the paper compares against: the 8 voxel centres around q,
+// v_s (b + (i, j, k)) with b = floor(q / v_s) and i, j, k in {0, 1}, weighted
+// by the tri-linear coefficients of f = q / v_s - b; its gradient is the
+// derivative of that interpolant, i.e. differences of corner values along
+// each axis weighted bilinearly in the other two (the same eight lookups).
+// Returns false unless all eight voxels are allocated and observed.
+bool trilinear(const OrcMap* M, const double* q, double* r, double* grad) {
+    const double vs = M->vs;
+    int b[3];
+    double f[3];
+    for (int a = 0; a < 3; ++a) {
+        const double s = q[a] / vs;
+        b[a] = (int)std::floor(s);
+        f[a] = s - b[a];
+    }
+    double c[2][2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int k = 0; k < 2; ++k) {
+                const Voxel* V = find_voxel(M, {b[0] + i, b[1] + j, b[2] + k});
+                if (!V || !(V->W > 0.0)) return false;
+                c[i][j][k] = V->psi;
+            }
+    const double wx[2] = {1.0 - f[0], f[0]}, wy[2] = {1.0 - f[1], f[1]}, wz[2] = {1.0 - f[2], f[2]};
+    double d = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int k = 0; k < 2; ++k) d += c[i][j][k] * wx[i] * wy[j] * wz[k];
+    for (int j = 0; j < 2; ++j)
+        for (int k = 0; k < 2; ++k) gx += (c[1][j][k] - c[0][j][k]) * wy[j] * wz[k];
+    for (int i = 0; i < 2; ++i)
+        for (int k = 0; k < 2; ++k) gy += (c[i][1][k] - c[i][0][k]) * wx[i] * wz[k];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) gz += (c[i][j][1] - c[i][j][0]) * wx[i] * wy[j];
+    *r = d;
+    grad[0] = gx / vs;
+    grad[1] = gy / vs;
+    grad[2] = gz / vs;
+    return true;
+}
+
 // Normal equations of the Huber-weighted tracking energy at pose T for one
 // depth image (values in double).  out29 = 21 upper-triangular H entries
-// (row-major), 6 of b, energy, count.
+// (row-major), 6 of b, energy, count.  model 0: the Taylor distance of
+// Eq. (14)-(16); model 1: the tri-linear distance of Eq. (12)-(13).
 void normal_equations(const OrcMap* M, const double* depth, const OrcCam& c, const double* T,
-                      double delta, double* out29) {
+                      double delta, double* out29, int model = 0) {
     double H[36] = {0}, b[6] = {0}, E = 0, n = 0;
     for (int v = 0; v < c.height; ++v)
         for (int u = 0; u < c.width; ++u) {
@@ -449,7 +492,7 @@ void normal_equations(const OrcMap* M, const double* depth, const OrcCam& c, con
             double x[3] = {D * ((double)u - c.cx) / c.fx, D * ((double)v - c.cy) / c.fy, D};
             double q[3], r, gh[3];
             transform(T, x, q);
-            if (!taylor(M, q, &r, gh, nullptr, nullptr)) continue;
+            if (model == 0 ? !taylor(M, q, &r, gh, nullptr, nullptr) : !trilinear(M, q, &r, gh)) continue;
             double J[6] = {gh[0], gh[1], gh[2],
                            q[1] * gh[2] - q[2] * gh[1],
                            q[2] * gh[0] - q[0] * gh[2],
@@ -779,12 +822,12 @@ void orc_normal_equations(const OrcMap* M, const double* depth, const OrcCam* ca
 // Fixed-iteration damped Gauss-Newton on one image (values in double).
 // stats (optional, iters x 2): energy and count at each linearisation.
 // Returns the number of failed (skipped) solves.
-int orc_gn_level(const OrcMap* M, const double* depth, const OrcCam* cam, int iters,
-                 double delta, double damping, double* T, double* stats) {
+int orc_gn_level_model(const OrcMap* M, const double* depth, const OrcCam* cam, int iters,
+                       double delta, double damping, double* T, double* stats, int model) {
     int failed = 0;
     for (int it = 0; it < iters; ++it) {
         double ne[29];
-        normal_equations(M, depth, *cam, T, delta, ne);
+        normal_equations(M, depth, *cam, T, delta, ne, model);
         if (stats) {
             stats[2 * it] = ne[27];
             stats[2 * it + 1] = ne[28];
@@ -794,10 +837,16 @@ int orc_gn_level(const OrcMap* M, const double* depth, const OrcCam* cam, int it
     return failed;
 }
 
+int orc_gn_level(const OrcMap* M, const double* depth, const OrcCam* cam, int iters,
+                 double delta, double damping, double* T, double* stats) {
+    return orc_gn_level_model(M, depth, cam, iters, delta, damping, T, stats, 0);
+}
+
 // Coarse-to-fine tracking: pyramid (binary32), then iters[l] GN steps per
-// level from the coarsest to the finest.
-int orc_track(const OrcMap* M, const float* depth, const OrcCam* cam, int levels,
-              const int32_t* iters, double delta, double damping, double* T, double* stats) {
+// level from the coarsest to the finest, with residual model `model`
+// (0 Taylor, 1 tri-linear).
+int orc_track_model(const OrcMap* M, const float* depth, const OrcCam* cam, int levels,
+                    const int32_t* iters, double delta, double damping, double* T, double* stats, int model) {
     std::vector<std::vector<float>> pyr(levels);
     std::vector<OrcCam> cams(levels);
     pyr[0].assign(depth, depth + (size_t)cam->width * cam->height);
@@ -818,11 +867,21 @@ int orc_track(const OrcMap* M, const float* depth, const OrcCam* cam, int levels
     int failed = 0, s = 0;
     for (int l = levels - 1; l >= 0; --l) {
         std::vector<double> dd(pyr[l].begin(), pyr[l].end());
-        failed += orc_gn_level(M, dd.data(), &cams[l], iters[l], delta, damping, T,
-                               stats ? stats + 2 * s : nullptr);
+        failed += orc_gn_level_model(M, dd.data(), &cams[l], iters[l], delta, damping, T,
+                                     stats ? stats + 2 * s : nullptr, model);
         s += iters[l];
     }
     return failed;
+}
+
+int orc_track(const OrcMap* M, const float* depth, const OrcCam* cam, int levels,
+              const int32_t* iters, double delta, double damping, double* T, double* stats) {
+    return orc_track_model(M, depth, cam, levels, iters, delta, damping, T, stats, 0);
+}
+
+// Tri-linear distance and gradient at world point q (0 if undefined).
+int orc_trilinear(const OrcMap* M, const double* q, double* r, double* grad) {
+    return trilinear(M, q, r, grad) ? 1 : 0;
 }
 
 // ---- small numerical kernels exposed for pin tests ----

@@ -257,3 +257,30 @@ def test_fuse_frame_equals_allocate_then_integrate(torch_mod, room_stream, stora
         np.testing.assert_array_equal(xa[oa], xb[ob])
     np.testing.assert_array_equal(A.counters(), B.counters())
     assert A.status_flags() == [] and B.status_flags() == []
+
+
+@pytest.mark.parametrize("levels,iters", [(3, (4, 0, 10)), (3, (0, 5, 10)), (3, (4, 5, 0)), (4, (2, 2, 3, 6))])
+def test_track_level_schedules(torch_mod, room_stream, levels, iters):
+    """Schedules with skipped or extra levels: work-groups join later levels
+    from the pose published at a level boundary (or skip them); the pose and
+    every iteration's energy must still match the oracle."""
+    torch = torch_mod
+    st = room_stream
+    O = _oracle_room_map(st, [0, 1, 2, 3])
+    G = _gpu_map(0.01, 0.05)
+    _import(O, G)
+    f = 5
+    log(f"case: track frame {f}, {levels} levels, iterations {iters}, separate initial pose buffer")
+    To, so, failed = O.track(st.depth[f], st.cam, st.poses[f - 1], levels, list(iters), 0.01)
+    init = dev(st.poses[f - 1].copy())
+    P = torch.zeros_like(init)
+    stats = torch.zeros(2 * sum(iters), dtype=torch.float32, device="cuda")
+    G.track(dev(st.depth[f]), st.cam, P, levels=levels, iters=iters, delta=0.01, stats=stats, init=init)
+    assert torch.equal(init, dev(st.poses[f - 1].copy()))
+    dr, dt = pose_diff(P.cpu().numpy(), To)
+    log(f"  GPU vs oracle: {dr:.2e} rad, {dt:.2e} m")
+    assert dr < 1e-5 and dt < 1e-5
+    sg = stats.cpu().numpy().reshape(-1, 2)
+    np.testing.assert_allclose(sg[:, 1], so[:, 1], rtol=1e-4)
+    np.testing.assert_allclose(sg[:, 0], so[:, 0], rtol=1e-3)
+    assert G.status_flags() == []
