@@ -15,7 +15,9 @@ Prints one JSON line.  Extra fields: "roofline" (dominant kernel),
 only the tracking kernel records events (two per frame; its duration feeds
 the roofline); "kernels" comes from a second pass over the same frames with
 every kernel timed, which is not part of "value" (events around every
-launch cost about 9 % of the frame rate).
+launch cost about 9 % of the frame rate).  "comparison" repeats the frames
+with the tri-linear eight-voxel distance of Eq. (12)-(13) in place of the
+Taylor distance (tracking time ratio, frame rate, ATE).
 """
 from __future__ import annotations
 
@@ -84,6 +86,8 @@ def _parse():
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--no-h2d", action="store_true", help="skip the PCIe-inclusive pass")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation measurement")
+    ap.add_argument("--no-comparison", action="store_true",
+                    help="skip the pass with the tri-linear comparison model")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times "
                          "(scale reference for hardware byte counters)")
@@ -118,9 +122,9 @@ def main():
     m = GsdfMap(cfg["voxel_size"], cfg["truncation"], max_blocks=1 << 16, storage=args.storage)
     s = torch.cuda.current_stream()
 
-    def step(f, src=None):
+    def step(f, src=None, model="taylor"):
         d = depth[f] if src is None else src
-        m.track(d, cam, est[f], levels=levels, iters=iters, delta=delta, init=est[f - 1])
+        m.track(d, cam, est[f], levels=levels, iters=iters, delta=delta, init=est[f - 1], model=model)
         m.fuse(d, cam, est[f])
 
     def start():
@@ -302,6 +306,33 @@ def main():
                          f"{n_cpu - 1} frames tracked + allocated + fused, single-threaded FP64, "
                          f"{el:.1f} s"}
 
+    # ---- the comparison model (Sec. 4.1 Eq. (12)-(13)): the same frames
+    # tracked with the tri-linear eight-voxel distance instead of the
+    # one-voxel Taylor distance (not part of "value")
+    comparison = None
+    if not args.no_comparison:
+        start()
+        lib.gsdf_timing_select(1 << _lib.K_TRACK)
+        torch.cuda.synchronize()
+        ev0.record(s)
+        for f in range(first, first + args.steps):
+            step(f, model="trilinear")
+        ev1.record(s)
+        torch.cuda.synchronize()
+        ms_tri = ev0.elapsed_time(ev1)
+        tr_tri = read_kernels().get("track")
+        lib.gsdf_timing_enable(0)
+        Et = est[: first + K].cpu().numpy()
+        comparison = {
+            "model": "tri-linear distance of the 8 voxels around each point (Eq. 12-13)",
+            "frames_per_s": args.steps / (ms_tri / 1e3),
+            "track_us": tr_tri["avg_us"] if tr_tri else None,
+            "taylor_track_us": track_live["avg_us"] if track_live else None,
+            "track_time_ratio": (tr_tri["avg_us"] / track_live["avg_us"]) if (tr_tri and track_live) else None,
+            "ate_rmse_m": float(np.sqrt(np.mean(np.sum((Et[:, :, 3] - G[:, :, 3]) ** 2, axis=1)))),
+            "status": m.status_flags(),
+        }
+
     report = {
         "metric": "tracked+fused frames/s at 640x480, 1 cm voxels; % of HBM peak GB/s",
         "value": fps,
@@ -325,6 +356,7 @@ def main():
         "fps_with_h2d": h2d,
         "accuracy": {"ate_rmse_m": ate, "status": status},
         "differentiation": diff,
+        "comparison": comparison,
         "work_per_frame": {"fusion_updates": work[0] / K, "fusion_pixel_visits": work[1] / K,
                            "fused_voxels": work[2] / K, "fused_blocks": work[3] / K,
                            "alloc_pairs": work[4] / K, "track_valid_px_iters": work[5] / K,

@@ -108,8 +108,17 @@ typedef struct gsdf_track_params {
     float huber_delta;       /* Huber threshold delta (metres)                    */
     double damping;          /* mu = damping * trace(H) / 6 added to H's diagonal */
     float min_inlier_frac;   /* GSDF_ELOST below this fraction at the finest level */
-    int32_t reserved;
+    int32_t model;           /* gsdf_residual_model                               */
 } gsdf_track_params;
+
+/* Residual model of tracking (Sec. 4.1). */
+typedef enum gsdf_residual_model {
+    GSDF_MODEL_TAYLOR = 0,     /* Eq. (14)-(16): one voxel, psi + g^ . (q - v)     */
+    GSDF_MODEL_TRILINEAR = 1   /* Eq. (12)-(13): tri-linear interpolant of the 8   */
+                               /* voxels around q and its derivative (the direct   */
+                               /* SDF tracking the paper compares against; needs   */
+                               /* all eight observed)                              */
+} gsdf_residual_model;
 
 /* ---------------------------------------------------------------------- */
 /* Map buffers                                                             */

@@ -41,7 +41,7 @@ class FuseParams(C.Structure):
 
 class TrackParams(C.Structure):
     _fields_ = [("levels", C.c_int32), ("iters", C.c_int32 * 4), ("huber_delta", C.c_float),
-                ("damping", C.c_double), ("min_inlier_frac", C.c_float), ("reserved", C.c_int32)]
+                ("damping", C.c_double), ("min_inlier_frac", C.c_float), ("model", C.c_int32)]
 
 
 _P = C.c_void_p

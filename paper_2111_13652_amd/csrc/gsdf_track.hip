@@ -298,6 +298,160 @@ __device__ inline void accumulate(const MapView& M, const TrackLevel& L, const T
     }
 }
 
+// Tri-linear residual model (Sec. 4.1 Eq. (12)-(13)): the direct SDF
+// tracking the paper compares its single-lookup Taylor model against.  Each
+// pixel reads the eight voxels around its point q (cell b = floor(q / v_s),
+// corners b + {0, 1}^3, through the hash table when a corner lies in a
+// neighbouring block); the distance is the tri-linear interpolant of their
+// values and the gradient its derivative (corner differences along each
+// axis, weighted bilinearly in the other two).  A pixel is used when all
+// eight voxels are observed.  Point and cell in float64, the rest as in the
+// Taylor model; the sums use the same layout.
+template <int STORAGE>
+__device__ inline void accumulate_trilinear(const MapView& M, const TrackLevel& L, const TrackArgs& a,
+                                            const double* pose, int first, int stride, const float* Dpre,
+                                            float acc[kNE], float cmp[kNE]) {
+    constexpr bool kPrecision = STORAGE != GSDF_FP32;
+    constexpr int B = kTrackBatch;
+    Kahan ks[kNE];
+#pragma unroll
+    for (int k = 0; k < kNE; ++k) acc[k] = 0.0f;
+    double R[9], t[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) R[3 * i + j] = pose[4 * i + j];
+        t[i] = pose[4 * i + 3];
+    }
+    const float ivsf = (float)a.inv_vs;
+    const int N = L.W * L.H;
+    for (int base = first; base < N; base += B * stride) {
+        float D[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const int i = base + j * stride;
+            D[j] = (Dpre && base == first) ? Dpre[j * kTrackBlock + threadIdx.x] : (i < N ? L.depth[i] : 0.0f);
+        }
+        // point, cell, the cell's block
+        int cb[B][3];
+        float f[B][3], qf[B][3];
+        bool live[B];
+        int32_t slot0[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const int i = base + j * stride;
+            live[j] = i < N && depth_ok(D[j], a.zmin, a.zmax);
+            if (!live[j]) continue;
+            if (kPrecision) ks[29].add(1.0f); else acc[29] += 1.0f;
+            const int v = i / L.W;
+            const int u = i - v * L.W;
+            const double Dd = (double)D[j];
+            const double x0 = Dd * (((double)u - L.cx) * L.ifx);
+            const double x1 = Dd * (((double)v - L.cy) * L.ify);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const double q = R[3 * r] * x0 + R[3 * r + 1] * x1 + R[3 * r + 2] * Dd + t[r];
+                const double sq = q * a.inv_vs;
+                cb[j][r] = (int)floor(sq);
+                f[j][r] = (float)(sq - (double)cb[j][r]);
+                qf[j][r] = (float)q;
+            }
+            slot0[j] = hash_find(M, block_of(cb[j][0]), block_of(cb[j][1]), block_of(cb[j][2]));
+            if (slot0[j] < 0) live[j] = false;
+        }
+        // the eight corners: weight and stored distance term
+        float cw[B][8];
+        uint32_t craw[B][8];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            if (!live[j]) continue;
+            const int b0x = block_of(cb[j][0]), b0y = block_of(cb[j][1]), b0z = block_of(cb[j][2]);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int mx = cb[j][0] + (c & 1), my = cb[j][1] + ((c >> 1) & 1), mz = cb[j][2] + (c >> 2);
+                const int bx = block_of(mx), by = block_of(my), bz = block_of(mz);
+                const int32_t slot =
+                    (bx == b0x && by == b0y && bz == b0z) ? slot0[j] : hash_find(M, bx, by, bz);
+                if (slot < 0) {
+                    cw[j][c] = 0.0f;
+                    craw[j][c] = 0u;
+                    continue;
+                }
+                const int64_t vi = (int64_t)slot * kBlockVoxels + morton9(mx & 7, my & 7, mz & 7);
+                cw[j][c] = M.weight[vi];
+                if (STORAGE == GSDF_FP32)
+                    craw[j][c] = __float_as_uint(reinterpret_cast<const float*>(M.vox)[4 * vi]);
+                else
+                    craw[j][c] = reinterpret_cast<const unsigned short*>(M.vox)[4 * vi];
+            }
+        }
+        // interpolant, residual, sums
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            if (!live[j]) continue;
+            bool all = true;
+            float c[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                all = all && cw[j][k] > 0.0f;
+                c[k] = STORAGE == GSDF_FP32 ? __uint_as_float(craw[j][k]) / cw[j][k]
+                                            : unpack16((unsigned short)craw[j][k], STORAGE) * M.truncation;
+            }
+            if (!all) continue;
+            const float wx[2] = {1.0f - f[j][0], f[j][0]};
+            const float wy[2] = {1.0f - f[j][1], f[j][1]};
+            const float wz[2] = {1.0f - f[j][2], f[j][2]};
+            float d = 0.0f, gx = 0.0f, gy = 0.0f, gz = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) d += c[k] * wx[k & 1] * wy[(k >> 1) & 1] * wz[k >> 2];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                // k enumerates the other two axes' corner bits
+                gx += (c[2 * k + 1] - c[2 * k]) * wy[k & 1] * wz[k >> 1];
+                gy += (c[(k & 1) + 4 * (k >> 1) + 2] - c[(k & 1) + 4 * (k >> 1)]) * wx[k & 1] * wz[k >> 1];
+                gz += (c[k + 4] - c[k]) * wx[k & 1] * wy[k >> 1];
+            }
+            const float g[3] = {gx * ivsf, gy * ivsf, gz * ivsf};
+            const float r = d;
+            const float J[6] = {g[0], g[1], g[2], qf[j][1] * g[2] - qf[j][2] * g[1],
+                                qf[j][2] * g[0] - qf[j][0] * g[2], qf[j][0] * g[1] - qf[j][1] * g[0]};
+            const float ar = fabsf(r);
+            const float w = ar <= a.delta ? 1.0f : a.delta / ar;
+            const float en = ar <= a.delta ? 0.5f * r * r : a.delta * (ar - 0.5f * a.delta);
+            int k = 0;
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                const float wj = w * J[p];
+#pragma unroll
+                for (int q2 = p; q2 < 6; ++q2) {
+                    if (kPrecision) ks[k].add(wj * J[q2]); else acc[k] += wj * J[q2];
+                    ++k;
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                if (kPrecision) ks[21 + p].add(w * J[p] * r); else acc[21 + p] += w * J[p] * r;
+            }
+            if (kPrecision) {
+                ks[27].add(en);
+                ks[28].add(1.0f);
+            } else {
+                acc[27] += en;
+                acc[28] += 1.0f;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kNE; ++k) {
+        if (kPrecision) {
+            acc[k] = ks[k].s;
+            cmp[k] = ks[k].c;
+        } else {
+            cmp[k] = 0.0f;
+        }
+    }
+}
+
 // Work-group sum: every thread writes its kNE sums to LDS (one transpose),
 // then 8 threads per entry add 32 values each with independent LDS reads,
 // and the first kNE threads combine the 8 parts and store the work-group
@@ -701,7 +855,7 @@ __device__ inline int level_groups(const TrackLevel& L, int G) {
 // reads a set while it is overwritten.  The published pose of a level
 // boundary is overwritten only at the next boundary, which needs the
 // contributions of the work-groups that joined and read it.
-template <int STORAGE>
+template <int STORAGE, int MODEL>
 __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArgs a, const double* pose_in,
                                                               double* pose_out, double* partials, unsigned* sync,
                                                               float* stats, int32_t* status) {
@@ -769,7 +923,10 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
 #pragma unroll
             for (int k = 0; k < 12; ++k) P[k] = s_pose[k];
             float acc[kNE], cmp[kNE];
-            accumulate<STORAGE>(M, L, a, P, first, Gl * kTrackBlock, s_depth, acc, cmp);
+            if constexpr (MODEL == GSDF_MODEL_TRILINEAR)
+                accumulate_trilinear<STORAGE>(M, L, a, P, first, Gl * kTrackBlock, s_depth, acc, cmp);
+            else
+                accumulate<STORAGE>(M, L, a, P, first, Gl * kTrackBlock, s_depth, acc, cmp);
             contribute<COMP>(acc, cmp, part, leafpart, sync, gi & 1, Gl, red, &s_flag);
             target += (unsigned)nleaf;
             if (threadIdx.x == 0) s_ok = wait_done(sync, kSyncDone, target) ? 1 : 0;
@@ -942,7 +1099,7 @@ inline int normal_eq_groups(int npx) {
 // per frame in dispatch, measured on MI355X): on a device that other work
 // keeps partly busy the last work-groups start late, and every wait is
 // bounded, so the worst case is a frame that fails with GSDF_EHIP.
-template <int STORAGE>
+template <int STORAGE, int MODEL>
 int track_groups() {
     static int cached[64] = {0};
     int dev = 0;
@@ -950,7 +1107,7 @@ int track_groups() {
     if (cached[dev] > 0) return cached[dev];
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_track_frame<STORAGE>, kTrackBlock, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_track_frame<STORAGE, MODEL>, kTrackBlock, 0) !=
         hipSuccess)
         return 0;
     // one work-group per CU: measured faster than two at 640x480 (the
@@ -961,14 +1118,25 @@ int track_groups() {
     return g;
 }
 
-template <int STORAGE>
+template <int STORAGE, int MODEL>
 int launch_track_frame(hipStream_t s, const MapView& M, const TrackArgs& a, const double* pose_in,
                        double* pose_out, double* partials, unsigned* sync, float* stats, int32_t* status) {
-    const int g = track_groups<STORAGE>();
+    const int g = track_groups<STORAGE, MODEL>();
     if (g <= 0) return GSDF_EHIP;
     TimedLaunch tl(GSDF_K_TRACK, s);
-    k_track_frame<STORAGE><<<g, kTrackBlock, 0, s>>>(M, a, pose_in, pose_out, partials, sync, stats, status);
+    k_track_frame<STORAGE, MODEL><<<g, kTrackBlock, 0, s>>>(M, a, pose_in, pose_out, partials, sync, stats,
+                                                            status);
     return GSDF_OK;
+}
+
+template <int STORAGE>
+int launch_track_model(int model, hipStream_t s, const MapView& M, const TrackArgs& a, const double* pose_in,
+                       double* pose_out, double* partials, unsigned* sync, float* stats, int32_t* status) {
+    if (model == GSDF_MODEL_TRILINEAR)
+        return launch_track_frame<STORAGE, GSDF_MODEL_TRILINEAR>(s, M, a, pose_in, pose_out, partials, sync,
+                                                                stats, status);
+    return launch_track_frame<STORAGE, GSDF_MODEL_TAYLOR>(s, M, a, pose_in, pose_out, partials, sync, stats,
+                                                         status);
 }
 
 inline void fill_levels(const gsdf_camera& cam, const float* depth, const ScratchLayout& sl, char* base,
@@ -1016,6 +1184,7 @@ extern "C" int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, con
     if (levels < 1 || levels > 4) return GSDF_EINVAL;
     for (int l = 0; l < levels; ++l)
         if (params->iters[l] < 0 || params->iters[l] > 1000) return GSDF_EINVAL;
+    if (params->model != GSDF_MODEL_TAYLOR && params->model != GSDF_MODEL_TRILINEAR) return GSDF_EINVAL;
     if ((cam->width >> (levels - 1)) < 1 || (cam->height >> (levels - 1)) < 1) return GSDF_EINVAL;
     const ScratchLayout sl = scratch_layout(*cam, levels);
     if (scratch_bytes < sl.total) return GSDF_EINVAL;
@@ -1056,9 +1225,9 @@ extern "C" int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, con
     const MapView M = make_view(*map);
     int rc;
     switch (map->desc.storage) {
-        case GSDF_FP32: rc = launch_track_frame<GSDF_FP32>(s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
-        case GSDF_BF16: rc = launch_track_frame<GSDF_BF16>(s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
-        default: rc = launch_track_frame<GSDF_FP16>(s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
+        case GSDF_FP32: rc = launch_track_model<GSDF_FP32>(params->model, s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
+        case GSDF_BF16: rc = launch_track_model<GSDF_BF16>(params->model, s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
+        default: rc = launch_track_model<GSDF_FP16>(params->model, s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
     }
     if (rc != GSDF_OK) return rc;
     return launch_status();

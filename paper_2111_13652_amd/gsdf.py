@@ -149,10 +149,12 @@ class GsdfMap:
     def track(self, depth: torch.Tensor, cam, pose: torch.Tensor, levels: int = 3,
               iters: Sequence[int] = (4, 5, 10), delta: float = 0.01, damping: float = 1e-6,
               min_inlier_frac: float = 0.1, stats: Optional[torch.Tensor] = None,
-              init: Optional[torch.Tensor] = None) -> None:
+              init: Optional[torch.Tensor] = None, model: str = "taylor") -> None:
         """Coarse-to-fine tracking; ``pose`` (3x4 float64, device) receives
         the estimate, starting from ``init`` (default: ``pose`` itself, updated
-        in place).  ``iters[l]`` iterations at level l (0 = finest)."""
+        in place).  ``iters[l]`` iterations at level l (0 = finest).  ``model``:
+        "taylor" (one voxel, Eq. (14)-(16)) or "trilinear" (eight voxels,
+        Eq. (12)-(13), the comparison model)."""
         c = camera(cam)
         _need(depth, torch.float32, (c.height, c.width), "depth")
         _need(pose, torch.float64, (3, 4), "pose")
@@ -165,7 +167,7 @@ class GsdfMap:
             if stats.numel() < 2 * sum(it[:levels]):
                 raise ValueError("stats too small")
         p = _lib.TrackParams(int(levels), (C.c_int32 * 4)(*it[:4]), float(delta), float(damping),
-                             float(min_inlier_frac), 0)
+                             float(min_inlier_frac), {"taylor": 0, "trilinear": 1}[model])
         scratch = self._scratch_for(c, levels)
         _lib.check(_lib.load().gsdf_track_frame(C.byref(self._map), _ptr(depth), C.byref(c),
                                                  C.byref(p), _ptr(init), _ptr(pose), _ptr(stats), _ptr(scratch),
