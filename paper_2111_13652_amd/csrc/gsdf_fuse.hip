@@ -50,6 +50,7 @@ struct FuseConsts {
     double fx_d, fy_d, ifx_d, ify_d, cx_d, cy_d;
     float zmin, zmax;
     float eps, cos_min;
+    float inv_span;   // 1 / (T - eps), the slope of the linear weight
     double inv_vs_d, vs_d;
     float vs_f, T_f;
     float inv_df;   // 1 / band sample spacing
@@ -58,10 +59,10 @@ struct FuseConsts {
     double fix_inv;      // 2^-f
 };
 
-__device__ inline float linear_weight(float d, float eps, float T) {
+__device__ inline float linear_weight(float d, float eps, float T, float inv_span) {
     if (d <= eps) return 1.0f;
     if (d >= T) return 0.0f;
-    return (T - d) / (T - eps);
+    return (T - d) * inv_span;
 }
 
 // ---------------------------------------------------------------------------
@@ -373,7 +374,7 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
                     base = __shfl(base, __ffsll((long long)ballot) - 1);
                     if (keep) {
                         const int slot_q = base + __popcll(ballot & ((1ull << lane) - 1ull));
-                        q_pix[slot_q] = (uint32_t)(v * fc.W + u);
+                        q_pix[slot_q] = ((uint32_t)v << 16) | (uint32_t)u;   // u, v < 2^16
                         q_k[slot_q] = (uint32_t)(k0 | (k1 << 16));
                     }
                 }
@@ -387,11 +388,11 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
             for (int p = threadIdx.x; p < lane_stride * 64; p += kFuseBlock) {
                 const int e = (p & 63) * lane_stride + (p >> 6);
                 if (e >= nq) continue;
-                const uint32_t pi = q_pix[e];
+                const uint32_t uv = q_pix[e];
                 const int k0 = (int)(q_k[e] & 0xffffu), k1 = (int)(q_k[e] >> 16);
-                const int v = (int)(pi / (uint32_t)fc.W);
-                const int u = (int)pi - v * fc.W;
-                const float4 px = pix[pi];
+                const int v = (int)(uv >> 16);
+                const int u = (int)(uv & 0xffffu);
+                const float4 px = pix[(size_t)v * fc.W + u];
                 const float D = px.w;
                 const float xr = pixel_xr(br, u);
                 const float yr = pixel_yr(br, v);
@@ -435,7 +436,7 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
                     for (int i = 0; i < 3; ++i) off[i] = fc.vs_f * (float)(m[i] - mref[i]) - prel[i];
                     float d = px.x * off[0] + px.y * off[1] + px.z * off[2];
                     d = fminf(fc.T_f, fmaxf(-fc.T_f, d));
-                    const float w = linear_weight(d, fc.eps, fc.T_f);
+                    const float w = linear_weight(d, fc.eps, fc.T_f, fc.inv_span);
                     if (!(w > 0.0f)) continue;
                     const int c = morton9(m[0] & 7, m[1] & 7, m[2] & 7);
                     atomicAdd(&aS[c], to_fixed(w * d, fc.fix_scale));
@@ -528,6 +529,7 @@ inline FuseConsts fuse_consts(const gsdf_map& map, const gsdf_camera& cam, const
     fc.zmin = cam.zmin;
     fc.zmax = cam.zmax;
     fc.eps = p.eps_weight;
+    fc.inv_span = (float)(1.0 / (map.desc.truncation - (double)p.eps_weight));
     fc.cos_min = p.cos_max_angle;
     fc.inv_vs_d = 1.0 / map.desc.voxel_size;
     fc.vs_d = map.desc.voxel_size;

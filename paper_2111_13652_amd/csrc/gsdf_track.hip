@@ -607,7 +607,7 @@ __device__ inline bool solve_update_wave(const double* ne, double damping, doubl
     double tr = 0.0;
 #pragma unroll
     for (int d = 0; d < 6; ++d) tr += ne[upper_index(d, d)];
-    const double mu = damping * tr / 6.0;
+    const double mu = damping * tr * (1.0 / 6.0);
     double row[7];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
@@ -639,14 +639,19 @@ __device__ inline bool solve_update_wave(const double* ne, double damping, doubl
     // exp of the twist (rho, phi) = (x[0..2], x[3..5]); coefficients as in se3_exp
     const double p0 = x[3], p1 = x[4], p2 = x[5];
     const double th2 = p0 * p0 + p1 * p1 + p2 * p2;
-    const double th = sqrt(th2);
     double A, B, C;
-    if (th < 0.02) {
-        const double t4 = th2 * th2, t6 = t4 * th2, t8 = t4 * t4;
-        A = 1.0 - th2 / 6.0 + t4 / 120.0 - t6 / 5040.0 + t8 / 362880.0;
-        B = 0.5 - th2 / 24.0 + t4 / 720.0 - t6 / 40320.0 + t8 / 3628800.0;
-        C = 1.0 / 6.0 - th2 / 120.0 + t4 / 5040.0 - t6 / 362880.0 + t8 / 39916800.0;
+    if (th2 < 0.02 * 0.02) {
+        // the series of se3_exp in Horner form with reciprocal constants
+        // (a division by a constant is a ten-instruction sequence in float64)
+        constexpr double a1 = -1.0 / 6.0, a2 = 1.0 / 120.0, a3 = -1.0 / 5040.0, a4 = 1.0 / 362880.0;
+        constexpr double b1 = -1.0 / 24.0, b2 = 1.0 / 720.0, b3 = -1.0 / 40320.0, b4 = 1.0 / 3628800.0;
+        constexpr double c0 = 1.0 / 6.0, c1 = -1.0 / 120.0, c2 = 1.0 / 5040.0, c3 = -1.0 / 362880.0,
+                         c4 = 1.0 / 39916800.0;
+        A = 1.0 + th2 * (a1 + th2 * (a2 + th2 * (a3 + th2 * a4)));
+        B = 0.5 + th2 * (b1 + th2 * (b2 + th2 * (b3 + th2 * b4)));
+        C = c0 + th2 * (c1 + th2 * (c2 + th2 * (c3 + th2 * c4)));
     } else {
+        const double th = sqrt(th2);
         const double sn = sin(th), cs = cos(th);
         A = sn / th;
         B = (1.0 - cs) / th2;
