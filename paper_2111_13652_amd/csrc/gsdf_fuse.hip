@@ -59,10 +59,10 @@ struct FuseConsts {
     double fix_inv;      // 2^-f
 };
 
-__device__ inline float linear_weight(float d, float eps, float T, float inv_span) {
-    if (d <= eps) return 1.0f;
-    if (d >= T) return 0.0f;
-    return (T - d) * inv_span;
+// w(d) = 1 for d <= eps, (T - d) / (T - eps) for eps < d < T, 0 for d >= T,
+// written as the clamp of the middle piece (the same function, no branches)
+__device__ inline float linear_weight(float d, float T, float inv_span) {
+    return fminf(1.0f, fmaxf(0.0f, (T - d) * inv_span));
 }
 
 // ---------------------------------------------------------------------------
@@ -200,8 +200,12 @@ __device__ inline void block_box(const FuseConsts& fc, const double* R, const do
         zhi = fmax(zhi, pc[2]);
         if (pc[2] <= 1e-6) behind = true;
         if (behind) continue;
-        const double u = fc.fx_d * pc[0] / pc[2] + fc.cx_d;
-        const double v = fc.fy_d * pc[1] / pc[2] + fc.cy_d;
+        // reciprocal (hardware estimate and one Newton step) instead of two
+        // divisions: the rectangle is widened by a pixel on each side anyway
+        double iz = __builtin_amdgcn_rcp(pc[2]);
+        iz = fma(iz, fma(-pc[2], iz, 1.0), iz);
+        const double u = fc.fx_d * pc[0] * iz + fc.cx_d;
+        const double v = fc.fy_d * pc[1] * iz + fc.cy_d;
         umin = fmin(umin, u);
         umax = fmax(umax, u);
         vmin = fmin(vmin, v);
@@ -225,13 +229,21 @@ __device__ inline void block_box(const FuseConsts& fc, const double* R, const do
     B->inv_bw = B->u1 >= B->u0 ? 1.0f / (float)(B->u1 - B->u0 + 1) : 0.0f;
 }
 
-// Fixed point with f fraction bits for the per-frame voxel sums.  Scaling a
-// float by 2^f is exact, so a term converts exactly unless it is below
-// 2^(23-f) (then it is rounded to 2^-f); integer sums are exact, and the
-// total is rounded once, to float.  f is chosen on the host so that the
-// largest possible sum fits (see fix_bits).
-__device__ inline unsigned long long to_fixed(float x, float scale) {
-    return (unsigned long long)__float2ll_rn(x * scale);
+// Fixed point with f fraction bits for the per-frame voxel sums.  A term
+// w x enters as (w 2^f) x: scaling by a power of two is exact, so this is
+// (w x) 2^f rounded once.  The 64-bit integer is formed from two 32-bit
+// conversions, hi = floor(w x 2^(f-32)) and lo = w x 2^f - hi 2^32 in
+// [0, 2^32) (one instruction each, where a direct 64-bit conversion is a
+// long sequence).  A term converts exactly unless it is below 2^(23-f) or a
+// small negative one (then it is rounded, deterministically, within
+// 2^(8-f)); integer sums are exact, and the total is rounded once, to float.
+// f is chosen on the host so that the largest possible sum fits (see
+// fix_bits).  ws = w 2^f, wh = w 2^(f-32).
+__device__ inline unsigned long long fixed_term(float ws, float wh, float x) {
+    const float s = ws * x;
+    const float hs = floorf(wh * x);
+    const float lo = fmaf(-hs, 4294967296.0f, s);
+    return ((unsigned long long)(unsigned)(int)hs << 32) | (unsigned long long)(unsigned)lo;
 }
 __device__ inline float from_fixed(unsigned long long a, double inv) {
     return (float)((double)(long long)a * inv);
@@ -240,9 +252,10 @@ __device__ inline float from_fixed(unsigned long long a, double inv) {
 template <int STORAGE>
 __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const float4* __restrict__ pix,
                                                            FuseConsts fc, const double* __restrict__ Twc) {
-    // per-voxel sums of the frame in 32.32 fixed point: integer additions
-    // are associative, so the sums (and the map) do not depend on the order
-    // in which the work-group's threads add their updates
+    // per-voxel sums of the frame in fixed point (see fixed_term), indexed
+    // lx + 8 ly + 64 lz (the pool's Morton order is applied at the write):
+    // integer additions are associative, so the sums (and the map) do not
+    // depend on the order in which the work-group's threads add their updates
     __shared__ unsigned long long aS[kBlockVoxels];
     __shared__ unsigned long long aG[3][kBlockVoxels];
     __shared__ unsigned long long aW[kBlockVoxels];
@@ -436,14 +449,15 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
                     for (int i = 0; i < 3; ++i) off[i] = fc.vs_f * (float)(m[i] - mref[i]) - prel[i];
                     float d = px.x * off[0] + px.y * off[1] + px.z * off[2];
                     d = fminf(fc.T_f, fmaxf(-fc.T_f, d));
-                    const float w = linear_weight(d, fc.eps, fc.T_f, fc.inv_span);
+                    const float w = linear_weight(d, fc.T_f, fc.inv_span);
                     if (!(w > 0.0f)) continue;
-                    const int c = morton9(m[0] & 7, m[1] & 7, m[2] & 7);
-                    atomicAdd(&aS[c], to_fixed(w * d, fc.fix_scale));
-                    atomicAdd(&aG[0][c], to_fixed(w * px.x, fc.fix_scale));
-                    atomicAdd(&aG[1][c], to_fixed(w * px.y, fc.fix_scale));
-                    atomicAdd(&aG[2][c], to_fixed(w * px.z, fc.fix_scale));
-                    atomicAdd(&aW[c], to_fixed(w, fc.fix_scale));
+                    const int c = (m[0] & 7) | ((m[1] & 7) << 3) | ((m[2] & 7) << 6);  // lx + 8 ly + 64 lz
+                    const float ws = w * fc.fix_scale, wh = ws * 2.3283064365386963e-10f;
+                    atomicAdd(&aS[c], fixed_term(ws, wh, d));
+                    atomicAdd(&aG[0][c], fixed_term(ws, wh, px.x));
+                    atomicAdd(&aG[1][c], fixed_term(ws, wh, px.y));
+                    atomicAdd(&aG[2][c], fixed_term(ws, wh, px.z));
+                    atomicAdd(&aW[c], fixed_term(ws, wh, 1.0f));
                     ++my_updates;
                 }
             }
@@ -458,7 +472,7 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
             const float sG[3] = {from_fixed(aG[0][c], fc.fix_inv), from_fixed(aG[1][c], fc.fix_inv),
                                  from_fixed(aG[2][c], fc.fix_inv)};
             ++my_voxels;
-            const int64_t vi = (int64_t)slot * kBlockVoxels + c;
+            const int64_t vi = (int64_t)slot * kBlockVoxels + morton9(c & 7, (c >> 3) & 7, c >> 6);
             if (STORAGE == GSDF_FP32) {
                 float4* rec = reinterpret_cast<float4*>(M.vox) + vi;
                 float4 r = *rec;
