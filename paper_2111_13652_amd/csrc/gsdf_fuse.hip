@@ -69,10 +69,11 @@ __device__ inline float linear_weight(float d, float T, float inv_span) {
 // 1. Normals
 // ---------------------------------------------------------------------------
 // Tile (tu, tv) of 16x16 pixels; every thread of the 256-thread work-group
-// must call it (it synchronises); tile is kTileH x (kTileH + 1) floats of LDS.
+// must call it (it synchronises); tile and itile are kTileH x (kTileH + 1)
+// floats of LDS (depths and their reciprocals, each computed once per tile).
 __device__ inline void normals_tile(const float* __restrict__ depth, const FuseConsts& fc,
                                     const double* __restrict__ Twc, float4* __restrict__ pix, int tu, int tv,
-                                    float (*tile)[kTileH + 1]) {
+                                    float (*tile)[kTileH + 1], float (*itile)[kTileH + 1]) {
     const int tx = threadIdx.x & (kTile - 1);
     const int ty = threadIdx.x / kTile;
     const int u0 = tu * kTile - kHalo;
@@ -83,6 +84,7 @@ __device__ inline void normals_tile(const float* __restrict__ depth, const FuseC
         float d = 0.0f;
         if (uu >= 0 && uu < fc.W && vv >= 0 && vv < fc.H) d = depth[(size_t)vv * fc.W + uu];
         tile[ly][lx] = d;
+        itile[ly][lx] = d > 0.0f ? 1.0f / d : 0.0f;
     }
     __syncthreads();
 
@@ -96,7 +98,9 @@ __device__ inline void normals_tile(const float* __restrict__ depth, const FuseC
         // least-squares plane 1/z = a . [x/z, y/z, 1] on the 5x5 window.
         // Over the symmetric window the design (1, du, dv) is orthogonal, so
         // the fit has a closed form in the centred inverse depths
-        // 1/D_i - 1/D_c = (D_c - D_i) / (D_i D_c), whose numerators are exact.
+        // 1/D_i - 1/D_c = (D_c - D_i) (1/D_c) (1/D_i), whose numerators are
+        // exact (no cancellation; the reciprocals come from the tile).
+        const float iDc = itile[ty + kHalo][tx + kHalo];
         float s0 = 0.0f, sa = 0.0f, sb = 0.0f;
         bool ok = true;
 #pragma unroll
@@ -105,26 +109,27 @@ __device__ inline void normals_tile(const float* __restrict__ depth, const FuseC
             for (int du = -kHalo; du <= kHalo; ++du) {
                 const float Di = tile[ty + kHalo + dv][tx + kHalo + du];
                 ok = ok && depth_ok(Di, fc.zmin, fc.zmax) && (fabsf(Di - Dc) <= fc.band.Tf);
-                const float dy = (Dc - Di) / (Di * Dc);
+                const float dy = (Dc - Di) * iDc * itile[ty + kHalo + dv][tx + kHalo + du];
                 s0 += dy;
                 sa += (float)du * dy;
                 sb += (float)dv * dy;
             }
         }
         if (ok) {
-            const float h = 1.0f / Dc + s0 * (1.0f / 25.0f);
+            const float h = iDc + s0 * (1.0f / 25.0f);
             const float alpha = sa * (1.0f / 50.0f);   // sum du^2 = 50 over the window
             const float beta = sb * (1.0f / 50.0f);
             const float ax = alpha * fc.fxf;
             const float ay = beta * fc.fyf;
             const float az = h - alpha * ((float)u - fc.rcx) - beta * ((float)v - fc.rcy);
             const float na = sqrtf(ax * ax + ay * ay + az * az);
-            const float rx = ((float)u - fc.rcx) / fc.fxf;
-            const float ry = ((float)v - fc.rcy) / fc.fyf;
-            const float cosang = h / (na * sqrtf(rx * rx + ry * ry + 1.0f));
+            const float rx = ((float)u - fc.rcx) * fc.band.ifx;
+            const float ry = ((float)v - fc.rcy) * fc.band.ify;
+            const float ina = 1.0f / na;
+            const float cosang = h * ina * __frsqrt_rn(rx * rx + ry * ry + 1.0f);
             if (cosang >= fc.cos_min) {
                 // a . ray = h > 0: the normal faces away from the camera
-                const float n0 = ax / na, n1 = ay / na, n2 = az / na;
+                const float n0 = ax * ina, n1 = ay * ina, n2 = az * ina;
                 float nw[3];
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
@@ -140,7 +145,8 @@ __global__ __launch_bounds__(256) void k_pixel_normals(const float* __restrict__
                                                        const double* __restrict__ Twc,
                                                        float4* __restrict__ pix) {
     __shared__ float tile[kTileH][kTileH + 1];
-    normals_tile(depth, fc, Twc, pix, blockIdx.x, blockIdx.y, tile);
+    __shared__ float itile[kTileH][kTileH + 1];
+    normals_tile(depth, fc, Twc, pix, blockIdx.x, blockIdx.y, tile, itile);
 }
 
 // The frame path's allocation and normals in one launch: both work on the
@@ -153,9 +159,10 @@ __global__ __launch_bounds__(256) void k_alloc_normals(MapView M, const float* _
     __shared__ unsigned long long s_keys[kAllocSet];
     __shared__ unsigned long long red[4];
     __shared__ float tile[kTileH][kTileH + 1];
+    __shared__ float itile[kTileH][kTileH + 1];
     allocate_tile(M, depth, fc.W, fc.H, fc.zmin, fc.zmax, fc.band, Twc, status, blockIdx.x, blockIdx.y, s_keys,
                   red);
-    normals_tile(depth, fc, Twc, pix, blockIdx.x, blockIdx.y, tile);
+    normals_tile(depth, fc, Twc, pix, blockIdx.x, blockIdx.y, tile, itile);
 }
 
 // ---------------------------------------------------------------------------
