@@ -710,9 +710,14 @@ constexpr int kLeaf = 16;
 constexpr int kMaxLeaves = kMaxGroups / kLeaf;
 // one set of partials: a partial per work-group, then one per leaf
 constexpr size_t kPartsPerSet = (size_t)(kMaxGroups + kMaxLeaves) * kPartStride;
+// Leaf tickets are kTicketStride words (256 B) apart: device-scope atomics
+// on one cache line share the memory-side atomic unit, and with all leaf
+// tickets on one line a full-resolution iteration spent 2.3 us in them
+// (measured; 176 against 186 us per frame at 640x480).
+constexpr int kTicketStride = 64;
 enum {
-    kSyncLeaf = 0,                          // [2][kMaxLeaves]
-    kSyncRoot = kSyncLeaf + 2 * kMaxLeaves,  // [2]
+    kSyncLeaf = 0,                                          // [2][kMaxLeaves] x kTicketStride
+    kSyncRoot = kSyncLeaf + 2 * kMaxLeaves * kTicketStride,  // [2]
     kSyncDone = kSyncRoot + 2,
     kSyncPub = kSyncDone + 1,               // iterations reflected by the published pose
     kSyncAbort = kSyncPub + 1,
@@ -727,7 +732,7 @@ __device__ inline bool leaf_arrive(unsigned* sync, int par, int groups) {
     const int leaf = blockIdx.x / kLeaf;
     const int leaf_size = min(kLeaf, groups - leaf * kLeaf);
     complete_device_stores();
-    unsigned* lc = &sync[kSyncLeaf + par * kMaxLeaves + leaf];
+    unsigned* lc = &sync[kSyncLeaf + (par * kMaxLeaves + leaf) * kTicketStride];
     if (__hip_atomic_fetch_add(lc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != (unsigned)leaf_size - 1)
         return false;
     __hip_atomic_store(lc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1010,8 +1015,8 @@ __global__ __launch_bounds__(kTrackBlock) void k_normal_equations(MapView M, Tra
 // All pyramid levels in one launch, each by the 2x2 rule in binary32: the
 // mean of four valid depths whose spread is within the truncation, else 0.
 // A work-group covers a 16x16 tile of level 1 (from level 0 in global
-// memory); its 8x8 level-2 and 4x4 level-3 pixels come from LDS.  Work-item
-// (0,0) of the grid also clears the sync words of the tracking kernel.
+// memory); its 8x8 level-2 and 4x4 level-3 pixels come from LDS.  The
+// work-groups also clear the sync words of the tracking kernel between them.
 struct PyramidArgs {
     const float* src;
     float* dst[4];
@@ -1034,8 +1039,12 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs p) {
     __shared__ float t1[16][17];
     __shared__ float t2[8][9];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    if (blockIdx.x == 0 && blockIdx.y == 0)
-        for (int k = threadIdx.x; k < kSyncWords; k += blockDim.x) p.sync[k] = 0u;
+    {
+        // every work-group clears its share of the tracking kernel's sync words
+        const int nthreads = gridDim.x * gridDim.y * blockDim.x;
+        const int tid = (blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
+        for (int k = tid; k < kSyncWords; k += nthreads) p.sync[k] = 0u;
+    }
     if (p.levels < 2) return;
     const int u = blockIdx.x * 16 + tx, v = blockIdx.y * 16 + ty;
     float d1 = 0.0f;
