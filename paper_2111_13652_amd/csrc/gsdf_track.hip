@@ -715,11 +715,17 @@ constexpr size_t kPartsPerSet = (size_t)(kMaxGroups + kMaxLeaves) * kPartStride;
 // tickets on one line a full-resolution iteration spent 2.3 us in them
 // (measured; 176 against 186 us per frame at 640x480).
 constexpr int kTicketStride = 64;
+// The done count is kept in kDoneCopies copies (one per XCD under the
+// round-robin placement of work-groups), each on its own line: a leaf
+// winner adds to every copy and a member polls copy blockIdx % kDoneCopies,
+// so 256 pollers do not share one line with the adds they wait for
+// (measured 168 against 176 us per frame).
+constexpr int kDoneCopies = 8;
 enum {
     kSyncLeaf = 0,                                          // [2][kMaxLeaves] x kTicketStride
     kSyncRoot = kSyncLeaf + 2 * kMaxLeaves * kTicketStride,  // [2]
-    kSyncDone = kSyncRoot + 2,
-    kSyncPub = kSyncDone + 1,               // iterations reflected by the published pose
+    kSyncDone = kSyncRoot + 2,              // [kDoneCopies] x kTicketStride
+    kSyncPub = kSyncDone + kDoneCopies * kTicketStride,  // iterations reflected by the published pose
     kSyncAbort = kSyncPub + 1,
     kSyncWords = kSyncAbort + 1
 };
@@ -820,7 +826,9 @@ __device__ inline void contribute(const float acc[kNE], const float cmp[kNE], do
     __syncthreads();
     if (threadIdx.x == 0) {
         complete_device_stores();
-        __hip_atomic_fetch_add(&sync[kSyncDone], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int r = 0; r < kDoneCopies; ++r)
+            __hip_atomic_fetch_add(&sync[kSyncDone + r * kTicketStride], 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -939,7 +947,8 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
                 accumulate<STORAGE>(M, L, a, P, first, Gl * kTrackBlock, s_depth, acc, cmp);
             contribute<COMP>(acc, cmp, part, leafpart, sync, gi & 1, Gl, red, &s_flag);
             target += (unsigned)nleaf;
-            if (threadIdx.x == 0) s_ok = wait_done(sync, kSyncDone, target) ? 1 : 0;
+            if (threadIdx.x == 0)
+                s_ok = wait_done(sync, kSyncDone + (blockIdx.x % kDoneCopies) * kTicketStride, target) ? 1 : 0;
             __syncthreads();
             if (!s_ok) {
                 if (threadIdx.x == 0) {
