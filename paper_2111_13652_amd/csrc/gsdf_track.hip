@@ -685,7 +685,7 @@ __device__ inline bool solve_update_wave(const double* ne, double damping, doubl
 }
 
 // Memory ordering between work-groups.  Everything one work-group hands to
-// another (partial sums, leaf sums, the pose, counters, the generation) is
+// another (partial sums, leaf sums, the published pose, tickets and counts) is
 // written and read only with device-scope atomic operations, which the
 // hardware keeps coherent per location across the XCDs without cache
 // maintenance.  Ordering is then all that is needed: a producer waits until
