@@ -134,3 +134,22 @@ def test_stored_gradients_beat_central_differences_in_kind():
     assert stored < 0.7 * central
     assert np.median(q[1][sel]) < np.median(q[4][sel])
     assert np.percentile(q[1][sel], 95) < np.percentile(q[4][sel], 95)
+
+
+def test_block_interior_fraction():
+    """Sec. 3.1: of the 8^3 voxels of a block only the 6^3 interior ones have
+    all six face neighbours inside it, so 57.8125 % reach into other blocks.
+    A lone, fully observed block gives exactly that through the oracle's
+    neighbour lookup; with its 26 neighbour blocks present every voxel has
+    its neighbours."""
+    g = lambda v: np.broadcast_to(np.array([0.0, 0.0, 1.0]), v.shape)
+    O = oracle.OracleMap(VS, 0.1)
+    one = np.array([[2, -1, 3]], np.int32)
+    O.set_voxels(one, np.zeros((1, 512)), g(np.zeros((1, 512, 3))), np.ones((1, 512)))
+    _, _, _, ok = O.fd_gradients(one)
+    assert (~ok).sum() / 512 == 0.578125
+    around = np.array([[2 + i, -1 + j, 3 + k] for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)], np.int32)
+    O2 = oracle.OracleMap(VS, 0.1)
+    O2.set_voxels(around, np.zeros((27, 512)), g(np.zeros((27, 512, 3))), np.ones((27, 512)))
+    _, _, _, ok2 = O2.fd_gradients(one)
+    assert ok2.all()
