@@ -75,6 +75,17 @@ def _traffic(kernel: str, storage: str):
     return m["bytes"]
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +102,8 @@ def _parse():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times "
                          "(scale reference for hardware byte counters)")
+    ap.add_argument("--workload", choices=("room640", "room1280"), default="room640",
+                    help="room640: the headline workload; room1280: 1280x720, 5 mm voxels, T 2.5 cm")
     ap.add_argument("--storage", choices=("fp32", "bf16", "fp16"), default="fp32",
                     help="voxel storage: fp32 (plain path) or the 16-bit precision form")
     return ap.parse_args()
@@ -107,11 +120,13 @@ def main():
     from paper_2111_13652_amd import _lib, synth
     from paper_2111_13652_amd.gsdf import GsdfMap
 
-    cfg = synth.CONFIG_ROOM
+    hd = args.workload == "room1280"
+    cfg = synth.CONFIG_ROOM_HD if hd else synth.CONFIG_ROOM
     cam = cfg["cam"]
     n_frames = max(100, 1 + args.warmup + args.steps)
     t0 = time.time()
-    stream = synth.make_stream(cam, n_frames, scene_seed=1, traj_seed=2, noise_seed=3)
+    # the 1280x720 stream uses trajectory 5 and noise 6 (its own seeds)
+    stream = synth.make_stream(cam, n_frames, scene_seed=1, traj_seed=5 if hd else 2, noise_seed=6 if hd else 3)
     print(f"# generated {n_frames} frames in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
 
     dev = torch.device("cuda:0")
@@ -119,7 +134,7 @@ def main():
     gt = torch.as_tensor(stream.poses).to(dev)                          # (F, 3, 4) float64
     est = torch.zeros_like(gt)
     levels, iters, delta = 3, (4, 5, 10), 0.01
-    m = GsdfMap(cfg["voxel_size"], cfg["truncation"], max_blocks=1 << 16, storage=args.storage)
+    m = GsdfMap(cfg["voxel_size"], cfg["truncation"], max_blocks=1 << (18 if hd else 16), storage=args.storage)
     s = torch.cuda.current_stream()
 
     def step(f, src=None, model="taylor"):
@@ -304,7 +319,7 @@ def main():
         cpu = {"value": (n_cpu - 1) / el, "unit": "frames/s", "cores": 1, "kind": "oracle",
                "sample": f"frames 0-{n_cpu - 1} of the same stream: frame 0 fused at ground truth, "
                          f"{n_cpu - 1} frames tracked + allocated + fused, single-threaded FP64, "
-                         f"{el:.1f} s"}
+                         f"{el:.1f} s on one core of {_cpu_model()} ({os.cpu_count()} visible)"}
 
     # ---- the comparison model (Sec. 4.1 Eq. (12)-(13)): the same frames
     # tracked with the tri-linear eight-voxel distance instead of the
@@ -334,7 +349,8 @@ def main():
         }
 
     report = {
-        "metric": "tracked+fused frames/s at 640x480, 1 cm voxels; % of HBM peak GB/s",
+        "metric": ("tracked+fused frames/s at 1280x720, 5 mm voxels; % of HBM peak GB/s" if hd else
+                   "tracked+fused frames/s at 640x480, 1 cm voxels; % of HBM peak GB/s"),
         "value": fps,
         "unit": "frames/s",
         "n_gpus": 1,
@@ -345,8 +361,10 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if args.storage == "fp32" else f"{args.storage} storage, f32 compute",
-        "data": "synthetic (seeded room stream standing in for TUM RGB-D 640x480 depth)",
-        "config": {"workload": "room stream 640x480, 1 cm voxels, T 5 cm, 8^3 blocks, 3-level "
+        "data": ("synthetic (seeded room stream at 1280x720)" if hd else
+                 "synthetic (seeded room stream standing in for TUM RGB-D 640x480 depth)"),
+        "config": {"workload": ("room stream 1280x720, 5 mm voxels, T 2.5 cm" if hd else
+                                "room stream 640x480, 1 cm voxels, T 5 cm") + ", 8^3 blocks, 3-level "
                                f"pyramid (4/5/10 GN iterations), {args.storage} voxels",
                    "frames": n_frames},
         "hbm_frac": eff_gbs / HBM_PEAK_GBS,
