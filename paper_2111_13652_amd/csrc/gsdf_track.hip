@@ -111,13 +111,14 @@ struct Kahan {
 // loads for the whole batch before using any of them (depths, then the
 // first hash probe of each, then weight and voxel record together), so a
 // batch costs three dependent memory round trips instead of four per
-// pixel.  Hash collisions fall back to the probing loop.
+// pixel.  Hash collisions fall back to the probing loop.  The pixels are
+// first, first + stride, ... below end.
 constexpr int kTrackBatch = 3;
 
 template <int STORAGE>
 __device__ inline void accumulate(const MapView& M, const TrackLevel& L, const TrackArgs& a,
-                                  const double* pose, int first, int stride, const float* Dpre, float acc[kNE],
-                                  float cmp[kNE]) {
+                                  const double* pose, int first, int stride, int end, const float* Dpre,
+                                  float acc[kNE], float cmp[kNE]) {
     constexpr bool kPrecision = STORAGE != GSDF_FP32;
     constexpr int B = kTrackBatch;
     Kahan ks[kNE];
@@ -144,7 +145,7 @@ __device__ inline void accumulate(const MapView& M, const TrackLevel& L, const T
     const float vsf = (float)a.vs, ivsf = (float)a.inv_vs;
     const float ifxf = (float)L.ifx, ifyf = (float)L.ify, cxf = (float)L.cx, cyf = (float)L.cy;
 
-    const int N = L.W * L.H;
+    const int N = end;
     for (int base = first; base < N; base += B * stride) {
         // ---- stage 1: depths (preloaded for the first batch when given)
         float D[B];
@@ -309,8 +310,8 @@ __device__ inline void accumulate(const MapView& M, const TrackLevel& L, const T
 // Taylor model; the sums use the same layout.
 template <int STORAGE>
 __device__ inline void accumulate_trilinear(const MapView& M, const TrackLevel& L, const TrackArgs& a,
-                                            const double* pose, int first, int stride, const float* Dpre,
-                                            float acc[kNE], float cmp[kNE]) {
+                                            const double* pose, int first, int stride, int end,
+                                            const float* Dpre, float acc[kNE], float cmp[kNE]) {
     constexpr bool kPrecision = STORAGE != GSDF_FP32;
     constexpr int B = kTrackBatch;
     Kahan ks[kNE];
@@ -324,7 +325,7 @@ __device__ inline void accumulate_trilinear(const MapView& M, const TrackLevel& 
         t[i] = pose[4 * i + 3];
     }
     const float ivsf = (float)a.inv_vs;
-    const int N = L.W * L.H;
+    const int N = end;
     for (int base = first; base < N; base += B * stride) {
         float D[B];
 #pragma unroll
@@ -860,6 +861,20 @@ __device__ inline int level_groups(const TrackLevel& L, int G) {
     return g > G ? G : g;
 }
 
+// Rank in the image of member b of n: the members split the level's pixels
+// into n contiguous chunks, and rank orders them so that the members on one
+// XCD take neighbouring chunks.  MI355X dispatches work-groups to its 8 XCDs
+// in turn (b on XCD b mod 8), each XCD with its own L2, so each L2 then
+// holds the voxels seen by one band of the image instead of the whole
+// visible map.  Any n gives a permutation of 0 .. n-1.
+constexpr int kXcds = 8;
+__device__ inline int band_rank(int b, int n) {
+    const int x = b % kXcds;
+    int start = 0;
+    for (int y = 0; y < x; ++y) start += (n - y + kXcds - 1) / kXcds;   // members on XCD y
+    return start + b / kXcds;
+}
+
 // The whole coarse-to-fine Gauss-Newton of one frame (one launch, one work-group per CU).
 //
 // Only the members of a level (the first Gl work-groups) run its
@@ -925,14 +940,19 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
             __syncthreads();
             have = gi;
         }
-        // a member's pixels are the same in every iteration of the level:
-        // the depths of each thread's first batch are loaded once and kept
-        // in LDS (each thread reads back only what it wrote)
-        const int first = blockIdx.x * kTrackBlock + threadIdx.x;
+        // a member's pixels are one contiguous chunk of the level, the same
+        // in every iteration: the depths of each thread's first batch are
+        // loaded once and kept in LDS (each thread reads back only what it
+        // wrote)
+        const int npx = L.W * L.H;
+        const int chunk = (npx + Gl - 1) / Gl;
+        const int c0 = min(band_rank(blockIdx.x, Gl) * chunk, npx);
+        const int c1 = min(c0 + chunk, npx);
+        const int first = c0 + threadIdx.x;
 #pragma unroll
         for (int j = 0; j < kTrackBatch; ++j) {
-            const int i = first + j * Gl * kTrackBlock;
-            s_depth[j * kTrackBlock + threadIdx.x] = i < L.W * L.H ? L.depth[i] : 0.0f;
+            const int i = first + j * kTrackBlock;
+            s_depth[j * kTrackBlock + threadIdx.x] = i < c1 ? L.depth[i] : 0.0f;
         }
         for (int it = 0; it < a.iters[l]; ++it, ++gi) {
             double* part = partials + (size_t)(gi & 1) * kPartsPerSet;
@@ -942,9 +962,9 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
             for (int k = 0; k < 12; ++k) P[k] = s_pose[k];
             float acc[kNE], cmp[kNE];
             if constexpr (MODEL == GSDF_MODEL_TRILINEAR)
-                accumulate_trilinear<STORAGE>(M, L, a, P, first, Gl * kTrackBlock, s_depth, acc, cmp);
+                accumulate_trilinear<STORAGE>(M, L, a, P, first, kTrackBlock, c1, s_depth, acc, cmp);
             else
-                accumulate<STORAGE>(M, L, a, P, first, Gl * kTrackBlock, s_depth, acc, cmp);
+                accumulate<STORAGE>(M, L, a, P, first, kTrackBlock, c1, s_depth, acc, cmp);
             contribute<COMP>(acc, cmp, part, leafpart, sync, gi & 1, Gl, red, &s_flag);
             target += (unsigned)nleaf;
             if (threadIdx.x == 0)
@@ -1011,8 +1031,8 @@ __global__ __launch_bounds__(kTrackBlock) void k_normal_equations(MapView M, Tra
 #pragma unroll
     for (int k = 0; k < 12; ++k) P[k] = pose[k];
     float acc[kNE], cmp[kNE];
-    accumulate<STORAGE>(M, a.lv[0], a, P, blockIdx.x * kTrackBlock + threadIdx.x,
-                        gridDim.x * kTrackBlock, nullptr, acc, cmp);
+    accumulate<STORAGE>(M, a.lv[0], a, P, blockIdx.x * kTrackBlock + threadIdx.x, gridDim.x * kTrackBlock,
+                        a.lv[0].W * a.lv[0].H, nullptr, acc, cmp);
     double ne[kNE];
     if (!reduce_tree<STORAGE != GSDF_FP32>(acc, cmp, partials, partials + (size_t)kMaxGroups * kPartStride, sync,
                                            0, gridDim.x, ne, red, &s_last))
