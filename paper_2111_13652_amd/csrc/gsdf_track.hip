@@ -467,9 +467,22 @@ struct ReduceLds {
     double tot[kNE];
 };
 
+// Partials and leaf sums of the tracking kernel carry the iteration they
+// belong to: the low 16 bits of each float64 word (a relative change below
+// 2^-36, the same for every reader) hold the tag, so a reader that sees the
+// tag has the value, with no separate signal to wait for first.  Tags are
+// 1 + the iteration index (at most 4000 iterations a frame), and the words
+// are cleared before each frame.
+constexpr unsigned long long kTagMask = 0xffffull;
+__device__ inline unsigned long long tag_word(double v, unsigned long long tag) {
+    return ((unsigned long long)__double_as_longlong(v) & ~kTagMask) | tag;
+}
+__device__ inline double untag_word(unsigned long long w) { return __longlong_as_double((long long)(w & ~kTagMask)); }
+constexpr unsigned kTagSpinLimit = 1u << 20;
+
 template <bool COMP>
 __device__ inline void store_partial(const float acc[kNE], const float cmp[kNE], double* partial,
-                                     ReduceLds& r) {
+                                     ReduceLds& r, unsigned long long tag = 0) {
 #pragma unroll
     for (int k = 0; k < kNE; ++k) r.v[k][threadIdx.x] = COMP ? acc[k] - cmp[k] : acc[k];
     __syncthreads();
@@ -509,7 +522,11 @@ __device__ inline void store_partial(const float acc[kNE], const float cmp[kNE],
 #pragma unroll
             for (int p = 0; p < 8; ++p) s += r.part[threadIdx.x][p];
         }
-        __hip_atomic_store(&partial[threadIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tag)
+            __hip_atomic_store(reinterpret_cast<unsigned long long*>(&partial[threadIdx.x]), tag_word(s, tag),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            __hip_atomic_store(&partial[threadIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
 }
@@ -689,44 +706,39 @@ __device__ inline bool solve_update_wave(const double* ne, double damping, doubl
 // another (partial sums, leaf sums, the published pose, tickets and counts) is
 // written and read only with device-scope atomic operations, which the
 // hardware keeps coherent per location across the XCDs without cache
-// maintenance.  Ordering is then all that is needed: a producer waits until
-// its device-scope stores have completed before it signals (s_waitcnt on all
-// counters, below), and a consumer issues its loads only after the signal's
-// value has returned.  A release/acquire fence at device scope would add an
+// maintenance.  A tagged word (the tracking kernel's partials and leaf
+// sums) needs nothing more: it is written by one 64-bit store, so a reader
+// that sees its tag sees its value.  Elsewhere ordering is all that is
+// needed: a producer waits until its device-scope stores have completed
+// before it signals (s_waitcnt on all counters, below), and a consumer
+// issues its loads only after the signal's value has returned.  A
+// release/acquire fence at device scope would add an
 // L2 write-back and invalidation per work-group and iteration (measured at
 // about 10 % of the kernel at 640x480) to order plain memory operations,
 // which this kernel does not exchange.
 __device__ inline void complete_device_stores() { __builtin_amdgcn_s_waitcnt(0); }
 
-// Sync words in the scratch buffer.  Arrival is a two-level tree of tickets
-// (device-scope atomics on one address serialise, so a single ticket for
-// hundreds of work-groups would cost tens of microseconds): kLeaf
-// work-groups share a leaf ticket; two ticket sets alternate between
-// iterations.  Single-launch reductions (the normal equations) close the
-// tree with a root ticket; the tracking kernel instead counts published leaf
-// sums in a monotonic done word that the work-groups of the level poll, and
-// publishes the pose at level boundaries for work-groups that join.  Then an
-// abort flag.
+// Reduction across work-groups: a two-level tree, kLeaf work-groups to a
+// leaf.  Single-launch reductions (the normal equations) use arrival
+// tickets (device-scope atomics on one address serialise, so a single
+// ticket for hundreds of work-groups would cost tens of microseconds): the
+// last work-group of a leaf adds the leaf's partials, the last leaf adds
+// the leaf sums.  The tracking kernel uses no tickets: its partials and
+// leaf sums are tagged with their iteration (below), the first work-group
+// of each leaf polls its leaf's partials, and every member polls the leaf
+// sums.  Sync words: the tickets, the iteration count of the pose published
+// at level boundaries for work-groups that join, and an abort flag.
 constexpr int kLeaf = 16;
 constexpr int kMaxLeaves = kMaxGroups / kLeaf;
 // one set of partials: a partial per work-group, then one per leaf
 constexpr size_t kPartsPerSet = (size_t)(kMaxGroups + kMaxLeaves) * kPartStride;
 // Leaf tickets are kTicketStride words (256 B) apart: device-scope atomics
-// on one cache line share the memory-side atomic unit, and with all leaf
-// tickets on one line a full-resolution iteration spent 2.3 us in them
-// (measured; 176 against 186 us per frame at 640x480).
+// on one cache line share the memory-side atomic unit.
 constexpr int kTicketStride = 64;
-// The done count is kept in kDoneCopies copies (one per XCD under the
-// round-robin placement of work-groups), each on its own line: a leaf
-// winner adds to every copy and a member polls copy blockIdx % kDoneCopies,
-// so 256 pollers do not share one line with the adds they wait for
-// (measured 168 against 176 us per frame).
-constexpr int kDoneCopies = 8;
 enum {
     kSyncLeaf = 0,                                          // [2][kMaxLeaves] x kTicketStride
     kSyncRoot = kSyncLeaf + 2 * kMaxLeaves * kTicketStride,  // [2]
-    kSyncDone = kSyncRoot + 2,              // [kDoneCopies] x kTicketStride
-    kSyncPub = kSyncDone + kDoneCopies * kTicketStride,  // iterations reflected by the published pose
+    kSyncPub = kSyncRoot + 2,                               // iterations reflected by the published pose
     kSyncAbort = kSyncPub + 1,
     kSyncWords = kSyncAbort + 1
 };
@@ -805,32 +817,84 @@ __device__ inline bool reduce_tree(const float acc[kNE], const float cmp[kNE], d
     return true;
 }
 
-// A participant's share of an iteration: store the work-group partial and
-// take the leaf ticket; the last work-group of the leaf adds the leaf's
-// partials, stores the leaf sum (device scope) and, once those stores have
-// completed, counts it in the done word.
+// The sum of n tagged partials (consecutive, kPartStride apart) of the
+// iteration tagged `tag`, in the order of total_partials (thread (k, p) adds
+// entry k of the partials p, p+8, ...), each word polled until it carries
+// the tag.  Result in r.tot; false (in every thread) on timeout or when
+// another work-group aborted.
 template <bool COMP>
-__device__ inline void contribute(const float acc[kNE], const float cmp[kNE], double* part, double* leafpart,
-                                  unsigned* sync, int par, int groups, ReduceLds& r, int* s_flag) {
-    store_partial<COMP>(acc, cmp, part + (size_t)blockIdx.x * kPartStride, r);
-    if (threadIdx.x == 0) *s_flag = leaf_arrive(sync, par, groups) ? 1 : 0;
+__device__ inline bool total_leaves(const double* leafpart, int nleaf, unsigned long long tag, const unsigned* sync,
+                                    ReduceLds& r) {
+    bool ok = true;
+    if (threadIdx.x < kNE * 8) {
+        const int k = threadIdx.x >> 3, p = threadIdx.x & 7;
+        double s = 0.0;
+        Kahan ks;
+        for (int b0 = p; b0 < nleaf && ok; b0 += 16) {
+            const int b1 = b0 + 8;
+            const unsigned long long* w0 =
+                reinterpret_cast<const unsigned long long*>(&leafpart[(size_t)b0 * kPartStride + k]);
+            const unsigned long long* w1 =
+                reinterpret_cast<const unsigned long long*>(&leafpart[(size_t)(b1 < nleaf ? b1 : b0) * kPartStride + k]);
+            unsigned long long x0 = __hip_atomic_load(w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned long long x1 =
+                b1 < nleaf ? __hip_atomic_load(w1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : tag;
+            unsigned spins = 0;
+            while ((x0 & kTagMask) != tag || (x1 & kTagMask) != tag) {
+                if (++spins > kTagSpinLimit ||
+                    ((spins & 255u) == 0u &&
+                     __hip_atomic_load(&sync[kSyncAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                    ok = false;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                if ((x0 & kTagMask) != tag) x0 = __hip_atomic_load(w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((x1 & kTagMask) != tag) x1 = __hip_atomic_load(w1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (COMP) {
+                ks.add((float)untag_word(x0));
+                if (b1 < nleaf) ks.add((float)untag_word(x1));
+            } else {
+                s += untag_word(x0);
+                if (b1 < nleaf) s += untag_word(x1);
+            }
+        }
+        r.part[k][p] = COMP ? (double)ks.value() : s;
+    }
+    if (__syncthreads_or(ok ? 0 : 1)) return false;
+    if (threadIdx.x < kNE) {
+        const int k = threadIdx.x;
+        if (COMP) {
+            Kahan ks;
+            for (int p = 0; p < 8; ++p) ks.add((float)r.part[k][p]);
+            r.tot[k] = (double)ks.value();
+        } else {
+            double t = 0.0;
+            for (int p = 0; p < 8; ++p) t += r.part[k][p];
+            r.tot[k] = t;
+        }
+    }
     __syncthreads();
-    if (!*s_flag) return;
+    return true;
+}
+
+// A member's share of an iteration: store the tagged work-group partial;
+// the first work-group of each leaf adds the leaf's partials as they carry
+// the tag and stores the tagged leaf sum (device scope).  False (in every
+// thread of a leaf's first work-group) on timeout or abort.
+template <bool COMP>
+__device__ inline bool contribute(const float acc[kNE], const float cmp[kNE], double* part, double* leafpart,
+                                  int groups, const unsigned* sync, ReduceLds& r, unsigned long long tag) {
+    store_partial<COMP>(acc, cmp, part + (size_t)blockIdx.x * kPartStride, r, tag);
+    if (blockIdx.x % kLeaf != 0) return true;
     const int leaf = blockIdx.x / kLeaf;
     const int leaf_size = min(kLeaf, groups - leaf * kLeaf);
-    double lsum[kNE];
-    total_partials<COMP>(part + (size_t)leaf * kLeaf * kPartStride, leaf_size, lsum, r);
+    if (!total_leaves<COMP>(part + (size_t)leaf * kLeaf * kPartStride, leaf_size, tag, sync, r)) return false;
     // r.tot holds the leaf sum in every thread; lanes of wave 0 store it
     if (threadIdx.x < kNE)
-        __hip_atomic_store(&leafpart[(size_t)leaf * kPartStride + threadIdx.x], r.tot[threadIdx.x],
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        complete_device_stores();
-        for (int r = 0; r < kDoneCopies; ++r)
-            __hip_atomic_fetch_add(&sync[kSyncDone + r * kTicketStride], 1u, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-    }
+        __hip_atomic_store(reinterpret_cast<unsigned long long*>(&leafpart[(size_t)leaf * kPartStride + threadIdx.x]),
+                           tag_word(r.tot[threadIdx.x], tag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
 }
 
 // Wait (thread 0 only) until the sync word `word` reaches `target`;
@@ -884,8 +948,9 @@ __device__ inline int band_rank(int b, int n) {
 // sums alternate between two sets by iteration parity.  A member writes set
 // (gi & 1) again at gi + 2 only after it has seen every leaf sum of gi + 1;
 // each of those was published after its leaf's members had contributed to
-// gi + 1, which they do only after reading the sums of gi, so no member
-// reads a set while it is overwritten.  The published pose of a level
+// gi + 1, which they do only after reading the sums of gi, and by the first
+// work-group of the leaf after it had read the leaf's partials of gi, so no
+// set is read while it is overwritten.  The published pose of a level
 // boundary is overwritten only at the next boundary, which needs the
 // contributions of the work-groups that joined and read it.
 template <int STORAGE, int MODEL>
@@ -893,7 +958,7 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
                                                               double* pose_out, double* partials, unsigned* sync,
                                                               float* stats, int32_t* status) {
     __shared__ double s_pose[12];
-    __shared__ int s_flag, s_ok;
+    __shared__ int s_ok;
     __shared__ ReduceLds red;
     __shared__ float s_depth[kTrackBatch * kTrackBlock];
     constexpr bool COMP = STORAGE != GSDF_FP32;
@@ -911,7 +976,6 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
     __syncthreads();
     int gi = 0;           // global iteration index
     int have = 0;         // iterations the pose in s_pose reflects
-    unsigned target = 0;  // leaf sums published once iteration gi is complete
     for (int l = a.levels - 1; l >= 0; --l) {
         if (a.iters[l] == 0) continue;
         const TrackLevel L = a.lv[l];
@@ -920,7 +984,6 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
         if ((int)blockIdx.x >= Gl) {
             // not a member: skip the level
             gi += a.iters[l];
-            target += (unsigned)(nleaf * a.iters[l]);
             continue;
         }
         if (have < gi) {
@@ -965,21 +1028,16 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
                 accumulate_trilinear<STORAGE>(M, L, a, P, first, kTrackBlock, c1, s_depth, acc, cmp);
             else
                 accumulate<STORAGE>(M, L, a, P, first, kTrackBlock, c1, s_depth, acc, cmp);
-            contribute<COMP>(acc, cmp, part, leafpart, sync, gi & 1, Gl, red, &s_flag);
-            target += (unsigned)nleaf;
-            if (threadIdx.x == 0)
-                s_ok = wait_done(sync, kSyncDone + (blockIdx.x % kDoneCopies) * kTicketStride, target) ? 1 : 0;
-            __syncthreads();
-            if (!s_ok) {
+            const unsigned long long tag = (unsigned long long)(gi + 1);
+            // every member: the same sum of the leaf sums, the same solve
+            if (!contribute<COMP>(acc, cmp, part, leafpart, Gl, sync, red, tag) ||
+                !total_leaves<COMP>(leafpart, nleaf, tag, sync, red)) {
                 if (threadIdx.x == 0) {
                     __hip_atomic_store(&sync[kSyncAbort], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     raise_status(status, GSDF_EHIP);
                 }
                 return;
             }
-            // every member: the same sum of the leaf sums, the same solve
-            double ne[kNE];
-            total_partials<COMP>(leafpart, nleaf, ne, red);
             if (threadIdx.x < 64) {
                 const bool solved = solve_update_wave(red.tot, a.damping, s_pose);
                 if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1053,6 +1111,8 @@ struct PyramidArgs {
     int levels;
     float zmin, zmax, Tf;
     unsigned* sync;
+    unsigned long long* sets[2];   // tagged partials and leaf sums of the two sets (null: none)
+    int part_words;                // words of the work-group partials of a set to clear
 };
 
 __device__ inline float pyr_combine(float a, float b, float c, float e, const PyramidArgs& p) {
@@ -1073,6 +1133,16 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs p) {
         const int nthreads = gridDim.x * gridDim.y * blockDim.x;
         const int tid = (blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
         for (int k = tid; k < kSyncWords; k += nthreads) p.sync[k] = 0u;
+        if (p.sets[0]) {
+            // the partials of the work-groups that run, then every leaf sum
+            constexpr int kLeafWords = kMaxLeaves * kPartStride;
+            for (int k = tid; k < p.part_words + kLeafWords; k += nthreads) {
+                const size_t w = k < p.part_words ? (size_t)k
+                                                  : (size_t)kMaxGroups * kPartStride + (size_t)(k - p.part_words);
+                p.sets[0][w] = 0ull;
+                p.sets[1][w] = 0ull;
+            }
+        }
     }
     if (p.levels < 2) return;
     const int u = blockIdx.x * 16 + tx, v = blockIdx.y * 16 + ty;
@@ -1261,8 +1331,12 @@ extern "C" int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, con
         p.zmax = cam->zmax;
         p.Tf = (float)map->desc.truncation;
         p.sync = sync;
+        for (int q = 0; q < 2; ++q)
+            p.sets[q] = reinterpret_cast<unsigned long long*>(partials + (size_t)q * kPartsPerSet);
+        p.part_words = kMaxGroups * kPartStride;
         TimedLaunch tp(GSDF_K_PYRAMID, s);
-        dim3 grd(levels > 1 ? ceil_div(a.lv[1].W, 16) : 1, levels > 1 ? ceil_div(a.lv[1].H, 16) : 1);
+        // a single level has no pyramid work: enough work-groups for the clearing
+        dim3 grd(levels > 1 ? ceil_div(a.lv[1].W, 16) : 32, levels > 1 ? ceil_div(a.lv[1].H, 16) : 1);
         k_pyramid<<<grd, 256, 0, s>>>(p);
     }
     const MapView M = make_view(*map);
