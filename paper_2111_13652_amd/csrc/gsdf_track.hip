@@ -913,11 +913,10 @@ __device__ inline bool wait_done(unsigned* sync, int word, unsigned target) {
 
 // Work-groups that take part at a level: about kPixPerGroup pixels each,
 // at least kMinGroups (so coarse levels keep enough memory parallelism and
-// a two-level arrival tree) and at most the grid.  Measured on MI355X at
-// 640x480: the per-iteration cost of the coarse levels is dominated by the
-// grid-wide reduction, which falls with fewer groups until the per-thread
-// pixel chains and the arrival contention take over.
-constexpr int kPixPerGroup = 1024;
+// a two-level tree) and at most the grid.  Measured on MI355X at 640x480
+// (levels of 19200, 76800 and 307200 pixels): 128, 256 and 256 members per
+// level; 64 at the coarsest level, or 128 at the middle one, are slower.
+constexpr int kPixPerGroup = 256;
 constexpr int kMinGroups = 128;
 __device__ inline int level_groups(const TrackLevel& L, int G) {
     int g = (L.W * L.H + kPixPerGroup - 1) / kPixPerGroup;
