@@ -42,6 +42,7 @@ constexpr int kTileH = kTile + 2 * kHalo;
 constexpr int kFuseBlock = 256;
 constexpr int kFuseChunk = 2048;   // box pixels scanned per pass (LDS queue capacity)
 constexpr int kFuseGroups = 4096;
+constexpr int kShortRun = 8;       // queue entries with at most this many band samples count as short
 constexpr float kBoxMargin = 1e-4f;  // metres; far above binary32 rounding of coordinates
 
 struct FuseConsts {
@@ -269,7 +270,7 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
     __shared__ BlockBox box;
     __shared__ uint32_t q_pix[kFuseChunk];
     __shared__ uint32_t q_k[kFuseChunk];
-    __shared__ int q_count;
+    __shared__ int q_count[2];   // short entries from the front, long ones from the back
 
     double R[9], t[3];
 #pragma unroll
@@ -333,7 +334,7 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
         // three lanes in four idle).
         for (int c0 = 0; c0 < npx; c0 += kFuseChunk) {
             const int cn = min(kFuseChunk, npx - c0);
-            if (threadIdx.x == 0) q_count = 0;
+            if (threadIdx.x < 2) q_count[threadIdx.x] = 0;
             __syncthreads();
             for (int p = threadIdx.x; p < cn; p += kFuseBlock) {
                 const int q = c0 + p;
@@ -384,30 +385,47 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
                         keep = k0 <= k1;
                     }
                 }
-                // wave-level compaction into the queue
-                const unsigned long long ballot = __ballot(keep);
-                if (ballot) {
-                    const int lane = threadIdx.x & 63;
-                    const int n_wave = __popcll(ballot);
+                // wave-level compaction into the queue: entries with at most
+                // kShortRun samples fill it from the front, longer ones from
+                // the back, so a wave of the fuse phase takes entries of one
+                // kind and its sample loop leaves fewer lanes idle
+                const bool is_long = k1 - k0 >= kShortRun;
+                const int lane = threadIdx.x & 63;
+#pragma unroll
+                for (int kind = 0; kind < 2; ++kind) {
+                    const bool mine = keep && (is_long == (kind == 1));
+                    const unsigned long long ballot = __ballot(mine);
+                    if (!ballot) continue;
+                    const int leader = __ffsll((long long)ballot) - 1;
                     int base = 0;
-                    if (lane == __ffsll((long long)ballot) - 1) base = atomicAdd(&q_count, n_wave);
-                    base = __shfl(base, __ffsll((long long)ballot) - 1);
-                    if (keep) {
-                        const int slot_q = base + __popcll(ballot & ((1ull << lane) - 1ull));
+                    if (lane == leader) base = atomicAdd(&q_count[kind], __popcll(ballot));
+                    base = __shfl(base, leader);
+                    if (mine) {
+                        const int r = base + __popcll(ballot & ((1ull << lane) - 1ull));
+                        const int slot_q = kind == 0 ? r : kFuseChunk - 1 - r;
                         q_pix[slot_q] = ((uint32_t)v << 16) | (uint32_t)u;   // u, v < 2^16
                         q_k[slot_q] = (uint32_t)(k0 | (k1 << 16));
                     }
                 }
             }
             __syncthreads();
-            const int nq = q_count;
-            // lane-major order over the queue: the lanes of a wave take
-            // entries nq/64 apart (different rows of the box), so the LDS
-            // atomics of one instruction rarely hit the same voxel
-            const int lane_stride = (nq + 63) / 64;
-            for (int p = threadIdx.x; p < lane_stride * 64; p += kFuseBlock) {
-                const int e = (p & 63) * lane_stride + (p >> 6);
-                if (e >= nq) continue;
+            const int nq0 = q_count[0], nq1 = q_count[1];
+            // lane-major order within each kind: the lanes of a wave take
+            // entries n/64 apart (different rows of the box), so the LDS
+            // atomics of one instruction rarely hit the same voxel; a wave's
+            // row of 64 entries lies within one kind
+            const int ls0 = (nq0 + 63) / 64, ls1 = (nq1 + 63) / 64;
+            for (int p = threadIdx.x; p < (ls0 + ls1) * 64; p += kFuseBlock) {
+                const int row = p >> 6;
+                int e;
+                if (row < ls0) {
+                    e = (p & 63) * ls0 + row;
+                    if (e >= nq0) continue;
+                } else {
+                    e = (p & 63) * ls1 + (row - ls0);
+                    if (e >= nq1) continue;
+                    e = kFuseChunk - 1 - e;
+                }
                 const uint32_t uv = q_pix[e];
                 const int k0 = (int)(q_k[e] & 0xffffu), k1 = (int)(q_k[e] >> 16);
                 const int v = (int)(uv >> 16);
