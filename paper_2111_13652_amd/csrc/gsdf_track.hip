@@ -10,11 +10,12 @@
 // of H = sum w J J^T, the 6 of b = sum w J r, the energy, the count of
 // pixels used and the count of valid pixels.  From there every sum is
 // float64: LDS across the waves of a work-group, then one partial per
-// work-group, then one sum per leaf of kLeaf work-groups (added by the last
-// of them to arrive, a device-scope ticket).  Every work-group then reads
-// the leaf sums, adds them in the same fixed order and solves the 6x6
-// system itself, so all of them hold the bit-identical new pose without a
-// round trip through a publisher; work-group 0 writes the final pose.
+// work-group, then one sum per leaf of kLeaf work-groups (added by the
+// first work-group of the leaf once every partial of the leaf carries the
+// iteration's tag).  Every work-group then reads the leaf sums the same
+// way, adds them in the same fixed order and solves the 6x6 system itself,
+// so all of them hold the bit-identical new pose without a round trip
+// through a publisher; work-group 0 writes the final pose.
 // Waits are bounded spins, so every wave exits even if something went
 // wrong.  Float64 partial sums keep the rounding noise of b far below what a
 // rank-deficient H (a lone sphere) would amplify through the damping.
@@ -460,7 +461,8 @@ __device__ inline void accumulate_trilinear(const MapView& M, const TrackLevel& 
 // chain ~180 dependent LDS permutes per wave.)  The plain path adds in
 // float64; the precision form (COMP) uses compensated float32 at every
 // stage.  The storing threads are lanes of wave 0, so thread 0 (which takes
-// the arrival ticket) waits for their completion before signalling.
+// the arrival ticket, where there is one) waits for their completion before
+// signalling.
 struct ReduceLds {
     float v[kNE][kTrackBlock];
     double part[kNE][8];
@@ -703,7 +705,7 @@ __device__ inline bool solve_update_wave(const double* ne, double damping, doubl
 }
 
 // Memory ordering between work-groups.  Everything one work-group hands to
-// another (partial sums, leaf sums, the published pose, tickets and counts) is
+// another (partial sums, leaf sums, the published pose, tickets and flags) is
 // written and read only with device-scope atomic operations, which the
 // hardware keeps coherent per location across the XCDs without cache
 // maintenance.  A tagged word (the tracking kernel's partials and leaf
@@ -727,7 +729,9 @@ __device__ inline void complete_device_stores() { __builtin_amdgcn_s_waitcnt(0);
 // leaf sums are tagged with their iteration (below), the first work-group
 // of each leaf polls its leaf's partials, and every member polls the leaf
 // sums.  Sync words: the tickets, the iteration count of the pose published
-// at level boundaries for work-groups that join, and an abort flag.
+// at level boundaries for work-groups that join, and an abort flag.  The
+// pyramid kernel clears them and the tagged words before each tracking
+// launch.
 constexpr int kLeaf = 16;
 constexpr int kMaxLeaves = kMaxGroups / kLeaf;
 // one set of partials: a partial per work-group, then one per leaf
@@ -1102,7 +1106,8 @@ __global__ __launch_bounds__(kTrackBlock) void k_normal_equations(MapView M, Tra
 // mean of four valid depths whose spread is within the truncation, else 0.
 // A work-group covers a 16x16 tile of level 1 (from level 0 in global
 // memory); its 8x8 level-2 and 4x4 level-3 pixels come from LDS.  The
-// work-groups also clear the sync words of the tracking kernel between them.
+// work-groups also clear the sync words and the tagged partials and leaf
+// sums of the tracking kernel between them.
 struct PyramidArgs {
     const float* src;
     float* dst[4];
@@ -1128,7 +1133,8 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs p) {
     __shared__ float t2[8][9];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     {
-        // every work-group clears its share of the tracking kernel's sync words
+        // every work-group clears its share of the tracking kernel's sync
+        // words and tagged words
         const int nthreads = gridDim.x * gridDim.y * blockDim.x;
         const int tid = (blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
         for (int k = tid; k < kSyncWords; k += nthreads) p.sync[k] = 0u;
