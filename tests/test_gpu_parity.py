@@ -322,3 +322,28 @@ def test_track_ignores_words_left_in_its_scratch(torch_mod, room_stream):
         P = run(G, iters)
         assert torch.equal(P, ref[iters]), (iters, (P - ref[iters]).abs().max().item())
         assert G.status_flags() == []
+
+
+def test_stream_closed_loop_matches_oracle(torch_mod):
+    """The frame loop end to end on the 640x480 room stream: frame 0 fused at
+    its true pose, every later frame tracked from the previous estimate and
+    fused at the new one, on the GPU and in the FP64 oracle, each feeding on
+    its own estimates.  Per-frame pose difference and both trajectories'
+    errors against the truth are reported; the two loops stay together."""
+    torch = torch_mod
+    from paper_2111_13652_amd.gsdf import run_stream
+    N = 16
+    st = synth.make_stream(ROOM["cam"], N, 1, 2, 3)   # the room stream's first N frames
+    log(f"case: closed loop, room 640x480, frames 0-{N - 1}, GPU and oracle each on their own estimates")
+    _, po = oracle.track_stream(st.depth[:N], st.cam, st.poses[:N], 0.01, 0.05)
+    po = np.asarray(po, np.float64)
+    G = _gpu_map(0.01, 0.05)
+    pg = run_stream(G, dev(st.depth[:N]), st.cam, dev(st.poses[0].copy())).cpu().numpy()
+    assert G.status_flags() == []
+    diffs = np.array([pose_diff(pg[f], po[f]) for f in range(N)])
+    ate = lambda P: float(np.sqrt(np.mean(np.sum((P[:, :, 3] - st.poses[:N, :, 3]) ** 2, axis=1))))
+    log(f"  per-frame GPU vs oracle: max {diffs[:, 0].max():.2e} rad, {diffs[:, 1].max():.2e} m "
+        f"(last frame {diffs[-1, 0]:.2e} rad, {diffs[-1, 1]:.2e} m)")
+    log(f"  ATE against the truth: GPU {ate(pg) * 1e3:.4f} mm, oracle {ate(po) * 1e3:.4f} mm")
+    assert diffs[:, 0].max() < 1e-5 and diffs[:, 1].max() < 1e-5
+    assert abs(ate(pg) - ate(po)) < 1e-6
