@@ -191,7 +191,12 @@ size_t gsdf_track_scratch_bytes(const gsdf_camera* cam, int32_t levels);
  * they may be the same buffer.  stats_dev (device, optional) receives 2
  * floats per iteration in execution order: the energy and the number of
  * pixels used at that linearisation.  scratch_dev must hold
- * gsdf_track_scratch_bytes(cam, levels) bytes. */
+ * gsdf_track_scratch_bytes(cam, levels) bytes; its contents on entry do not
+ * matter (the call clears what it needs before its iterations), and calls
+ * that may overlap in time (on different streams) need separate scratch.
+ * The launch needs every one of its work-groups resident at once (one per
+ * compute unit); every wait in it is bounded, so a device too busy to hold
+ * them fails the frame with GSDF_EHIP in *status_dev rather than hanging. */
 int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, const gsdf_camera* cam,
                      const gsdf_track_params* params, const double* T_init_dev, double* T_wc_out_dev,
                      float* stats_dev, void* scratch_dev, size_t scratch_bytes, int32_t* status_dev, void* stream);
