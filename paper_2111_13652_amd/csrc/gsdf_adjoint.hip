@@ -31,6 +31,9 @@ namespace gsdf {
 constexpr int kAdjBlock = 256;
 constexpr int kAdjPart = 8;         // doubles per work-group partial: loss, 6 pose sums, count
 constexpr int kAdjMaxGroups = 512;  // work-groups per keyframe
+constexpr int kAdjTile = 16;        // a work-group takes 16x16 pixel tiles
+constexpr int kAdjSet = 512;        // LDS table of a tile's voxels (entries)
+constexpr long long kAdjEmpty = -1;
 
 struct AdjArgs {
     int32_t W, H, groups, freeze;
@@ -135,22 +138,33 @@ __global__ __launch_bounds__(kAdjBlock) void k_keyframe_loss(MapView M, AdjArgs 
 #pragma unroll
     for (int k = 0; k < kAdjPart; ++k) acc[k] = 0.0f;
 
-    // Lanes of a wave take consecutive pixels of a row, so neighbouring lanes
-    // often share a voxel.  The gradient pass first sums each run of lanes
-    // with the same voxel (a segmented reduction over the wave) and lets the
-    // run's first lane issue the atomic adds: one set per (run, voxel)
-    // instead of one per pixel.
+    // A work-group takes 16x16 pixel tiles; a tile's pixels share a few
+    // dozen voxels, so the gradient pass first adds each pixel's terms into
+    // an LDS table keyed by voxel and then issues one set of global atomic
+    // adds per distinct voxel of the tile (device-scope float atomics are
+    // the costly part of the scatter).  A full table sends the pixel's terms
+    // to global memory directly.
+    __shared__ long long s_key[kAdjSet];
+    __shared__ float s_val[4][kAdjSet];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int base = blockIdx.x * kAdjBlock + wave * 64; base < N; base += a.groups * kAdjBlock) {
-        const int i = base + lane;
+    const int tiles_x = (a.W + kAdjTile - 1) / kAdjTile;
+    const int ntiles = tiles_x * ((a.H + kAdjTile - 1) / kAdjTile);
+    for (int tile = blockIdx.x; tile < ntiles; tile += a.groups) {
+        if (GRAD) {
+            for (int e = threadIdx.x; e < kAdjSet; e += kAdjBlock) {
+                s_key[e] = kAdjEmpty;
+                s_val[0][e] = s_val[1][e] = s_val[2][e] = s_val[3][e] = 0.0f;
+            }
+            __syncthreads();
+        }
+        const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+        const int u = tx * kAdjTile + (threadIdx.x % kAdjTile);
+        const int v = ty * kAdjTile + threadIdx.x / kAdjTile;
+        const int i = v * a.W + u;
         PixelTerm P;
         bool ok = false;
-        if (i < N) {
-            const int v = i / a.W;
-            const int u = i - v * a.W;
+        if (u < a.W && v < a.H)
             ok = pixel_term(M, a, R, t, params, dimg[i], u, v, aimg ? aimg + 3 * (size_t)i : nullptr, &P);
-        }
-        float g4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         if (ok) {
             const float r = P.psi + P.gh[0] * P.dq[0] + P.gh[1] * P.dq[1] + P.gh[2] * P.dq[2];
             const float ar = fabsf(r);
@@ -165,37 +179,40 @@ __global__ __launch_bounds__(kAdjBlock) void k_keyframe_loss(MapView M, AdjArgs 
                 for (int k = 0; k < 6; ++k) acc[1 + k] += rp * J[k];
                 const float gd = P.gh[0] * P.dq[0] + P.gh[1] * P.dq[1] + P.gh[2] * P.dq[2];
                 const float c = rp * P.inv_ng;
-                g4[0] = rp;
-                g4[1] = c * (P.dq[0] - P.gh[0] * gd);
-                g4[2] = c * (P.dq[1] - P.gh[1] * gd);
-                g4[3] = c * (P.dq[2] - P.gh[2] * gd);
+                const float g4[4] = {rp, c * (P.dq[0] - P.gh[0] * gd), c * (P.dq[1] - P.gh[1] * gd),
+                                     c * (P.dq[2] - P.gh[2] * gd)};
+                const long long key = (long long)P.vi;
+                unsigned h = (unsigned)(((unsigned long long)key * 0x9E3779B97F4A7C15ull) >> 55) & (kAdjSet - 1);
+                bool placed = false;
+                for (int probe = 0; probe < 32; ++probe) {
+                    const long long old = (long long)atomicCAS(reinterpret_cast<unsigned long long*>(&s_key[h]),
+                                                               (unsigned long long)kAdjEmpty,
+                                                               (unsigned long long)key);
+                    if (old == kAdjEmpty || old == key) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) atomicAdd(&s_val[k][h], g4[k]);
+                        placed = true;
+                        break;
+                    }
+                    h = (h + 1) & (kAdjSet - 1);
+                }
+                if (!placed) {
+                    float* dst = dparams + 4 * P.vi;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) atomicAdd(dst + k, g4[k]);
+                }
             }
         }
         if (GRAD) {
-            const int64_t key = ok ? P.vi : -1 - (int64_t)lane;   // unusable lanes: runs of their own
-            const int lo = __shfl_up((int)(key & 0xffffffff), 1);
-            const int hi = __shfl_up((int)(key >> 32), 1);
-            const int64_t prev = ((int64_t)hi << 32) | (uint32_t)lo;
-            const bool head = lane == 0 || prev != key;
-            const unsigned long long heads = __ballot(head);
-            const int rid = __popcll(heads & ((2ull << lane) - 1ull));   // run index, inclusive count
-            for (int off = 1; off < 64; off <<= 1) {
-                const int j = lane + off;
-                const bool same = j < 64 && __popcll(heads & ((2ull << j) - 1ull)) == rid;
-                if (!__any(same)) break;
-                float o[4];
+            __syncthreads();
+            for (int e = threadIdx.x; e < kAdjSet; e += kAdjBlock) {
+                const long long key = s_key[e];
+                if (key == kAdjEmpty) continue;
+                float* dst = dparams + 4 * key;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) o[k] = __shfl_down(g4[k], off);
-                if (same) {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) g4[k] += o[k];
-                }
+                for (int k = 0; k < 4; ++k) atomicAdd(dst + k, s_val[k][e]);
             }
-            if (ok && head) {
-                float* dst = dparams + 4 * P.vi;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) atomicAdd(dst + k, g4[k]);
-            }
+            __syncthreads();
         }
     }
     // work-group sums in float64: wave shuffles, then one value per wave
