@@ -31,8 +31,9 @@ namespace gsdf {
 constexpr int kAdjBlock = 256;
 constexpr int kAdjPart = 8;         // doubles per work-group partial: loss, 6 pose sums, count
 constexpr int kAdjMaxGroups = 512;  // work-groups per keyframe
-constexpr int kAdjTile = 16;        // a work-group takes 16x16 pixel tiles
-constexpr int kAdjSet = 512;        // LDS table of a tile's voxels (entries)
+constexpr int kAdjTile = 32;        // a work-group takes 32x32 pixel tiles, four pixels a thread
+constexpr int kAdjSetBits = 10;
+constexpr int kAdjSet = 1 << kAdjSetBits;   // LDS table of a tile's voxels (entries)
 constexpr long long kAdjEmpty = -1;
 
 struct AdjArgs {
@@ -138,12 +139,13 @@ __global__ __launch_bounds__(kAdjBlock) void k_keyframe_loss(MapView M, AdjArgs 
 #pragma unroll
     for (int k = 0; k < kAdjPart; ++k) acc[k] = 0.0f;
 
-    // A work-group takes 16x16 pixel tiles; a tile's pixels share a few
-    // dozen voxels, so the gradient pass first adds each pixel's terms into
+    // A work-group takes 32x32 pixel tiles; a tile's pixels share a few
+    // hundred voxels, so the gradient pass first adds each pixel's terms into
     // an LDS table keyed by voxel and then issues one set of global atomic
     // adds per distinct voxel of the tile (device-scope float atomics are
     // the costly part of the scatter).  A full table sends the pixel's terms
-    // to global memory directly.
+    // to global memory directly.  The larger the tile, the fewer of its
+    // voxels it shares with its neighbours, which flush them again.
     __shared__ long long s_key[kAdjSet];
     __shared__ float s_val[4][kAdjSet];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -158,48 +160,50 @@ __global__ __launch_bounds__(kAdjBlock) void k_keyframe_loss(MapView M, AdjArgs 
             __syncthreads();
         }
         const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
-        const int u = tx * kAdjTile + (threadIdx.x % kAdjTile);
-        const int v = ty * kAdjTile + threadIdx.x / kAdjTile;
-        const int i = v * a.W + u;
-        PixelTerm P;
-        bool ok = false;
-        if (u < a.W && v < a.H)
-            ok = pixel_term(M, a, R, t, params, dimg[i], u, v, aimg ? aimg + 3 * (size_t)i : nullptr, &P);
-        if (ok) {
-            const float r = P.psi + P.gh[0] * P.dq[0] + P.gh[1] * P.dq[1] + P.gh[2] * P.dq[2];
-            const float ar = fabsf(r);
-            const bool quad = ar <= a.delta;
-            acc[0] += quad ? 0.5f * r * r : a.delta * (ar - 0.5f * a.delta);
-            acc[7] += 1.0f;
-            if (GRAD) {
-                const float rp = s * (quad ? r : copysignf(a.delta, r));   // s rho'(r)
-                const float J[6] = {P.gh[0], P.gh[1], P.gh[2], P.q[1] * P.gh[2] - P.q[2] * P.gh[1],
-                                    P.q[2] * P.gh[0] - P.q[0] * P.gh[2], P.q[0] * P.gh[1] - P.q[1] * P.gh[0]};
+        for (int px = threadIdx.x; px < kAdjTile * kAdjTile; px += kAdjBlock) {
+            const int u = tx * kAdjTile + (px % kAdjTile);
+            const int v = ty * kAdjTile + px / kAdjTile;
+            const int i = v * a.W + u;
+            PixelTerm P;
+            bool ok = false;
+            if (u < a.W && v < a.H)
+                ok = pixel_term(M, a, R, t, params, dimg[i], u, v, aimg ? aimg + 3 * (size_t)i : nullptr, &P);
+            if (ok) {
+                const float r = P.psi + P.gh[0] * P.dq[0] + P.gh[1] * P.dq[1] + P.gh[2] * P.dq[2];
+                const float ar = fabsf(r);
+                const bool quad = ar <= a.delta;
+                acc[0] += quad ? 0.5f * r * r : a.delta * (ar - 0.5f * a.delta);
+                acc[7] += 1.0f;
+                if (GRAD) {
+                    const float rp = s * (quad ? r : copysignf(a.delta, r));   // s rho'(r)
+                    const float J[6] = {P.gh[0], P.gh[1], P.gh[2], P.q[1] * P.gh[2] - P.q[2] * P.gh[1],
+                                        P.q[2] * P.gh[0] - P.q[0] * P.gh[2], P.q[0] * P.gh[1] - P.q[1] * P.gh[0]};
 #pragma unroll
-                for (int k = 0; k < 6; ++k) acc[1 + k] += rp * J[k];
-                const float gd = P.gh[0] * P.dq[0] + P.gh[1] * P.dq[1] + P.gh[2] * P.dq[2];
-                const float c = rp * P.inv_ng;
-                const float g4[4] = {rp, c * (P.dq[0] - P.gh[0] * gd), c * (P.dq[1] - P.gh[1] * gd),
-                                     c * (P.dq[2] - P.gh[2] * gd)};
-                const long long key = (long long)P.vi;
-                unsigned h = (unsigned)(((unsigned long long)key * 0x9E3779B97F4A7C15ull) >> 55) & (kAdjSet - 1);
-                bool placed = false;
-                for (int probe = 0; probe < 32; ++probe) {
-                    const long long old = (long long)atomicCAS(reinterpret_cast<unsigned long long*>(&s_key[h]),
-                                                               (unsigned long long)kAdjEmpty,
-                                                               (unsigned long long)key);
-                    if (old == kAdjEmpty || old == key) {
+                    for (int k = 0; k < 6; ++k) acc[1 + k] += rp * J[k];
+                    const float gd = P.gh[0] * P.dq[0] + P.gh[1] * P.dq[1] + P.gh[2] * P.dq[2];
+                    const float c = rp * P.inv_ng;
+                    const float g4[4] = {rp, c * (P.dq[0] - P.gh[0] * gd), c * (P.dq[1] - P.gh[1] * gd),
+                                         c * (P.dq[2] - P.gh[2] * gd)};
+                    const long long key = (long long)P.vi;
+                    unsigned h = (unsigned)(((unsigned long long)key * 0x9E3779B97F4A7C15ull) >> (64 - kAdjSetBits));
+                    bool placed = false;
+                    for (int probe = 0; probe < 32; ++probe) {
+                        const long long old = (long long)atomicCAS(reinterpret_cast<unsigned long long*>(&s_key[h]),
+                                                                   (unsigned long long)kAdjEmpty,
+                                                                   (unsigned long long)key);
+                        if (old == kAdjEmpty || old == key) {
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) atomicAdd(&s_val[k][h], g4[k]);
-                        placed = true;
-                        break;
+                            for (int k = 0; k < 4; ++k) atomicAdd(&s_val[k][h], g4[k]);
+                            placed = true;
+                            break;
+                        }
+                        h = (h + 1) & (kAdjSet - 1);
                     }
-                    h = (h + 1) & (kAdjSet - 1);
-                }
-                if (!placed) {
-                    float* dst = dparams + 4 * P.vi;
+                    if (!placed) {
+                        float* dst = dparams + 4 * P.vi;
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) atomicAdd(dst + k, g4[k]);
+                        for (int k = 0; k < 4; ++k) atomicAdd(dst + k, g4[k]);
+                    }
                 }
             }
         }
@@ -319,7 +323,7 @@ __global__ void k_compose_poses(int32_t K, const double* __restrict__ T0, const 
 }
 
 inline int adj_groups(const gsdf_camera& cam) {
-    const int n = ceil_div(cam.width * cam.height, kAdjBlock);
+    const int n = ceil_div(cam.width, kAdjTile) * ceil_div(cam.height, kAdjTile);
     return n < kAdjMaxGroups ? n : kAdjMaxGroups;
 }
 
