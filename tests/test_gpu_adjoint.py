@@ -31,17 +31,7 @@ def room_stream():
 @pytest.fixture(scope="module")
 def maps(torch_mod, room_stream):
     """Oracle map of frames 0-3 and the GPU map holding the same values."""
-    from paper_2111_13652_amd.gsdf import GsdfMap
-    st = room_stream
-    O = oracle.OracleMap(0.01, 0.05)
-    for f in range(4):
-        O.allocate(st.depth[f], st.cam, st.poses[f])
-        O.integrate(st.depth[f], st.cam, st.poses[f])
-    G = GsdfMap(0.01, 0.05, 60000)
-    keys = O.keys()
-    psi, g, W, _ = O.voxels(keys)
-    G.import_blocks(keys, psi, g, W)
-    return O, G
+    return _oracle_and_gpu_maps(room_stream, range(4))
 
 
 def _keyframes(st, idx, seed):
@@ -51,14 +41,38 @@ def _keyframes(st, idx, seed):
     return st.depth[list(idx)], T0, xi
 
 
+def _oracle_and_gpu_maps(st, frames):
+    from paper_2111_13652_amd.gsdf import GsdfMap
+    O = oracle.OracleMap(0.01, 0.05)
+    for f in frames:
+        O.allocate(st.depth[f], st.cam, st.poses[f])
+        O.integrate(st.depth[f], st.cam, st.poses[f])
+    G = GsdfMap(0.01, 0.05, 60000)
+    keys = O.keys()
+    psi, g, W, _ = O.voxels(keys)
+    G.import_blocks(keys, psi, g, W)
+    return O, G
+
+
 def test_loss_and_gradients_match_the_oracle(torch_mod, room_stream, maps):
-    torch = torch_mod
-    from paper_2111_13652_amd.gsdf import KeyframeLoss, voxel_order
     O, G = maps
-    st = room_stream
-    depth, T0, xi = _keyframes(st, (4, 6, 8), 11)
+    _check_against_oracle(torch_mod, O, G, room_stream, (4, 6, 8), 11)
+
+
+def test_loss_and_gradients_on_a_ragged_image(torch_mod):
+    """An image of 150x110 pixels: the adjoint's pixel tiles do not divide
+    it, so the last tile of every row and column is partly outside."""
+    cam = synth.Camera(131.0, 131.0, 74.5, 54.5, 150, 110, 0.4, 4.0)
+    st = synth.make_stream(cam, 8, 1, 2, 3)
+    O, G = _oracle_and_gpu_maps(st, range(4))
+    _check_against_oracle(torch_mod, O, G, st, (4, 5, 7), 13)
+
+
+def _check_against_oracle(torch, O, G, st, idx, seed):
+    from paper_2111_13652_amd.gsdf import KeyframeLoss, voxel_order
+    depth, T0, xi = _keyframes(st, idx, seed)
     K = len(depth)
-    log(f"case: {K} keyframes 640x480, twist gradients + voxel gradients vs oracle")
+    log(f"case: {K} keyframes {st.cam.width}x{st.cam.height}, twist gradients + voxel gradients vs oracle")
     gk = G.keys()
     # the oracle's association at xi, reused frozen by the GPU: both sides
     # then sum over exactly the same (pixel, voxel) pairs
