@@ -49,41 +49,6 @@ struct TrackArgs {
     float min_inlier_frac;
 };
 
-__device__ inline double wave_sum(double x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
-}
-
-// Voxel values of the map at pool index vi: psi, gradient direction; false
-// when unobserved.
-template <int STORAGE>
-__device__ inline bool read_voxel(const MapView& M, int64_t vi, float* psi, float gh[3]) {
-    const float Wv = M.weight[vi];
-    if (!(Wv > 0.0f)) return false;
-    float g0, g1, g2;
-    if (STORAGE == GSDF_FP32) {
-        const float4 r = reinterpret_cast<const float4*>(M.vox)[vi];
-        *psi = r.x / Wv;
-        g0 = r.y;
-        g1 = r.z;
-        g2 = r.w;
-    } else {
-        const ushort4 p = reinterpret_cast<const ushort4*>(M.vox)[vi];
-        *psi = unpack16(p.x, STORAGE) * M.truncation;
-        g0 = unpack16(p.y, STORAGE);
-        g1 = unpack16(p.z, STORAGE);
-        g2 = unpack16(p.w, STORAGE);
-    }
-    const float n2 = g0 * g0 + g1 * g1 + g2 * g2;
-    if (!(n2 > 0.0f)) return false;
-    const float inv = 1.0f / sqrtf(n2);
-    gh[0] = g0 * inv;
-    gh[1] = g1 * inv;
-    gh[2] = g2 * inv;
-    return true;
-}
-
 // Compensated (Kahan) float32 accumulation: after any number of add()s,
 // value() is the sum with O(eps) rather than O(n eps) error.
 struct Kahan {
