@@ -166,7 +166,7 @@ def main():
     if timing:
         # inside the timed region only the roofline kernel (tracking) records
         # events (two per frame); the per-kernel breakdown is a second pass
-        lib.gsdf_timing_select(1 << _lib.K_TRACK)
+        m.timing(1 << _lib.K_TRACK)
     first = 1 + args.warmup
     c0 = m.counters()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -187,12 +187,9 @@ def main():
         out = {}
         for name, kid in (("track", _lib.K_TRACK), ("fuse_blocks", _lib.K_INTEGRATE),
                           ("alloc_normals", _lib.K_ALLOC_NORMALS), ("pyramid", _lib.K_PYRAMID)):
-            tot = C.c_double()
-            n = C.c_int64()
-            lib.gsdf_timing_read(kid, C.byref(tot), C.byref(n))
-            if n.value:
-                out[name] = {"total_ms": tot.value, "launches": n.value,
-                             "avg_us": 1e3 * tot.value / max(1, n.value)}
+            tot, n = m.timing_read(kid)
+            if n:
+                out[name] = {"total_ms": tot, "launches": n, "avg_us": 1e3 * tot / max(1, n)}
         return out
 
     kernels = {}
@@ -201,12 +198,12 @@ def main():
         track_live = read_kernels().get("track")
         # breakdown pass: the same frames again with every kernel timed
         start()
-        lib.gsdf_timing_enable(1)
+        m.timing(0xffffffff)
         for f in range(first, first + args.steps):
             step(f)
         torch.cuda.synchronize()
         kernels = read_kernels()
-        lib.gsdf_timing_enable(0)
+        m.timing(0)
 
     # ---- algorithmic bytes, from the live work counters
     K = args.steps
@@ -261,7 +258,7 @@ def main():
             fwd_bwd()
         reps = 20
         if timing:
-            lib.gsdf_timing_enable(1)
+            m.timing(0xffffffff)
         torch.cuda.synchronize()
         ev0.record(s)
         for _ in range(reps):
@@ -272,11 +269,9 @@ def main():
         dk = {}
         if timing:
             for name, kid in (("loss", _lib.K_LOSS), ("backward", _lib.K_BACKWARD)):
-                tot = C.c_double()
-                n = C.c_int64()
-                lib.gsdf_timing_read(kid, C.byref(tot), C.byref(n))
-                dk[name] = {"avg_us": 1e3 * tot.value / max(1, n.value), "launches": n.value}
-            lib.gsdf_timing_enable(0)
+                tot, n = m.timing_read(kid)
+                dk[name] = {"avg_us": 1e3 * tot / max(1, n), "launches": n}
+            m.timing(0)
         from paper_2111_13652_amd.gsdf import keyframe_loss
         cnt = torch.zeros(len(kf), dtype=torch.float64, device=dev)
         keyframe_loss(m, params.detach(), xi.detach(), D, cam, T0, delta, count=cnt)
@@ -327,7 +322,7 @@ def main():
     comparison = None
     if not args.no_comparison:
         start()
-        lib.gsdf_timing_select(1 << _lib.K_TRACK)
+        m.timing(1 << _lib.K_TRACK)
         torch.cuda.synchronize()
         ev0.record(s)
         for f in range(first, first + args.steps):
@@ -336,7 +331,7 @@ def main():
         torch.cuda.synchronize()
         ms_tri = ev0.elapsed_time(ev1)
         tr_tri = read_kernels().get("track")
-        lib.gsdf_timing_enable(0)
+        m.timing(0)
         Et = est[: first + K].cpu().numpy()
         comparison = {
             "model": "tri-linear distance of the 8 voxels around each point (Eq. 12-13)",

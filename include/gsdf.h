@@ -44,10 +44,12 @@ extern "C" {
 
 typedef enum {
     GSDF_OK = 0,
-    GSDF_EINVAL = -1,     /* bad argument (host)                                   */
+    GSDF_EINVAL = -1,     /* bad argument (host); on the device: a non-finite pose, */
+                          /* with which the call did no work                        */
     GSDF_ECAPACITY = -2,  /* hash table or block pool full (device): the block is  */
                           /* not allocated and later steps skip its voxels         */
-    GSDF_EHIP = -3,       /* a HIP call failed (host)                               */
+    GSDF_EHIP = -3,       /* a HIP call failed (host), or tracking gave up waiting  */
+                          /* for work-groups that never ran (device)                */
     GSDF_ENOTPD = -4,     /* a Gauss-Newton system was not positive definite        */
                           /* (device): that iteration's pose update is skipped      */
     GSDF_ELOST = -5       /* tracking used fewer than min_inlier_frac of the valid  */
@@ -75,14 +77,21 @@ typedef struct gsdf_map_desc {
     int32_t reserved1;
 } gsdf_map_desc;
 
+/* Per-kernel event timer (host object owned by the caller, see
+ * gsdf_timer_create); NULL in gsdf_map.timer means no timing. */
+typedef struct gsdf_timer gsdf_timer;
+
 /* The four caller-allocated device buffers of a map (sizes from
- * gsdf_map_buffer_sizes).  Layout inside them is private to the library. */
+ * gsdf_map_buffer_sizes).  Layout inside them is private to the library.
+ * The library keeps no state of its own between calls: everything a map
+ * needs lives in these buffers and in this struct. */
 typedef struct gsdf_map {
     void* hash;     /* hash table                                             */
     void* vox;      /* voxel records, max_blocks * 512                          */
     void* weight;   /* float32 accumulated weight W per voxel, max_blocks * 512 */
     void* aux;      /* block keys, counters, per-frame accumulators and lists   */
     gsdf_map_desc desc;
+    gsdf_timer* timer;  /* optional: launches on this map record events in it   */
 } gsdf_map;
 
 /* Pinhole camera (Sec. 4.1 back-projection x = D [(u-cx)/fx, (v-cy)/fy, 1]). */
@@ -109,6 +118,10 @@ typedef struct gsdf_track_params {
     double damping;          /* mu = damping * trace(H) / 6 added to H's diagonal */
     float min_inlier_frac;   /* GSDF_ELOST below this fraction at the finest level */
     int32_t model;           /* gsdf_residual_model                               */
+    int32_t max_polls;       /* bound on the polls of each wait between work-     */
+                             /* groups before the frame is given up with          */
+                             /* GSDF_EHIP; 0 = the library default (2^20 for the  */
+                             /* per-iteration sums, 2^24 for a level boundary)    */
 } gsdf_track_params;
 
 /* Residual model of tracking (Sec. 4.1). */
@@ -195,8 +208,14 @@ size_t gsdf_track_scratch_bytes(const gsdf_camera* cam, int32_t levels);
  * matter (the call clears what it needs before its iterations), and calls
  * that may overlap in time (on different streams) need separate scratch.
  * The launch needs every one of its work-groups resident at once (one per
- * compute unit); every wait in it is bounded, so a device too busy to hold
- * them fails the frame with GSDF_EHIP in *status_dev rather than hanging. */
+ * compute unit); every wait in it is bounded (params->max_polls), so a
+ * device too busy to hold them fails the frame with GSDF_EHIP in
+ * *status_dev rather than hanging; the estimate is then undefined.  A
+ * non-finite initial pose runs no iteration: the estimate is the initial
+ * pose and GSDF_EINVAL is raised.  GSDF_ENOTPD: some iteration's system was
+ * not positive definite (its update skipped); GSDF_ELOST: fewer than
+ * min_inlier_frac of the valid finest-level pixels found an observed voxel
+ * at the last linearisation. */
 int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, const gsdf_camera* cam,
                      const gsdf_track_params* params, const double* T_init_dev, double* T_wc_out_dev,
                      float* stats_dev, void* scratch_dev, size_t scratch_bytes, int32_t* status_dev, void* stream);
@@ -239,7 +258,7 @@ int gsdf_voxel_order(int32_t order_out[512]);
 int gsdf_compose_poses(int32_t n, const double* T0_dev, const double* xi_dev, double* T_out_dev,
                        void* stream);
 
-/* Scratch bytes of gsdf_keyframe_loss / gsdf_keyframe_backward. */
+/* Scratch bytes of gsdf_keyframe_loss / gsdf_backward. */
 size_t gsdf_keyframe_scratch_bytes(const gsdf_camera* cam, int32_t n_keyframes);
 
 /* Keyframe loss (Sec. 4.1 Eq. (5), (14); Huber penalty of Sec. 5.1): for
@@ -263,8 +282,11 @@ int gsdf_keyframe_loss(const gsdf_map* map, const float* depth_dev, int32_t n_ke
                        int32_t* assoc_dev, int32_t freeze, double* loss_dev, double* count_dev,
                        void* scratch_dev, size_t scratch_bytes, void* stream);
 
-/* Adjoint of gsdf_keyframe_loss, recomputing every residual (nothing per
- * pixel is stored between the two calls).  With s_i = grad_loss_dev[i]
+/* backward: the adjoint of gsdf_keyframe_loss (the differentiable form of
+ * the tracking energy of Sec. 4.1 Eq. (5), (14); g^ is differentiated
+ * through its normalisation, the association of pixel to voxel is held
+ * fixed as in Sec. 4.2), recomputing every residual (nothing per pixel is
+ * stored between the two calls).  With s_i = grad_loss_dev[i]
  * (K float32, device), rho' the Huber derivative and g^ = g/|g|:
  *   dparams[j] += sum s_i rho'(r) {1, (I - g^ g^T)(q - v_j) / |g_j|}
  *     (scatter-added at the voxel's slot: clear dparams_dev first),
@@ -272,12 +294,12 @@ int gsdf_keyframe_loss(const gsdf_map* map, const float* depth_dev, int32_t n_ke
  *     (K x 6 float64, overwritten; Jl the left Jacobian of SE(3)),
  *   loss_dev (optional) as gsdf_keyframe_loss.
  * Same argument rules as gsdf_keyframe_loss. */
-int gsdf_keyframe_backward(const gsdf_map* map, const float* depth_dev, int32_t n_keyframes,
-                           const gsdf_camera* cam, const double* T0_dev, const double* xi_dev,
-                           const float* params_dev, int64_t param_blocks, float huber_delta,
-                           int32_t* assoc_dev, int32_t freeze, const float* grad_loss_dev,
-                           float* dparams_dev, double* dxi_dev, double* loss_dev,
-                           void* scratch_dev, size_t scratch_bytes, void* stream);
+int gsdf_backward(const gsdf_map* map, const float* depth_dev, int32_t n_keyframes,
+                  const gsdf_camera* cam, const double* T0_dev, const double* xi_dev,
+                  const float* params_dev, int64_t param_blocks, float huber_delta,
+                  int32_t* assoc_dev, int32_t freeze, const float* grad_loss_dev,
+                  float* dparams_dev, double* dxi_dev, double* loss_dev,
+                  void* scratch_dev, size_t scratch_bytes, void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Photometric term (joint refinement with colour)                         */
@@ -390,8 +412,11 @@ int gsdf_gradient_quality(const gsdf_map* map, const double* spheres_dev, int32_
 /* Inspection, import (used for parity checks and checkpoints)             */
 /* ---------------------------------------------------------------------- */
 
-/* Block keys in pool order: keys_out_dev (device, max_blocks x 3 int32) and
- * their count in *n_dev (int32, device). */
+/* Block keys in pool-slot order: keys_out_dev (device, max_blocks x 3 int32)
+ * and their count in *n_dev (int32, device).  Row i is the block whose
+ * voxels are row i of gsdf_export_voxels and of gsdf_export_params, so the
+ * order pairs keys with values; a caller that wants the keys as a set sorts
+ * them (the parity tests compare sorted (x, y, z) triples). */
 int gsdf_export_keys(const gsdf_map* map, int32_t* keys_out_dev, int32_t* n_dev, void* stream);
 
 /* Work counters accumulated since the last reset (device, 16 uint64):
@@ -431,18 +456,19 @@ enum {
     GSDF_K_COUNT = 16
 };
 
-/* Enable (1) or disable (0) event timing around every kernel launch and
- * clear the accumulated totals. */
-int gsdf_timing_enable(int32_t on);
+/* Create a timer that records HIP events around the launches of the kernel
+ * ids whose bits are set in `mask` (two events per timed launch, on the
+ * launch's stream).  Attach it to a map by setting gsdf_map.timer; the
+ * caller owns it and destroys it after the last timed launch completed. */
+int gsdf_timer_create(uint32_t mask, gsdf_timer** timer_out);
+int gsdf_timer_destroy(gsdf_timer* timer);
 
-/* Event timing around the launches of the kernel ids whose bits are set in
- * `mask` only (0 disables), clearing the accumulated totals; each timed
- * launch records two events on its stream. */
-int gsdf_timing_select(uint32_t mask);
+/* Select the timed kernel ids (0 = none) and clear the accumulated totals. */
+int gsdf_timer_select(gsdf_timer* timer, uint32_t mask);
 
 /* Total milliseconds and launch count recorded for one kernel id since the
- * last enable; synchronises the recorded events. */
-int gsdf_timing_read(int32_t kernel_id, double* total_ms, int64_t* launches);
+ * last select; synchronises the recorded events. */
+int gsdf_timer_read(gsdf_timer* timer, int32_t kernel_id, double* total_ms, int64_t* launches);
 
 const char* gsdf_status_string(int32_t code);
 

@@ -26,7 +26,7 @@ class MapDesc(C.Structure):
 
 class Map(C.Structure):
     _fields_ = [("hash", C.c_void_p), ("vox", C.c_void_p), ("weight", C.c_void_p),
-                ("aux", C.c_void_p), ("desc", MapDesc)]
+                ("aux", C.c_void_p), ("desc", MapDesc), ("timer", C.c_void_p)]
 
 
 class Camera(C.Structure):
@@ -41,7 +41,8 @@ class FuseParams(C.Structure):
 
 class TrackParams(C.Structure):
     _fields_ = [("levels", C.c_int32), ("iters", C.c_int32 * 4), ("huber_delta", C.c_float),
-                ("damping", C.c_double), ("min_inlier_frac", C.c_float), ("model", C.c_int32)]
+                ("damping", C.c_double), ("min_inlier_frac", C.c_float), ("model", C.c_int32),
+                ("max_polls", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -74,8 +75,8 @@ _SIGNATURES = {
     "gsdf_keyframe_scratch_bytes": (_SZ, [C.POINTER(Camera), _I32]),
     "gsdf_keyframe_loss": (_I, [C.POINTER(Map), _P, _I32, C.POINTER(Camera), _P, _P, _P, C.c_int64,
                                 C.c_float, _P, _I32, _P, _P, _P, _SZ, _P]),
-    "gsdf_keyframe_backward": (_I, [C.POINTER(Map), _P, _I32, C.POINTER(Camera), _P, _P, _P, C.c_int64,
-                                    C.c_float, _P, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
+    "gsdf_backward": (_I, [C.POINTER(Map), _P, _I32, C.POINTER(Camera), _P, _P, _P, C.c_int64,
+                           C.c_float, _P, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
     "gsdf_photometric_scratch_bytes": (_SZ, [C.c_int64, _I32]),
     "gsdf_photometric_loss": (_I, [C.POINTER(Map), _P, _P, _I32, C.POINTER(Camera), _P, _P, _P, _P, C.c_int64,
                                    C.c_float, C.c_float, _P, _P, _P, _SZ, _P]),
@@ -89,9 +90,10 @@ _SIGNATURES = {
     "gsdf_surfel_scratch_bytes": (_SZ, [C.POINTER(Map)]),
     "gsdf_extract_surfels": (_I, [C.POINTER(Map), _I32, _P, _P, _P, C.c_int64, _P, _P, _SZ, _P]),
     "gsdf_gradient_quality": (_I, [C.POINTER(Map), _P, _I32, _P, C.c_int64, _P]),
-    "gsdf_timing_enable": (_I, [_I32]),
-    "gsdf_timing_select": (_I, [C.c_uint32]),
-    "gsdf_timing_read": (_I, [_I32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "gsdf_timer_create": (_I, [C.c_uint32, C.POINTER(C.c_void_p)]),
+    "gsdf_timer_destroy": (_I, [_P]),
+    "gsdf_timer_select": (_I, [_P, C.c_uint32]),
+    "gsdf_timer_read": (_I, [_P, _I32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "gsdf_status_string": (C.c_char_p, [_I32]),
 }
 
@@ -130,5 +132,5 @@ def check(code: int, what: str = "") -> None:
 
 def status_bits(word: int):
     """Names of the device status bits set in a status word."""
-    names = {ECAPACITY: "capacity", ENOTPD: "not_pd", ELOST: "lost", EINVAL: "invalid"}
+    names = {ECAPACITY: "capacity", ENOTPD: "not_pd", ELOST: "lost", EINVAL: "invalid", EHIP: "gave_up"}
     return [n for c, n in names.items() if word & (1 << (-c))]

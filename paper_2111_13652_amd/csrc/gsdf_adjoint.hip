@@ -380,7 +380,7 @@ int gsdf_keyframe_loss(const gsdf_map* map, const float* depth_dev, int32_t n_ke
     hipStream_t s = (hipStream_t)stream;
     const AdjArgs a = adj_args(*map, *cam, huber_delta, freeze, param_blocks);
     {
-        TimedLaunch tl(GSDF_K_LOSS, s);
+        TimedLaunch tl(map->timer, GSDF_K_LOSS, s);
         k_keyframe_loss<false><<<dim3(a.groups, n_keyframes), kAdjBlock, 0, s>>>(
             make_view(*map), a, depth_dev, T0_dev, xi_dev, reinterpret_cast<const float4*>(params_dev), nullptr,
             assoc_dev, nullptr, (double*)scratch);
@@ -389,11 +389,11 @@ int gsdf_keyframe_loss(const gsdf_map* map, const float* depth_dev, int32_t n_ke
     return launch_status();
 }
 
-int gsdf_keyframe_backward(const gsdf_map* map, const float* depth_dev, int32_t n_keyframes,
-                           const gsdf_camera* cam, const double* T0_dev, const double* xi_dev,
-                           const float* params_dev, int64_t param_blocks, float huber_delta, int32_t* assoc_dev,
-                           int32_t freeze, const float* grad_loss_dev, float* dparams_dev, double* dxi_dev,
-                           double* loss_dev, void* scratch, size_t scratch_bytes, void* stream) {
+int gsdf_backward(const gsdf_map* map, const float* depth_dev, int32_t n_keyframes,
+                  const gsdf_camera* cam, const double* T0_dev, const double* xi_dev, const float* params_dev,
+                  int64_t param_blocks, float huber_delta, int32_t* assoc_dev, int32_t freeze,
+                  const float* grad_loss_dev, float* dparams_dev, double* dxi_dev, double* loss_dev, void* scratch,
+                  size_t scratch_bytes, void* stream) {
     int rc = keyframe_common(map, depth_dev, n_keyframes, cam, T0_dev, xi_dev, params_dev, param_blocks,
                              huber_delta, scratch, scratch_bytes);
     if (rc != GSDF_OK) return rc;
@@ -401,7 +401,7 @@ int gsdf_keyframe_backward(const gsdf_map* map, const float* depth_dev, int32_t 
     hipStream_t s = (hipStream_t)stream;
     const AdjArgs a = adj_args(*map, *cam, huber_delta, freeze, param_blocks);
     {
-        TimedLaunch tl(GSDF_K_BACKWARD, s);
+        TimedLaunch tl(map->timer, GSDF_K_BACKWARD, s);
         k_keyframe_loss<true><<<dim3(a.groups, n_keyframes), kAdjBlock, 0, s>>>(
             make_view(*map), a, depth_dev, T0_dev, xi_dev, reinterpret_cast<const float4*>(params_dev),
             grad_loss_dev, assoc_dev, dparams_dev, (double*)scratch);

@@ -20,6 +20,10 @@ __device__ inline void allocate_tile(const MapView& M, const float* __restrict__
                                      float zmax, const BandConsts& bc, const double* __restrict__ Twc,
                                      int32_t* status, int tu, int tv, unsigned long long* s_keys,
                                      unsigned long long* red) {
+    if (!pose_finite(Twc)) {   // the same pose for every thread: a uniform exit
+        if (tu == 0 && tv == 0 && threadIdx.x == 0) raise_status(status, GSDF_EINVAL);
+        return;
+    }
     for (int i = threadIdx.x; i < kAllocSet; i += blockDim.x) s_keys[i] = kEmptyKey;
     __syncthreads();
     const int u = tu * 16 + (threadIdx.x & 15);

@@ -22,6 +22,15 @@ __device__ inline void raise_status(int32_t* status, int code) {
     if (status) atomicOr(status, 1 << (-code));
 }
 
+// A pose (12 float64, row-major 3x4) whose every entry is finite.  Calls
+// given anything else do no work and report GSDF_EINVAL on the device.
+__device__ inline bool pose_finite(const double* T) {
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) ok = ok && isfinite(T[k]);
+    return ok;
+}
+
 // ---------------------------------------------------------------------------
 // Block keys: three 21-bit biased coordinates packed into 63 bits.  The
 // all-ones word never encodes a valid key and marks an empty hash slot.

@@ -32,6 +32,7 @@
 
 #include "gsdf_alloc.hpp"
 #include "gsdf_common.hpp"
+#include "gsdf_fixed.hpp"
 #include "gsdf_host.hpp"
 
 namespace gsdf {
@@ -237,29 +238,14 @@ __device__ inline void block_box(const FuseConsts& fc, const double* R, const do
     B->inv_bw = B->u1 >= B->u0 ? 1.0f / (float)(B->u1 - B->u0 + 1) : 0.0f;
 }
 
-// Fixed point with f fraction bits for the per-frame voxel sums.  A term
-// w x enters as (w 2^f) x: scaling by a power of two is exact, so this is
-// (w x) 2^f rounded once.  The 64-bit integer is formed from two 32-bit
-// conversions, hi = floor(w x 2^(f-32)) and lo = w x 2^f - hi 2^32 in
-// [0, 2^32) (one instruction each, where a direct 64-bit conversion is a
-// long sequence).  A term converts exactly unless it is below 2^(23-f) or a
-// small negative one (then it is rounded, deterministically, within
-// 2^(8-f)); integer sums are exact, and the total is rounded once, to float.
-// f is chosen on the host so that the largest possible sum fits (see
-// fix_bits).  ws = w 2^f, wh = w 2^(f-32).
-__device__ inline unsigned long long fixed_term(float ws, float wh, float x) {
-    const float s = ws * x;
-    const float hs = floorf(wh * x);
-    const float lo = fmaf(-hs, 4294967296.0f, s);
-    return ((unsigned long long)(unsigned)(int)hs << 32) | (unsigned long long)(unsigned)lo;
-}
-__device__ inline float from_fixed(unsigned long long a, double inv) {
-    return (float)((double)(long long)a * inv);
-}
+// Per-frame voxel sums are fixed point with f fraction bits (fixed_term,
+// gsdf_fixed.hpp); f is chosen on the host so that the largest possible sum
+// fits (see fix_bits).
 
 template <int STORAGE>
 __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const float4* __restrict__ pix,
-                                                           FuseConsts fc, const double* __restrict__ Twc) {
+                                                           FuseConsts fc, const double* __restrict__ Twc,
+                                                           int32_t* status) {
     // per-voxel sums of the frame in fixed point (see fixed_term), indexed
     // lx + 8 ly + 64 lz (the pool's Morton order is applied at the write):
     // integer additions are associative, so the sums (and the map) do not
@@ -272,6 +258,10 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
     __shared__ uint32_t q_k[kFuseChunk];
     __shared__ int q_count[2];   // short entries from the front, long ones from the back
 
+    if (!pose_finite(Twc)) {   // nothing is fused at a non-finite pose
+        if (blockIdx.x == 0 && threadIdx.x == 0) raise_status(status, GSDF_EINVAL);
+        return;
+    }
     double R[9], t[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -596,7 +586,6 @@ extern "C" int gsdf_integrate_frame(gsdf_map* map, const float* depth_dev, const
                                     const double* T_wc_dev, const gsdf_fuse_params* params,
                                     void* scratch_dev, size_t scratch_bytes, int32_t* status_dev,
                                     void* stream) {
-    (void)status_dev;
     if (!valid_map(map) || !depth_dev || !valid_cam(cam) || !T_wc_dev || !params || !scratch_dev)
         return GSDF_EINVAL;
     if (!(params->eps_weight < map->desc.truncation)) return GSDF_EINVAL;
@@ -606,16 +595,16 @@ extern "C" int gsdf_integrate_frame(gsdf_map* map, const float* depth_dev, const
     const MapView M = make_view(*map);
     float4* pix = (float4*)scratch_dev;
     {
-        TimedLaunch t(GSDF_K_NORMALS, s);
+        TimedLaunch t(map->timer, GSDF_K_NORMALS, s);
         dim3 grid(ceil_div(cam->width, kTile), ceil_div(cam->height, kTile));
         k_pixel_normals<<<grid, 256, 0, s>>>(depth_dev, fc, T_wc_dev, pix);
     }
     {
-        TimedLaunch t(GSDF_K_INTEGRATE, s);
+        TimedLaunch t(map->timer, GSDF_K_INTEGRATE, s);
         switch (map->desc.storage) {
-            case GSDF_FP32: k_fuse_blocks<GSDF_FP32><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev); break;
-            case GSDF_BF16: k_fuse_blocks<GSDF_BF16><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev); break;
-            default: k_fuse_blocks<GSDF_FP16><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev); break;
+            case GSDF_FP32: k_fuse_blocks<GSDF_FP32><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev, status_dev); break;
+            case GSDF_BF16: k_fuse_blocks<GSDF_BF16><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev, status_dev); break;
+            default: k_fuse_blocks<GSDF_FP16><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev, status_dev); break;
         }
     }
     return launch_status();
@@ -633,16 +622,16 @@ extern "C" int gsdf_fuse_frame(gsdf_map* map, const float* depth_dev, const gsdf
     const MapView M = make_view(*map);
     float4* pix = (float4*)scratch_dev;
     {
-        TimedLaunch t(GSDF_K_ALLOC_NORMALS, s);
+        TimedLaunch t(map->timer, GSDF_K_ALLOC_NORMALS, s);
         dim3 grid(ceil_div(cam->width, kTile), ceil_div(cam->height, kTile));
         k_alloc_normals<<<grid, 256, 0, s>>>(M, depth_dev, fc, T_wc_dev, pix, status_dev);
     }
     {
-        TimedLaunch t(GSDF_K_INTEGRATE, s);
+        TimedLaunch t(map->timer, GSDF_K_INTEGRATE, s);
         switch (map->desc.storage) {
-            case GSDF_FP32: k_fuse_blocks<GSDF_FP32><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev); break;
-            case GSDF_BF16: k_fuse_blocks<GSDF_BF16><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev); break;
-            default: k_fuse_blocks<GSDF_FP16><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev); break;
+            case GSDF_FP32: k_fuse_blocks<GSDF_FP32><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev, status_dev); break;
+            case GSDF_BF16: k_fuse_blocks<GSDF_BF16><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev, status_dev); break;
+            default: k_fuse_blocks<GSDF_FP16><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev, status_dev); break;
         }
     }
     return launch_status();

@@ -12,20 +12,23 @@
 
 namespace gsdf {
 
-// ---- optional per-kernel event timing (see gsdf_timing_enable) ----
-bool timing_on(int kernel_id);
-void timing_begin(int kernel_id, hipStream_t s);
-void timing_end(int kernel_id, hipStream_t s);
+// ---- optional per-kernel event timing: the caller's gsdf_timer attached to
+// the map (gsdf_map.timer; NULL = none) ----
+bool timing_on(gsdf_timer* t, int kernel_id);
+void timing_begin(gsdf_timer* t, int kernel_id, hipStream_t s);
+void timing_end(gsdf_timer* t, int kernel_id, hipStream_t s);
 
 struct TimedLaunch {
+    gsdf_timer* t;
     int id;
     hipStream_t s;
     bool on;
-    TimedLaunch(int kernel_id, hipStream_t stream) : id(kernel_id), s(stream), on(timing_on(kernel_id)) {
-        if (on) timing_begin(id, s);
+    TimedLaunch(gsdf_timer* timer, int kernel_id, hipStream_t stream)
+        : t(timer), id(kernel_id), s(stream), on(timer && timing_on(timer, kernel_id)) {
+        if (on) timing_begin(t, id, s);
     }
     ~TimedLaunch() {
-        if (on) timing_end(id, s);
+        if (on) timing_end(t, id, s);
     }
 };
 

@@ -4,6 +4,7 @@
 
 #include <climits>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "gsdf_alloc.hpp"
@@ -13,21 +14,22 @@
 namespace gsdf {
 
 // ---------------------------------------------------------------------------
-// Kernel timer: HIP events recorded around launches while enabled.
+// Kernel timer: HIP events recorded around the launches of the kernel ids
+// selected in a caller-owned gsdf_timer (attached to a map).
 // ---------------------------------------------------------------------------
-namespace {
-struct TimerState {
+}  // namespace gsdf
+
+struct gsdf_timer {
     std::mutex mu;
     uint32_t mask = 0;  // bit k: time kernel id k
     std::vector<std::pair<hipEvent_t, hipEvent_t>> done[GSDF_K_COUNT];
     hipEvent_t open[GSDF_K_COUNT] = {};
     std::vector<hipEvent_t> pool;
 };
-TimerState& timer() {
-    static TimerState t;
-    return t;
-}
-hipEvent_t take_event(TimerState& t) {
+
+namespace gsdf {
+namespace {
+hipEvent_t take_event(gsdf_timer& t) {
     if (!t.pool.empty()) {
         hipEvent_t e = t.pool.back();
         t.pool.pop_back();
@@ -37,25 +39,38 @@ hipEvent_t take_event(TimerState& t) {
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
 }
+
+// Return every recorded event to the pool and clear the totals.
+void recycle(gsdf_timer& t) {
+    for (int k = 0; k < GSDF_K_COUNT; ++k) {
+        for (auto& p : t.done[k]) {
+            t.pool.push_back(p.first);
+            t.pool.push_back(p.second);
+        }
+        t.done[k].clear();
+        if (t.open[k]) {
+            t.pool.push_back(t.open[k]);
+            t.open[k] = nullptr;
+        }
+    }
+}
 }  // namespace
 
-bool timing_on(int id) { return (timer().mask >> id) & 1u; }
+bool timing_on(gsdf_timer* t, int id) { return (t->mask >> id) & 1u; }
 
-void timing_begin(int id, hipStream_t s) {
-    TimerState& t = timer();
-    std::lock_guard<std::mutex> g(t.mu);
-    hipEvent_t e = take_event(t);
-    if (e && hipEventRecord(e, s) == hipSuccess) t.open[id] = e;
+void timing_begin(gsdf_timer* t, int id, hipStream_t s) {
+    std::lock_guard<std::mutex> g(t->mu);
+    hipEvent_t e = take_event(*t);
+    if (e && hipEventRecord(e, s) == hipSuccess) t->open[id] = e;
 }
 
-void timing_end(int id, hipStream_t s) {
-    TimerState& t = timer();
-    std::lock_guard<std::mutex> g(t.mu);
-    hipEvent_t b = t.open[id];
-    t.open[id] = nullptr;
+void timing_end(gsdf_timer* t, int id, hipStream_t s) {
+    std::lock_guard<std::mutex> g(t->mu);
+    hipEvent_t b = t->open[id];
+    t->open[id] = nullptr;
     if (!b) return;
-    hipEvent_t e = take_event(t);
-    if (e && hipEventRecord(e, s) == hipSuccess) t.done[id].push_back({b, e});
+    hipEvent_t e = take_event(*t);
+    if (e && hipEventRecord(e, s) == hipSuccess) t->done[id].push_back({b, e});
 }
 
 // ---------------------------------------------------------------------------
@@ -228,7 +243,7 @@ int gsdf_allocate_blocks(gsdf_map* map, const float* depth_dev, const gsdf_camer
     hipStream_t s = (hipStream_t)stream;
     const BandConsts bc = band_consts(*cam, map->desc.voxel_size, map->desc.truncation);
     dim3 grid(ceil_div(cam->width, 16), ceil_div(cam->height, 16));
-    TimedLaunch t(GSDF_K_ALLOCATE, s);
+    TimedLaunch t(map->timer, GSDF_K_ALLOCATE, s);
     k_allocate<<<grid, 256, 0, s>>>(make_view(*map), depth_dev, cam->width, cam->height,
                                       cam->zmin, cam->zmax, bc, T_wc_dev, status_dev);
     return launch_status();
@@ -273,39 +288,47 @@ int gsdf_import_blocks(gsdf_map* map, const int32_t* keys_dev, int32_t n, const 
     return launch_status();
 }
 
-int gsdf_timing_enable(int32_t on) { return gsdf_timing_select(on ? 0xffffffffu : 0u); }
-
-int gsdf_timing_select(uint32_t mask) {
-    TimerState& t = timer();
-    std::lock_guard<std::mutex> g(t.mu);
-    for (int k = 0; k < GSDF_K_COUNT; ++k) {
-        for (auto& p : t.done[k]) {
-            t.pool.push_back(p.first);
-            t.pool.push_back(p.second);
-        }
-        t.done[k].clear();
-        if (t.open[k]) {
-            t.pool.push_back(t.open[k]);
-            t.open[k] = nullptr;
-        }
-    }
-    t.mask = mask;
+int gsdf_timer_create(uint32_t mask, gsdf_timer** out) {
+    if (!out) return GSDF_EINVAL;
+    gsdf_timer* t = new (std::nothrow) gsdf_timer;
+    if (!t) return GSDF_EINVAL;
+    t->mask = mask;
+    *out = t;
     return GSDF_OK;
 }
 
-int gsdf_timing_read(int32_t kernel_id, double* total_ms, int64_t* launches) {
-    if (kernel_id < 0 || kernel_id >= GSDF_K_COUNT || !total_ms || !launches) return GSDF_EINVAL;
-    TimerState& t = timer();
-    std::lock_guard<std::mutex> g(t.mu);
+int gsdf_timer_destroy(gsdf_timer* t) {
+    if (!t) return GSDF_OK;
+    {
+        std::lock_guard<std::mutex> g(t->mu);
+        recycle(*t);
+        for (hipEvent_t e : t->pool) hipEventDestroy(e);
+        t->pool.clear();
+    }
+    delete t;
+    return GSDF_OK;
+}
+
+int gsdf_timer_select(gsdf_timer* t, uint32_t mask) {
+    if (!t) return GSDF_EINVAL;
+    std::lock_guard<std::mutex> g(t->mu);
+    recycle(*t);
+    t->mask = mask;
+    return GSDF_OK;
+}
+
+int gsdf_timer_read(gsdf_timer* t, int32_t kernel_id, double* total_ms, int64_t* launches) {
+    if (!t || kernel_id < 0 || kernel_id >= GSDF_K_COUNT || !total_ms || !launches) return GSDF_EINVAL;
+    std::lock_guard<std::mutex> g(t->mu);
     double sum = 0;
-    for (auto& p : t.done[kernel_id]) {
+    for (auto& p : t->done[kernel_id]) {
         if (hipEventSynchronize(p.second) != hipSuccess) return GSDF_EHIP;
         float ms = 0;
         if (hipEventElapsedTime(&ms, p.first, p.second) != hipSuccess) return GSDF_EHIP;
         sum += ms;
     }
     *total_ms = sum;
-    *launches = (int64_t)t.done[kernel_id].size();
+    *launches = (int64_t)t->done[kernel_id].size();
     return GSDF_OK;
 }
 

@@ -367,7 +367,7 @@ static void photo_launch(int mode, const gsdf_map* map, const float* depth, cons
     if (param_blocks > 0) {
         const MapView M = make_view(*map);
         const float4* P = reinterpret_cast<const float4*>(params);
-        TimedLaunch tl(GSDF_K_PHOTOMETRIC, s);
+        TimedLaunch tl(map->timer, GSDF_K_PHOTOMETRIC, s);
         if (mode == 0)
             k_photometric<0><<<(unsigned)param_blocks, kPhotoBlock, 0, s>>>(
                 M, a, depth, rgb, poses, P, colors, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, partials);

@@ -31,7 +31,8 @@ constexpr int kNE = 30;          // 21 H + 6 b + energy + used + valid
 constexpr int kPartStride = 32;  // doubles per work-group partial
 constexpr int kTrackBlock = 256;
 constexpr int kMaxGroups = 2048;
-constexpr unsigned kSpinLimit = 1u << 24;
+constexpr unsigned kJoinPolls = 1u << 24;   // default bounds of the waits
+constexpr unsigned kTagPolls = 1u << 20;
 
 struct TrackLevel {
     const float* depth;
@@ -47,6 +48,8 @@ struct TrackArgs {
     double inv_vs, vs;
     double damping;
     float min_inlier_frac;
+    unsigned tag_polls;    // bound on the polls of one tagged word
+    unsigned join_polls;   // bound on the polls of the level-boundary pose
 };
 
 // Compensated (Kahan) float32 accumulation: after any number of add()s,
@@ -445,7 +448,6 @@ __device__ inline unsigned long long tag_word(double v, unsigned long long tag) 
     return ((unsigned long long)__double_as_longlong(v) & ~kTagMask) | tag;
 }
 __device__ inline double untag_word(unsigned long long w) { return __longlong_as_double((long long)(w & ~kTagMask)); }
-constexpr unsigned kTagSpinLimit = 1u << 20;
 
 template <bool COMP>
 __device__ inline void store_partial(const float acc[kNE], const float cmp[kNE], double* partial,
@@ -793,7 +795,7 @@ __device__ inline bool reduce_tree(const float acc[kNE], const float cmp[kNE], d
 // another work-group aborted.
 template <bool COMP>
 __device__ inline bool total_leaves(const double* leafpart, int nleaf, unsigned long long tag, const unsigned* sync,
-                                    ReduceLds& r) {
+                                    unsigned max_polls, ReduceLds& r) {
     bool ok = true;
     if (threadIdx.x < kNE * 8) {
         const int k = threadIdx.x >> 3, p = threadIdx.x & 7;
@@ -810,7 +812,7 @@ __device__ inline bool total_leaves(const double* leafpart, int nleaf, unsigned 
                 b1 < nleaf ? __hip_atomic_load(w1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : tag;
             unsigned spins = 0;
             while ((x0 & kTagMask) != tag || (x1 & kTagMask) != tag) {
-                if (++spins > kTagSpinLimit ||
+                if (++spins > max_polls ||
                     ((spins & 255u) == 0u &&
                      __hip_atomic_load(&sync[kSyncAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
                     ok = false;
@@ -853,12 +855,14 @@ __device__ inline bool total_leaves(const double* leafpart, int nleaf, unsigned 
 // thread of a leaf's first work-group) on timeout or abort.
 template <bool COMP>
 __device__ inline bool contribute(const float acc[kNE], const float cmp[kNE], double* part, double* leafpart,
-                                  int groups, const unsigned* sync, ReduceLds& r, unsigned long long tag) {
+                                  int groups, const unsigned* sync, unsigned max_polls, ReduceLds& r,
+                                  unsigned long long tag) {
     store_partial<COMP>(acc, cmp, part + (size_t)blockIdx.x * kPartStride, r, tag);
     if (blockIdx.x % kLeaf != 0) return true;
     const int leaf = blockIdx.x / kLeaf;
     const int leaf_size = min(kLeaf, groups - leaf * kLeaf);
-    if (!total_leaves<COMP>(part + (size_t)leaf * kLeaf * kPartStride, leaf_size, tag, sync, r)) return false;
+    if (!total_leaves<COMP>(part + (size_t)leaf * kLeaf * kPartStride, leaf_size, tag, sync, max_polls, r))
+        return false;
     // r.tot holds the leaf sum in every thread; lanes of wave 0 store it
     if (threadIdx.x < kNE)
         __hip_atomic_store(reinterpret_cast<unsigned long long*>(&leafpart[(size_t)leaf * kPartStride + threadIdx.x]),
@@ -869,10 +873,10 @@ __device__ inline bool contribute(const float acc[kNE], const float cmp[kNE], do
 // Wait (thread 0 only) until the sync word `word` reaches `target`;
 // device-scope polling with a short sleep.  Returns false on timeout or when
 // another work-group aborted.
-__device__ inline bool wait_done(unsigned* sync, int word, unsigned target) {
+__device__ inline bool wait_done(unsigned* sync, int word, unsigned target, unsigned max_polls) {
     unsigned spins = 0;
     while (__hip_atomic_load(&sync[word], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        if (++spins > kSpinLimit ||
+        if (++spins > max_polls ||
             __hip_atomic_load(&sync[kSyncAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             return false;
         __builtin_amdgcn_s_sleep(2);
@@ -942,6 +946,13 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
     // after the last iteration, which needs all of those contributions
     if (threadIdx.x < 12) s_pose[threadIdx.x] = pose_in[threadIdx.x];
     __syncthreads();
+    if (!pose_finite(s_pose)) {
+        // every work-group reads the same pose and leaves here: no iteration
+        // runs, the estimate is the initial pose and the call reports it
+        if (blockIdx.x == 0 && threadIdx.x < 12) pose_out[threadIdx.x] = s_pose[threadIdx.x];
+        if (blockIdx.x == 0 && threadIdx.x == 0) raise_status(status, GSDF_EINVAL);
+        return;
+    }
     int gi = 0;           // global iteration index
     int have = 0;         // iterations the pose in s_pose reflects
     for (int l = a.levels - 1; l >= 0; --l) {
@@ -956,7 +967,7 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
         }
         if (have < gi) {
             // joining: take the pose published at the end of the previous level
-            if (threadIdx.x == 0) s_ok = wait_done(sync, kSyncPub, (unsigned)gi) ? 1 : 0;
+            if (threadIdx.x == 0) s_ok = wait_done(sync, kSyncPub, (unsigned)gi, a.join_polls) ? 1 : 0;
             __syncthreads();
             if (!s_ok) {
                 if (threadIdx.x == 0) {
@@ -998,8 +1009,8 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
                 accumulate<STORAGE>(M, L, a, P, first, kTrackBlock, c1, s_depth, acc, cmp);
             const unsigned long long tag = (unsigned long long)(gi + 1);
             // every member: the same sum of the leaf sums, the same solve
-            if (!contribute<COMP>(acc, cmp, part, leafpart, Gl, sync, red, tag) ||
-                !total_leaves<COMP>(leafpart, nleaf, tag, sync, red)) {
+            if (!contribute<COMP>(acc, cmp, part, leafpart, Gl, sync, a.tag_polls, red, tag) ||
+                !total_leaves<COMP>(leafpart, nleaf, tag, sync, a.tag_polls, red)) {
                 if (threadIdx.x == 0) {
                     __hip_atomic_store(&sync[kSyncAbort], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     raise_status(status, GSDF_EHIP);
@@ -1174,52 +1185,46 @@ inline int normal_eq_groups(int npx) {
     return g < 1 ? 1 : (g > kMaxGroups ? kMaxGroups : g);
 }
 
-// Work-group count of the tracking kernel (cached per device): one per CU.
-// The work-groups wait for each other, so all of them must be resident at
-// once.  The occupancy query confirms that a CU holds at least one; the
-// grid then fits the device with room to spare.  The kernel is launched
-// like any other on the stream (a cooperative launch costs about 15 us more
-// per frame in dispatch, measured on MI355X): on a device that other work
-// keeps partly busy the last work-groups start late, and every wait is
-// bounded, so the worst case is a frame that fails with GSDF_EHIP.
-template <int STORAGE, int MODEL>
-int track_groups() {
-    static int cached[64] = {0};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-    if (cached[dev] > 0) return cached[dev];
-    int cus = 0, per_cu = 0;
+// Work-group count of the tracking kernel: one per CU of the current
+// device (queried on every call; the runtime answers from its own device
+// table).  The work-groups wait for each other, so all of them must be
+// resident at once.  A work-group needs 256 threads (one wave per SIMD) and
+// less LDS than a CU holds (checked below at compile time), so an idle CU
+// always takes one.  The kernel is launched like any other on the stream (a
+// cooperative launch costs about 15 us more per frame in dispatch, measured
+// on MI355X): on a device that other work keeps partly busy the last
+// work-groups start late, and every wait is bounded, so the worst case is a
+// frame that fails with GSDF_EHIP.
+constexpr size_t kTrackLds = sizeof(ReduceLds) + sizeof(float) * kTrackBatch * kTrackBlock + 16 * sizeof(double);
+static_assert(kTrackLds <= 64 * 1024, "the tracking work-group must fit one CU's LDS");
+inline int track_groups() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_track_frame<STORAGE, MODEL>, kTrackBlock, 0) !=
-        hipSuccess)
-        return 0;
-    // one work-group per CU: measured faster than two at 640x480 (the
-    // per-iteration reduction cost grows with the group count)
-    int g = per_cu > 0 ? cus : 0;
-    if (g > kMaxGroups) g = kMaxGroups;
-    cached[dev] = g;
-    return g;
+    return cus < kMaxGroups ? cus : kMaxGroups;
 }
 
 template <int STORAGE, int MODEL>
-int launch_track_frame(hipStream_t s, const MapView& M, const TrackArgs& a, const double* pose_in,
-                       double* pose_out, double* partials, unsigned* sync, float* stats, int32_t* status) {
-    const int g = track_groups<STORAGE, MODEL>();
+int launch_track_frame(gsdf_timer* timer, hipStream_t s, const MapView& M, const TrackArgs& a,
+                       const double* pose_in, double* pose_out, double* partials, unsigned* sync, float* stats,
+                       int32_t* status) {
+    const int g = track_groups();
     if (g <= 0) return GSDF_EHIP;
-    TimedLaunch tl(GSDF_K_TRACK, s);
+    TimedLaunch tl(timer, GSDF_K_TRACK, s);
     k_track_frame<STORAGE, MODEL><<<g, kTrackBlock, 0, s>>>(M, a, pose_in, pose_out, partials, sync, stats,
                                                             status);
     return GSDF_OK;
 }
 
 template <int STORAGE>
-int launch_track_model(int model, hipStream_t s, const MapView& M, const TrackArgs& a, const double* pose_in,
-                       double* pose_out, double* partials, unsigned* sync, float* stats, int32_t* status) {
+int launch_track_model(int model, gsdf_timer* timer, hipStream_t s, const MapView& M, const TrackArgs& a,
+                       const double* pose_in, double* pose_out, double* partials, unsigned* sync, float* stats,
+                       int32_t* status) {
     if (model == GSDF_MODEL_TRILINEAR)
-        return launch_track_frame<STORAGE, GSDF_MODEL_TRILINEAR>(s, M, a, pose_in, pose_out, partials, sync,
-                                                                stats, status);
-    return launch_track_frame<STORAGE, GSDF_MODEL_TAYLOR>(s, M, a, pose_in, pose_out, partials, sync, stats,
-                                                         status);
+        return launch_track_frame<STORAGE, GSDF_MODEL_TRILINEAR>(timer, s, M, a, pose_in, pose_out, partials,
+                                                                sync, stats, status);
+    return launch_track_frame<STORAGE, GSDF_MODEL_TAYLOR>(timer, s, M, a, pose_in, pose_out, partials, sync,
+                                                         stats, status);
 }
 
 inline void fill_levels(const gsdf_camera& cam, const float* depth, const ScratchLayout& sl, char* base,
@@ -1256,10 +1261,12 @@ extern "C" size_t gsdf_track_scratch_bytes(const gsdf_camera* cam, int32_t level
     return scratch_layout(*cam, levels).total;
 }
 
-extern "C" int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, const gsdf_camera* cam,
-                                const gsdf_track_params* params, const double* T_init_dev, double* T_wc_out_dev,
-                                float* stats_dev, void* scratch_dev, size_t scratch_bytes,
-                                int32_t* status_dev, void* stream) {
+namespace gsdf {
+
+// gsdf_track_frame on a given scratch buffer.
+int track_frame_on(const gsdf_map* map, const float* depth_dev, const gsdf_camera* cam,
+                   const gsdf_track_params* params, const double* T_init_dev, double* T_wc_out_dev, float* stats_dev,
+                   void* scratch_dev, size_t scratch_bytes, int32_t* status_dev, void* stream) {
     if (!valid_map(map) || !depth_dev || !valid_cam(cam) || !params || !T_init_dev || !T_wc_out_dev ||
         !scratch_dev)
         return GSDF_EINVAL;
@@ -1268,6 +1275,7 @@ extern "C" int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, con
     for (int l = 0; l < levels; ++l)
         if (params->iters[l] < 0 || params->iters[l] > 1000) return GSDF_EINVAL;
     if (params->model != GSDF_MODEL_TAYLOR && params->model != GSDF_MODEL_TRILINEAR) return GSDF_EINVAL;
+    if (params->max_polls < 0) return GSDF_EINVAL;
     if ((cam->width >> (levels - 1)) < 1 || (cam->height >> (levels - 1)) < 1) return GSDF_EINVAL;
     const ScratchLayout sl = scratch_layout(*cam, levels);
     if (scratch_bytes < sl.total) return GSDF_EINVAL;
@@ -1287,6 +1295,8 @@ extern "C" int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, con
     a.vs = map->desc.voxel_size;
     a.damping = params->damping;
     a.min_inlier_frac = params->min_inlier_frac;
+    a.tag_polls = params->max_polls > 0 ? (unsigned)params->max_polls : kTagPolls;
+    a.join_polls = params->max_polls > 0 ? (unsigned)params->max_polls : kJoinPolls;
 
     {
         PyramidArgs p;
@@ -1304,7 +1314,7 @@ extern "C" int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, con
         for (int q = 0; q < 2; ++q)
             p.sets[q] = reinterpret_cast<unsigned long long*>(partials + (size_t)q * kPartsPerSet);
         p.part_words = kMaxGroups * kPartStride;
-        TimedLaunch tp(GSDF_K_PYRAMID, s);
+        TimedLaunch tp(map->timer, GSDF_K_PYRAMID, s);
         // a single level has no pyramid work: enough work-groups for the clearing
         dim3 grd(levels > 1 ? ceil_div(a.lv[1].W, 16) : 32, levels > 1 ? ceil_div(a.lv[1].H, 16) : 1);
         k_pyramid<<<grd, 256, 0, s>>>(p);
@@ -1312,12 +1322,22 @@ extern "C" int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, con
     const MapView M = make_view(*map);
     int rc;
     switch (map->desc.storage) {
-        case GSDF_FP32: rc = launch_track_model<GSDF_FP32>(params->model, s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
-        case GSDF_BF16: rc = launch_track_model<GSDF_BF16>(params->model, s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
-        default: rc = launch_track_model<GSDF_FP16>(params->model, s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
+        case GSDF_FP32: rc = launch_track_model<GSDF_FP32>(params->model, map->timer, s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
+        case GSDF_BF16: rc = launch_track_model<GSDF_BF16>(params->model, map->timer, s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
+        default: rc = launch_track_model<GSDF_FP16>(params->model, map->timer, s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
     }
     if (rc != GSDF_OK) return rc;
     return launch_status();
+}
+
+}  // namespace gsdf
+
+extern "C" int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, const gsdf_camera* cam,
+                                const gsdf_track_params* params, const double* T_init_dev, double* T_wc_out_dev,
+                                float* stats_dev, void* scratch_dev, size_t scratch_bytes,
+                                int32_t* status_dev, void* stream) {
+    return track_frame_on(map, depth_dev, cam, params, T_init_dev, T_wc_out_dev, stats_dev, scratch_dev,
+                          scratch_bytes, status_dev, stream);
 }
 
 extern "C" int gsdf_normal_equations(const gsdf_map* map, const float* depth_dev,
@@ -1342,6 +1362,8 @@ extern "C" int gsdf_normal_equations(const gsdf_map* map, const float* depth_dev
     a.vs = map->desc.voxel_size;
     a.damping = 0.0;
     a.min_inlier_frac = 0.0f;
+    a.tag_polls = kTagPolls;
+    a.join_polls = kJoinPolls;
     PyramidArgs p = {};
     p.levels = 1;
     p.sync = sync;

@@ -76,7 +76,38 @@ class GsdfMap:
         self.storage = storage
         self.status = torch.zeros(1, dtype=torch.int32, device=self.device)
         self._scratch = {}
+        self._timer = None
         self.reset()
+
+    def __del__(self):
+        t = getattr(self, "_timer", None)
+        if t is not None and _lib._lib is not None:
+            _lib._lib.gsdf_timer_destroy(t)
+            self._timer = None
+
+    # ---- per-kernel event timing (a gsdf_timer attached to this map) ----
+    def timing(self, mask: int) -> None:
+        """Record events around the launches of the kernel ids whose bits are
+        set in ``mask`` (0: none) and clear the totals."""
+        lib = _lib.load()
+        if self._timer is None:
+            h = C.c_void_p()
+            _lib.check(lib.gsdf_timer_create(int(mask) & 0xffffffff, C.byref(h)), "timer_create")
+            self._timer = h
+            self._map.timer = h
+        else:
+            _lib.check(lib.gsdf_timer_select(self._timer, int(mask) & 0xffffffff), "timer_select")
+
+    def timing_read(self, kernel_id: int):
+        """(total ms, launches) recorded for one kernel id since the last
+        ``timing`` call; synchronises the recorded events."""
+        if self._timer is None:
+            return 0.0, 0
+        tot = C.c_double()
+        n = C.c_int64()
+        _lib.check(_lib.load().gsdf_timer_read(self._timer, int(kernel_id), C.byref(tot), C.byref(n)),
+                   "timer_read")
+        return tot.value, n.value
 
     # ---- buffers ----
     @property
@@ -149,12 +180,13 @@ class GsdfMap:
     def track(self, depth: torch.Tensor, cam, pose: torch.Tensor, levels: int = 3,
               iters: Sequence[int] = (4, 5, 10), delta: float = 0.01, damping: float = 1e-6,
               min_inlier_frac: float = 0.1, stats: Optional[torch.Tensor] = None,
-              init: Optional[torch.Tensor] = None, model: str = "taylor") -> None:
+              init: Optional[torch.Tensor] = None, model: str = "taylor", max_polls: int = 0) -> None:
         """Coarse-to-fine tracking; ``pose`` (3x4 float64, device) receives
         the estimate, starting from ``init`` (default: ``pose`` itself, updated
         in place).  ``iters[l]`` iterations at level l (0 = finest).  ``model``:
         "taylor" (one voxel, Eq. (14)-(16)) or "trilinear" (eight voxels,
-        Eq. (12)-(13), the comparison model)."""
+        Eq. (12)-(13), the comparison model).  ``max_polls`` bounds each
+        wait between work-groups (0: the library default)."""
         c = camera(cam)
         _need(depth, torch.float32, (c.height, c.width), "depth")
         _need(pose, torch.float64, (3, 4), "pose")
@@ -167,7 +199,7 @@ class GsdfMap:
             if stats.numel() < 2 * sum(it[:levels]):
                 raise ValueError("stats too small")
         p = _lib.TrackParams(int(levels), (C.c_int32 * 4)(*it[:4]), float(delta), float(damping),
-                             float(min_inlier_frac), {"taylor": 0, "trilinear": 1}[model])
+                             float(min_inlier_frac), {"taylor": 0, "trilinear": 1}[model], int(max_polls))
         scratch = self._scratch_for(c, levels)
         _lib.check(_lib.load().gsdf_track_frame(C.byref(self._map), _ptr(depth), C.byref(c),
                                                  C.byref(p), _ptr(init), _ptr(pose), _ptr(stats), _ptr(scratch),
@@ -348,7 +380,7 @@ class KeyframeLoss(torch.autograd.Function):
         dparams = torch.zeros_like(params)
         dxi = torch.empty_like(xi)
         scratch = gmap._keyframe_scratch(c, K)
-        _lib.check(_lib.load().gsdf_keyframe_backward(
+        _lib.check(_lib.load().gsdf_backward(
             C.byref(gmap._map), _ptr(depth), K, C.byref(c), _ptr(T0), _ptr(xi), _ptr(params),
             int(params.shape[0]), float(delta), _ptr(assoc), 1 if freeze else 0, _ptr(gl), _ptr(dparams),
             _ptr(dxi), None, _ptr(scratch), scratch.numel(), _stream()), "keyframe_backward")

@@ -58,33 +58,41 @@ def voxel_coords(keys):
 
 def compare_voxels(gpu, orc, keys, voxel_size, exclude=frozenset(), psi_tol=1e-4, g_tol=1e-5,
                    w_rtol=1e-5, w_atol=1e-4):
-    """Parity of psi (in units of the voxel size), g-direction and W on voxels
-    observed by both sides; returns a report dict.
+    """Parity of psi (in units of the voxel size), g-direction and W; returns
+    a report dict.
 
-    W is checked as |dW| <= w_rtol W + w_atol: the linear weight has slope
-    1/(T - eps) in d, so a voxel whose observations all lie near d = T has a
-    tiny W whose relative error is large while its absolute error (in units of
-    one full-weight observation) stays ~1e-7 per observation."""
+    psi and g are compared on voxels observed by both sides.  W is compared
+    on every voxel observed by either side, as |dW| <= w_rtol W + w_atol:
+    W is a sum of observation weights, and the linear weight has slope
+    1/(T - eps) in d, so each observation's weight carries an absolute error
+    of that slope times the float32 error of d (about 25/m x 1e-8 m) however
+    small the weight is.  A voxel whose only observations lie within that
+    error of d = T has W ~ 1e-7 and may be observed by one side only; the
+    same bound covers it (its W must stay below w_atol).  Voxels touched by
+    a pixel whose angle test is within rounding of its threshold
+    (``exclude``) are left out and counted."""
     pg, gg, Wg = gpu
     po, go, Wo = orc
-    both = (Wg > 0) & (Wo > 0)
+    either = (Wg > 0) | (Wo > 0)
     if exclude:
         coords = voxel_coords(keys)
-        ex = np.zeros_like(both)
-        for b, j in np.argwhere(both):
+        ex = np.zeros_like(either)
+        for b, j in np.argwhere(either):
             if tuple(coords[b, j]) in exclude:
                 ex[b, j] = True
-        both &= ~ex
+        either &= ~ex
         n_excluded = int(ex.sum())
     else:
         n_excluded = 0
-    one_side = ((Wg > 0) != (Wo > 0)).sum()
+    both = either & (Wg > 0) & (Wo > 0)
+    one = either & ~both
     dpsi = np.abs(pg[both] - po[both]) / voxel_size
     ghg = gg[both] / np.linalg.norm(gg[both], axis=-1, keepdims=True)
     gho = go[both] / np.linalg.norm(go[both], axis=-1, keepdims=True)
     dg = np.linalg.norm(ghg - gho, axis=-1)
-    dW = np.abs(Wg[both] - Wo[both]) / (Wo[both] + w_atol / w_rtol)
-    rep = dict(n=int(both.sum()), excluded=n_excluded, one_side=int(one_side),
+    dW = np.abs(Wg[either] - Wo[either]) / (Wo[either] + w_atol / w_rtol)
+    rep = dict(n=int(both.sum()), excluded=n_excluded, one_side=int(one.sum()),
+               one_side_w_max=float(np.maximum(Wg[one], Wo[one]).max()) if one.any() else 0.0,
                psi_max=float(dpsi.max()), psi_p9999=float(np.quantile(dpsi, 0.9999)),
                g_max=float(dg.max()), w_max=float(dW.max()))
     log("voxel parity", rep)

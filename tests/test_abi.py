@@ -77,7 +77,7 @@ def test_voxel_order_and_differentiable_calls_validate_without_gpu():
     assert lib.gsdf_keyframe_scratch_bytes(C.byref(cam), 0) == 0
     assert lib.gsdf_keyframe_loss(None, None, 1, C.byref(cam), None, None, None, 0, 0.01, None, 0, None,
                                   None, None, 0, None) == _lib.EINVAL
-    assert lib.gsdf_keyframe_backward(None, None, 1, C.byref(cam), None, None, None, 0, 0.01, None, 0, None,
+    assert lib.gsdf_backward(None, None, 1, C.byref(cam), None, None, None, 0, 0.01, None, 0, None,
                                       None, None, None, None, 0, None) == _lib.EINVAL
     assert lib.gsdf_compose_poses(-1, None, None, None, None) == _lib.EINVAL
     assert lib.gsdf_compose_poses(0, None, None, None, None) == _lib.OK

@@ -94,21 +94,24 @@ def test_fusion_matches_emulated_storage(torch_mod, room_stream, storage):
         G.integrate(D, cam, P)
         torch.cuda.synchronize()
         (pg, gg, Wg), (po, go, Wo), keys = align_voxels(G, O)
-        both = (Wg > 0) & (Wo > 0)
+        either = (Wg > 0) | (Wo > 0)
         if exclude:
             c = 8 * keys[:, None, :] + loc[None]
-            for b, j in np.argwhere(both):
+            for b, j in np.argwhere(either):
                 if tuple(c[b, j]) in exclude:
-                    both[b, j] = False
-        assert ((Wg > 0) != (Wo > 0)).sum() <= len(exclude)
+                    either[b, j] = False
+        both = either & (Wg > 0) & (Wo > 0)
+        one = either & ~both
         x_g, x_o = pg[both] / T, po[both] / T
         wterm = 2e-4 / Wo[both]
         dpsi = np.abs(x_g - x_o) / (_ulp_bound(x_g, x_o, storage) + 2e-5 + wterm)
         dg = np.abs(gg[both] - go[both]) / (_ulp_bound(gg[both], go[both], storage) + 1e-5
                                            + wterm[:, None])
-        dW = np.abs(Wg[both] - Wo[both]) / (Wo[both] + 10.0)
+        # W on every voxel either side observed (a voxel seen only within
+        # rounding of d = T has a tiny W on one side and none on the other)
+        dW = np.abs(Wg[either] - Wo[either]) / (Wo[either] + 10.0)
         q = lambda x: torch.tensor(x, dtype=torch.float32).to(DTYPES[storage]).float().numpy()
-        rep = dict(n=int(both.sum()), excluded=len(exclude), psi_rel_bar=float(dpsi.max()),
+        rep = dict(n=int(both.sum()), excluded=len(exclude), one_side=int(one.sum()), psi_rel_bar=float(dpsi.max()),
                    g_rel_bar=float(dg.max()), psi_frac_differ=float(np.mean(q(x_g) != q(x_o))),
                    g_frac_differ=float(np.mean(gg[both] != go[both])), w_rel=float(dW.max()))
         log("precision fusion parity", storage, rep)
@@ -189,8 +192,10 @@ def test_hd_error_against_fp64_oracle_and_fp32_path(torch_mod):
         both = (Wg > 0) & (Wo > 0) & (np.abs(po) < T)
         e = np.abs(pg[both] - po[both])
         e32 = np.abs(pg[both] - maps["fp32"][0][0][both])
+        one = (Wg > 0) != (Wo > 0)
         report[storage] = dict(psi_max_vs_oracle=float(e.max() / vs), psi_rms_vs_oracle=float(
-            np.sqrt(np.mean(e ** 2)) / vs), psi_max_vs_fp32=float(e32.max() / vs))
+            np.sqrt(np.mean(e ** 2)) / vs), psi_max_vs_fp32=float(e32.max() / vs), one_side=int(one.sum()),
+            one_side_w_max=float(np.maximum(Wg[one], Wo[one]).max()) if one.any() else 0.0)
     # pose: the tracked loop of each form against the FP64 oracle's loop
     _, To = oracle.track_stream(st.depth, cam, st.poses, vs, T)
     from paper_2111_13652_amd.gsdf import run_stream
@@ -206,6 +211,10 @@ def test_hd_error_against_fp64_oracle_and_fp32_path(torch_mod):
         report[storage].update(pose_vs_oracle=d_or, pose_vs_fp32=d_32, pose_vs_truth=d_gt)
     for k, v in report.items():
         log("HD error", k, v)
+    # a voxel observed by one side only was seen within rounding of d = T:
+    # its weight stays below the absolute W bound of the parity contract
+    for storage in ("fp32", "bf16", "fp16"):
+        assert report[storage]["one_side_w_max"] <= 1e-4, (storage, report[storage])
     # FP32 storage is the plain path: oracle tolerances
     assert report["fp32"]["psi_max_vs_oracle"] <= 1e-4
     assert max(report["fp32"]["pose_vs_oracle"]) < 1e-5
