@@ -220,6 +220,21 @@ int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, const gsdf_cam
                      const gsdf_track_params* params, const double* T_init_dev, double* T_wc_out_dev,
                      float* stats_dev, void* scratch_dev, size_t scratch_bytes, int32_t* status_dev, void* stream);
 
+/* gsdf_track_frame without a scratch argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Its scratch is a fixed array
+ * of gsdf_track_noalloc_max_bytes() bytes in the library's device memory,
+ * one per GPU, held until the process ends; a camera whose
+ * gsdf_track_scratch_bytes(cam, levels) exceeds it is rejected with
+ * GSDF_EINVAL.  Every call on one GPU shares that GPU's array (the call
+ * clears what it needs first), so calls that may overlap in time on one
+ * GPU (on different streams) race and must not be issued.  Other arguments,
+ * results and status as for gsdf_track_frame. */
+size_t gsdf_track_noalloc_max_bytes(void);
+int gsdf_track_frame_noalloc(const gsdf_map* map, const float* depth_dev, const gsdf_camera* cam,
+                             const gsdf_track_params* params, const double* T_init_dev, double* T_wc_out_dev,
+                             float* stats_dev, int32_t* status_dev, void* stream);
+
 /* One linearisation of the tracking energy at T_wc_dev on the full-resolution
  * image (Eq. (5), (14)-(16)): out29_dev (device, 29 float64) = the 21 upper-
  * triangular entries of H = sum w J J^T (row-major), the 6 of b = sum w J r,

@@ -64,6 +64,9 @@ _SIGNATURES = {
     "gsdf_track_scratch_bytes": (_SZ, [C.POINTER(Camera), _I32]),
     "gsdf_track_frame": (_I, [C.POINTER(Map), _P, C.POINTER(Camera), C.POINTER(TrackParams), _P, _P, _P, _P,
                               _SZ, _P, _P]),
+    "gsdf_track_noalloc_max_bytes": (_SZ, []),
+    "gsdf_track_frame_noalloc": (_I, [C.POINTER(Map), _P, C.POINTER(Camera), C.POINTER(TrackParams), _P, _P, _P,
+                                      _P, _P]),
     "gsdf_normal_equations": (_I, [C.POINTER(Map), _P, C.POINTER(Camera), _P, C.c_float, _P, _P, _SZ, _P]),
     "gsdf_export_keys": (_I, [C.POINTER(Map), _P, _P, _P]),
     "gsdf_export_voxels": (_I, [C.POINTER(Map), _I32, _P, _P, _P, _P]),

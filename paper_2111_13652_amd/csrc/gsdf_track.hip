@@ -21,6 +21,8 @@
 // rank-deficient H (a lone sphere) would amplify through the damping.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "gsdf_common.hpp"
 #include "gsdf_host.hpp"
 #include "gsdf_se3.hpp"
@@ -1263,7 +1265,8 @@ extern "C" size_t gsdf_track_scratch_bytes(const gsdf_camera* cam, int32_t level
 
 namespace gsdf {
 
-// gsdf_track_frame on a given scratch buffer.
+// gsdf_track_frame on a given scratch buffer (the caller's, or the
+// library's fixed array for gsdf_track_frame_noalloc).
 int track_frame_on(const gsdf_map* map, const float* depth_dev, const gsdf_camera* cam,
                    const gsdf_track_params* params, const double* T_init_dev, double* T_wc_out_dev, float* stats_dev,
                    void* scratch_dev, size_t scratch_bytes, int32_t* status_dev, void* stream) {
@@ -1330,6 +1333,31 @@ int track_frame_on(const gsdf_map* map, const float* depth_dev, const gsdf_camer
     return launch_status();
 }
 
+// Scratch of gsdf_track_frame_noalloc: one file-scope device array, which
+// each GPU the library runs on holds until the process ends.  Its host-side
+// name is only a handle for the runtime: kernels receive the device address
+// that hipGetSymbolAddress returns for the current device, looked up once
+// per device and kept.
+constexpr size_t kNoAllocScratch = (size_t)8 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch`, or nullptr.
+void* noalloc_scratch() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace gsdf
 
 extern "C" int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, const gsdf_camera* cam,
@@ -1338,6 +1366,20 @@ extern "C" int gsdf_track_frame(const gsdf_map* map, const float* depth_dev, con
                                 int32_t* status_dev, void* stream) {
     return track_frame_on(map, depth_dev, cam, params, T_init_dev, T_wc_out_dev, stats_dev, scratch_dev,
                           scratch_bytes, status_dev, stream);
+}
+
+extern "C" size_t gsdf_track_noalloc_max_bytes(void) { return kNoAllocScratch; }
+
+extern "C" int gsdf_track_frame_noalloc(const gsdf_map* map, const float* depth_dev, const gsdf_camera* cam,
+                                        const gsdf_track_params* params, const double* T_init_dev,
+                                        double* T_wc_out_dev, float* stats_dev, int32_t* status_dev,
+                                        void* stream) {
+    if (!valid_cam(cam) || !params || params->levels < 1 || params->levels > 4) return GSDF_EINVAL;
+    if (scratch_layout(*cam, params->levels).total > kNoAllocScratch) return GSDF_EINVAL;
+    void* base = noalloc_scratch();
+    if (!base) return GSDF_EHIP;
+    return track_frame_on(map, depth_dev, cam, params, T_init_dev, T_wc_out_dev, stats_dev, base, kNoAllocScratch,
+                          status_dev, stream);
 }
 
 extern "C" int gsdf_normal_equations(const gsdf_map* map, const float* depth_dev,
