@@ -521,21 +521,27 @@ class Stream:
 
 
 def make_stream(cam: Camera, n_frames: int, scene_seed: int = 1, traj_seed: int = 2,
-                noise_seed: Optional[int] = 3, n_objects: int = 20) -> Stream:
+                noise_seed: Optional[int] = 3, n_objects: int = 20,
+                frames: Optional[Sequence[int]] = None) -> Stream:
     """The seeded synthetic room stream (scene, trajectory, per-frame noise).
 
     Per-frame noise uses one child of ``SeedSequence(noise_seed)`` per frame,
-    so any frame can be regenerated on its own.
+    so any frame can be regenerated on its own: ``frames`` renders only
+    those frames of the ``n_frames``-frame stream (the scene keeps its
+    objects away from every camera centre of the whole trajectory, so it
+    depends on ``n_frames``); ``depth`` then holds them in that order and
+    ``poses`` is still the whole trajectory.
     """
     poses = smooth_trajectory(traj_seed, n_frames)
     scene = room_scene(scene_seed, poses[:, :, 3], n_objects=n_objects)
     kids = np.random.SeedSequence(noise_seed).spawn(n_frames) if noise_seed is not None else None
-    depth = np.empty((n_frames, cam.height, cam.width), np.float32)
-    for i in range(n_frames):
+    which = list(range(n_frames)) if frames is None else [int(f) for f in frames]
+    depth = np.empty((len(which), cam.height, cam.width), np.float32)
+    for j, i in enumerate(which):
         z = render_depth(scene, cam, poses[i])
         if kids is not None:
             z = add_depth_noise(z, np.random.Generator(np.random.PCG64(kids[i])))
-        depth[i] = to_depth_image(z, cam)
+        depth[j] = to_depth_image(z, cam)
     return Stream(cam=cam, depth=depth, poses=poses, scene=scene)
 
 

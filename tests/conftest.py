@@ -13,9 +13,11 @@ def pytest_configure(config):
 
 
 def gpu_available() -> bool:
+    # counting devices does not initialise the GPU runtime in this process,
+    # so background processes can still be started after this check
     try:
         import torch
-        return torch.cuda.is_available()
+        return torch.cuda.device_count() > 0
     except Exception:
         return False
 
@@ -27,3 +29,23 @@ def pytest_collection_modifyitems(config, items):
     for item in items:
         if "gpu" in item.keywords:
             item.add_marker(skip)
+
+
+def pytest_collection_finish(session):
+    """Start the background oracle runs of the full-length GPU tests as soon
+    as they are collected on a machine with a GPU, so that they overlap the
+    GPU tests that run before them."""
+    if not any(item.nodeid.startswith("tests/test_gpu_full_length.py") and "gpu" in item.keywords
+               for item in session.items):
+        return
+    if not gpu_available():
+        return
+    from tests import full_length_jobs
+    full_length_jobs.start()
+
+
+def pytest_sessionfinish(session, exitstatus):
+    import sys
+    mod = sys.modules.get("tests.full_length_jobs")
+    if mod is not None:
+        mod.stop()

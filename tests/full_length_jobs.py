@@ -1,0 +1,171 @@
+"""CPU work of the full-length GPU parity tests (tests/test_gpu_full_length.py),
+run in background processes so that the FP64 oracle's long runs overlap the
+GPU tests that precede them.
+
+The jobs start when pytest has collected the full-length tests on a machine
+with a GPU (tests/conftest.py); each test then waits for the results it
+needs.  A job generates its own input frames (the generator is seeded, so
+every process gets the same bytes) and calls only the oracle: nothing here
+touches the GPU or the library under test.
+
+Streams (the sizes of the workloads the method is measured on):
+  room: 100 frames 640x480, 1 cm voxels, T 5 cm (scene 1, trajectory 2,
+        noise 3);
+  hd:   500 frames 1280x720, 5 mm voxels, T 2.5 cm (scene 1, trajectory 5,
+        noise 6); the oracle runs its first 100 frames.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import multiprocessing as mp
+import os
+import time
+
+import numpy as np
+
+ROOM_FRAMES = 100
+HD_FRAMES = 500
+HD_ORACLE_FRAMES = 100
+HD_CHUNK = 50
+HD_SAMPLE_BLOCKS = 4000
+
+_pool = None
+_futures: dict = {}
+
+
+def _log(msg: str) -> None:
+    print(f"[oracle job {os.getpid()}] {msg}", flush=True)
+
+
+def _room(frames=None):
+    from paper_2111_13652_amd import synth
+    return synth.make_stream(synth.CONFIG_ROOM["cam"], ROOM_FRAMES, 1, 2, 3, frames=frames)
+
+
+def _hd(frames=None):
+    from paper_2111_13652_amd import synth
+    return synth.make_stream(synth.CONFIG_ROOM_HD["cam"], HD_FRAMES, 1, 5, 6, frames=frames)
+
+
+# ---------------------------------------------------------------------------
+# jobs (module-level functions, so that spawned processes can run them)
+# ---------------------------------------------------------------------------
+def room_frames_job(lo: int, hi: int):
+    st = _room(range(lo, hi))
+    return st.depth, st.poses
+
+
+def hd_frames_job(lo: int, hi: int):
+    st = _hd(range(lo, hi))
+    return st.depth, st.poses
+
+
+def room_ground_truth_job():
+    """Every frame allocated and fused at its true pose.  Returns the final
+    sorted keys, for each key the first frame whose allocation created it,
+    the final voxels (psi, g, W; voxel order lx + 8 ly + 64 lz), the voxel
+    coordinates touched by pixels whose angle test was within rounding of
+    its threshold, and the number of updates."""
+    import oracle
+    from paper_2111_13652_amd import synth
+    t0 = time.time()
+    st = _room()
+    cfg = synth.CONFIG_ROOM
+    O = oracle.OracleMap(cfg["voxel_size"], cfg["truncation"])
+    seen: dict = {}
+    marginal = set()
+    updates = 0
+    for f in range(ROOM_FRAMES):
+        O.allocate(st.depth[f], st.cam, st.poses[f])
+        for k in map(tuple, O.keys()):
+            if k not in seen:
+                seen[k] = f
+        n, marg = O.integrate(st.depth[f], st.cam, st.poses[f], return_marginal=True)
+        updates += n
+        for v, u in np.argwhere(marg):
+            for m in O.band_voxels(st.cam, st.poses[f], int(u), int(v), float(st.depth[f][v, u])):
+                marginal.add(tuple(int(c) for c in m))
+        if f % 20 == 19:
+            _log(f"room ground truth: frame {f} ({time.time() - t0:.0f} s)")
+    keys = O.keys()
+    first = np.array([seen[tuple(k)] for k in keys], np.int32)
+    psi, g, W, _ = O.voxels(keys)
+    return dict(keys=keys, first=first, psi=psi, g=g, W=W,
+                marginal=np.array(sorted(marginal), np.int32).reshape(-1, 3), updates=updates,
+                seconds=time.time() - t0)
+
+
+def room_closed_loop_job():
+    """The frame loop: frame 0 fused at its true pose, every later frame
+    tracked from the previous estimate and fused at the new one."""
+    import oracle
+    from paper_2111_13652_amd import synth
+    t0 = time.time()
+    st = _room()
+    cfg = synth.CONFIG_ROOM
+    tim: list = []
+    _, est = oracle.track_stream(st.depth, st.cam, st.poses, cfg["voxel_size"], cfg["truncation"], timings=tim)
+    _log(f"room closed loop: {ROOM_FRAMES} frames in {time.time() - t0:.0f} s")
+    return dict(poses=np.asarray(est), seconds=time.time() - t0)
+
+
+def hd_closed_loop_job():
+    """The frame loop on the first frames of the 1280x720 stream, and the
+    voxels of a seeded sample of the final map's blocks."""
+    import oracle
+    from paper_2111_13652_amd import synth
+    t0 = time.time()
+    st = _hd(range(HD_ORACLE_FRAMES))
+    cfg = synth.CONFIG_ROOM_HD
+    M, est = oracle.track_stream(st.depth, st.cam, st.poses, cfg["voxel_size"], cfg["truncation"])
+    keys = M.keys()
+    rng = np.random.default_rng(7)
+    pick = np.sort(rng.choice(len(keys), size=min(HD_SAMPLE_BLOCKS, len(keys)), replace=False))
+    psi, g, W, _ = M.voxels(keys[pick])
+    _log(f"hd closed loop: {HD_ORACLE_FRAMES} frames in {time.time() - t0:.0f} s, {len(keys)} blocks")
+    return dict(poses=np.asarray(est), n_blocks=len(keys), keys=keys[pick], psi=psi, g=g, W=W,
+                seconds=time.time() - t0)
+
+
+# ---------------------------------------------------------------------------
+# scheduling
+# ---------------------------------------------------------------------------
+def start() -> None:
+    """Submit every job (longest first) to a pool of spawned processes."""
+    global _pool
+    if _pool is not None:
+        return
+    workers = max(2, min(8, (os.cpu_count() or 2) - 2))
+    _pool = cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"))
+    _futures["hd_loop"] = _pool.submit(hd_closed_loop_job)
+    _futures["room_loop"] = _pool.submit(room_closed_loop_job)
+    _futures["room_gt"] = _pool.submit(room_ground_truth_job)
+    for lo in range(0, ROOM_FRAMES, 25):
+        _futures[f"room_frames_{lo}"] = _pool.submit(room_frames_job, lo, min(lo + 25, ROOM_FRAMES))
+    for lo in range(0, HD_FRAMES, HD_CHUNK):
+        _futures[f"hd_frames_{lo}"] = _pool.submit(hd_frames_job, lo, min(lo + HD_CHUNK, HD_FRAMES))
+
+
+def result(name: str):
+    start()
+    return _futures[name].result()
+
+
+def frames(kind: str):
+    """(depth (F, H, W) float32, poses (F, 3, 4)) of a whole stream."""
+    n, step = (ROOM_FRAMES, 25) if kind == "room" else (HD_FRAMES, HD_CHUNK)
+    parts = [result(f"{kind}_frames_{lo}") for lo in range(0, n, step)]
+    return np.concatenate([p[0] for p in parts]), parts[0][1]
+
+
+def stop() -> None:
+    """End the pool without waiting for jobs nobody will read (a run that
+    stopped early)."""
+    global _pool
+    if _pool is not None:
+        procs = list(getattr(_pool, "_processes", {}).values())
+        _pool.shutdown(wait=False, cancel_futures=True)
+        for p in procs:
+            if p.is_alive():
+                p.terminate()
+        _pool = None

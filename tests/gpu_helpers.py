@@ -50,6 +50,12 @@ def marginal_voxels(orc_map, depth, cam, pose, marginal):
     return out
 
 
+def pack_coords(c):
+    """One int64 per integer (x, y, z) triple (|coordinate| < 2^20)."""
+    c = np.asarray(c, np.int64) + (1 << 20)
+    return (c[..., 0] << 42) | (c[..., 1] << 21) | c[..., 2]
+
+
 def voxel_coords(keys):
     c = np.arange(512)
     loc = np.stack([c % 8, (c // 8) % 8, c // 64], -1)
@@ -74,12 +80,9 @@ def compare_voxels(gpu, orc, keys, voxel_size, exclude=frozenset(), psi_tol=1e-4
     pg, gg, Wg = gpu
     po, go, Wo = orc
     either = (Wg > 0) | (Wo > 0)
-    if exclude:
-        coords = voxel_coords(keys)
-        ex = np.zeros_like(either)
-        for b, j in np.argwhere(either):
-            if tuple(coords[b, j]) in exclude:
-                ex[b, j] = True
+    if len(exclude):
+        ex = np.isin(pack_coords(voxel_coords(keys)), pack_coords(np.array(list(exclude)).reshape(-1, 3)))
+        ex &= either
         either &= ~ex
         n_excluded = int(ex.sum())
     else:
