@@ -1,28 +1,36 @@
 """Throughput of the Gradient-SDF tracking + fusion loop on one MI355X.
 
 Workload: the seeded synthetic room stream at 640x480 (fx = fy = 525,
-cx = 319.5, cy = 239.5), 1 cm voxels, 5 cm truncation, 8^3 blocks,
-3-level pyramid with 4/5/10 Gauss-Newton iterations (finest first), Huber
-delta 1 cm.  Depth noise sigma(z) = 0.0012 + 0.0019 (z - 0.4)^2, range
+cx = 319.5, cy = 239.5), 100 frames, 1 cm voxels, 5 cm truncation, 8^3
+blocks, 3-level pyramid with 4/5/10 Gauss-Newton iterations (finest first),
+Huber delta 1 cm.  Depth noise sigma(z) = 0.0012 + 0.0019 (z - 0.4)^2, range
 0.4-4 m.  One step = one frame: track it against the map, then allocate and
-integrate it at the estimated pose (gsdf_track_frame, gsdf_fuse_frame).  Frame 0 is fused at its ground-truth
-pose before the warm-up.  All depth frames are resident in HBM before the
+integrate it at the estimated pose (gsdf_track_frame, gsdf_fuse_frame).
+Frame 0 is fused at its ground-truth pose, frames 1..W are the warm-up and
+frames W+1..W+K are timed.  All depth frames are resident in HBM before the
 timed region starts.
 
-Prints one JSON line.  Extra fields: "roofline" (dominant kernel),
-"cpu_baseline" (the FP64 oracle on a bounded sample of the same stream),
-"kernels" (per-kernel event timing), "accuracy".  Inside the timed region
-only the tracking kernel records events (two per frame; its duration feeds
-the roofline); "kernels" comes from a second pass over the same frames with
-every kernel timed, which is not part of "value" (events around every
-launch cost about 9 % of the frame rate).  "comparison" repeats the frames
-with the tri-linear eight-voxel distance of Eq. (12)-(13) in place of the
-Taylor distance (tracking time ratio, frame rate, ATE).
+Prints one JSON line.  Besides the contract's keys:
+  "roofline"      the dominant kernel's algorithmic bytes per launch over its
+                  mean launch time (HIP events recorded inside the library
+                  around that kernel only, on its stream, in the timed region);
+  "cpu_baseline"  the FP64 oracle on a bounded sample of the same stream;
+  "kernels"       per-kernel event times from a second pass over the timed
+                  frames with every kernel timed (not part of "value": events
+                  around every launch cost about 9 % of the frame rate);
+  "full_stream"   three passes over the whole 100-frame stream (median);
+  "differentiation"  forward + adjoint over keyframes 0, 10, ..., 90 on the
+                  100-frame map;
+  "joint_refinement" one step of the joint geometry / colour / pose
+                  refinement over 30 keyframes (bf16 map, colour stream);
+  "comparison"    the paper's baseline system on the same frames: a map
+                  without stored gradients tracked with the tri-linear
+                  eight-voxel distance of Eq. (12)-(13), against the
+                  gradient map with the Taylor distance.
 """
 from __future__ import annotations
 
 import argparse
-import ctypes as C
 import json
 import os
 import sys
@@ -36,30 +44,25 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 
-# Algorithmic bytes per unit of work.  Voxel record: float4 + float W = 20 B
-# (fp32 storage) or 4 x 16-bit + float W = 12 B (bf16 / fp16 storage).
-RECORD_BYTES = {"fp32": 20.0, "bf16": 12.0, "fp16": 12.0}
-B_TRACK_PIXEL = 4.0        # depth read, every pixel of a level, every iteration
-B_HASH_ENTRY = 16.0        # hash entry probed per valid tracked pixel
-B_FUSE_PIXEL = 4.0 + 16.0  # depth read + float4 normal write, per pixel (normals kernel)
-B_ALLOC_PIXEL = 4.0        # depth read per pixel
-B_ALLOC_PAIR = 16.0        # hash entry per distinct (tile, block) probe
-
+# Algorithmic bytes per unit of work.
+#  tracking, per valid pixel-iteration: depth 4 + hash entry 16 + the voxel's
+#    {psi, g} (16 B for float32, 8 B for the 16-bit pack); the float32 sum
+#    form also reads W (4 B) to form psi, which the count leaves out;
+#  fusion, per (pixel, voxel) update: read + write of the voxel record
+#    (float4 + W = 20 B; 16-bit pack + W = 12 B; distance + W = 8 B);
+#  allocation + normals, per pixel: depth 4 + {n_w, D} 16 written; plus a hash
+#    entry (16 B) per distinct (16x16 tile, block) probe.
+TRACK_BYTES = {"fp32": 36.0, "bf16": 28.0, "fp16": 28.0, "nograd": 36.0}
+RECORD_BYTES = {"fp32": 20.0, "bf16": 12.0, "fp16": 12.0, "nograd": 8.0}
+B_PIXEL_PREP = 4.0 + 16.0
+B_ALLOC_PAIR = 16.0
 
 # HBM-side bytes per launch from two rocprofv3 --pmc passes (FETCH_SIZE, then
 # WRITE_SIZE) over this workload, each scaled by what the same counter reads
 # for a plain 256 MiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  A
 # figure is reported only while the kernel's sources still hash to the
 # values they had when the counters were taken.
-MEASURED_TRAFFIC = {
-    "track": {"bytes": (4543.5 * 1.9998 + 953.4 * 1.0000) * 1024,
-              "sources": {"gsdf_track.hip": "e48e2b81b767175200e93b78cea03f67eadd0974bc34dc7d9b203319cd2dd9cf",
-                          "gsdf_common.hpp": "b1b85872a85ba22d8f1fb4f97babef87774323fbb1458396f354eee1e14379fa",
-                          "gsdf_se3.hpp": "13c15ea94701e1129da7175cf338be9aa9cc57bf8857172577cef813f6209733"}},
-    "fuse_blocks": {"bytes": (20546.0 * 1.9998 + 11862.1 * 1.0000) * 1024,
-              "sources": {"gsdf_fuse.hip": "4dac1eb1758459638188f0928bfc5d3e8e9076b6052a38f7fa28694f870d664a",
-                          "gsdf_common.hpp": "b1b85872a85ba22d8f1fb4f97babef87774323fbb1458396f354eee1e14379fa"}},
-}
+MEASURED_TRAFFIC = {}
 
 
 def _traffic(kernel: str, storage: str):
@@ -96,9 +99,11 @@ def _parse():
                     help="frames of the stream the oracle runs for the CPU baseline")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--no-h2d", action="store_true", help="skip the PCIe-inclusive pass")
+    ap.add_argument("--no-full", action="store_true", help="skip the three full-stream passes")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation measurement")
+    ap.add_argument("--no-joint", action="store_true", help="skip the joint-refinement step")
     ap.add_argument("--no-comparison", action="store_true",
-                    help="skip the pass with the tri-linear comparison model")
+                    help="skip the pass with the paper's baseline system")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times "
                          "(scale reference for hardware byte counters)")
@@ -107,6 +112,10 @@ def _parse():
     ap.add_argument("--storage", choices=("fp32", "bf16", "fp16"), default="fp32",
                     help="voxel storage: fp32 (plain path) or the 16-bit precision form")
     return ap.parse_args()
+
+
+def _median(x):
+    return float(np.median(np.asarray(x, np.float64)))
 
 
 def main():
@@ -125,8 +134,8 @@ def main():
     cam = cfg["cam"]
     n_frames = max(100, 1 + args.warmup + args.steps)
     t0 = time.time()
-    # the 1280x720 stream uses trajectory 5 and noise 6 (its own seeds)
-    stream = synth.make_stream(cam, n_frames, scene_seed=1, traj_seed=5 if hd else 2, noise_seed=6 if hd else 3)
+    sc, tr, nz = cfg["seeds"]
+    stream = synth.make_stream(cam, n_frames, scene_seed=sc, traj_seed=tr, noise_seed=nz)
     print(f"# generated {n_frames} frames in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
 
     dev = torch.device("cuda:0")
@@ -134,21 +143,41 @@ def main():
     gt = torch.as_tensor(stream.poses).to(dev)                          # (F, 3, 4) float64
     est = torch.zeros_like(gt)
     levels, iters, delta = 3, (4, 5, 10), 0.01
-    m = GsdfMap(cfg["voxel_size"], cfg["truncation"], max_blocks=1 << (18 if hd else 16), storage=args.storage)
+    max_blocks = 1 << (18 if hd else 16)
+    m = GsdfMap(cfg["voxel_size"], cfg["truncation"], max_blocks=max_blocks, storage=args.storage)
     s = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
 
-    def step(f, src=None, model="taylor"):
+    def step(M, f, src=None, model="taylor"):
         d = depth[f] if src is None else src
-        m.track(d, cam, est[f], levels=levels, iters=iters, delta=delta, init=est[f - 1], model=model)
-        m.fuse(d, cam, est[f])
+        M.track(d, cam, est[f], levels=levels, iters=iters, delta=delta, init=est[f - 1], model=model)
+        M.fuse(d, cam, est[f])
 
-    def start():
-        m.reset()
+    def start(M, warm=args.warmup, model="taylor"):
+        M.reset()
         est[0].copy_(gt[0])
-        m.fuse(depth[0], cam, est[0])
-        for f in range(1, 1 + args.warmup):
-            step(f)
+        M.fuse(depth[0], cam, est[0])
+        for f in range(1, 1 + warm):
+            step(M, f, model=model)
         torch.cuda.synchronize()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        ev0.record(s)
+        fn()
+        ev1.record(s)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1)
+
+    def read_kernels(M):
+        out = {}
+        for name, kid in (("track", _lib.K_TRACK), ("fuse_blocks", _lib.K_INTEGRATE),
+                          ("alloc_normals", _lib.K_ALLOC_NORMALS), ("pyramid", _lib.K_PYRAMID)):
+            tot, n = M.timing_read(kid)
+            if n:
+                out[name] = {"total_ms": tot, "launches": n, "avg_us": 1e3 * tot / max(1, n)}
+        return out
 
     if args.copy_mib > 0:
         n = args.copy_mib << 18
@@ -160,62 +189,43 @@ def main():
         print(f"# copy reference: 3 x {args.copy_mib} MiB read + written", file=sys.stderr, flush=True)
         del src, dst
 
-    start()
-    lib = _lib.load()
+    # ---- the timed region: frames first .. first + K - 1
+    start(m)
     timing = not args.no_timing
     if timing:
         # inside the timed region only the roofline kernel (tracking) records
         # events (two per frame); the per-kernel breakdown is a second pass
         m.timing(1 << _lib.K_TRACK)
     first = 1 + args.warmup
+    K = args.steps
     c0 = m.counters()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(s)
-    for f in range(first, first + args.steps):
-        step(f)
-    ev1.record(s)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    fps = args.steps / (ms / 1e3)
-    c1 = m.counters()
-    work = (c1 - c0).astype(np.float64)
+    ms = timed(lambda: [step(m, f) for f in range(first, first + K)])
+    fps = K / (ms / 1e3)
+    work = (m.counters() - c0).astype(np.float64)
     status = m.status_flags()
+    E = est[: first + K].cpu().numpy()
+    G = stream.poses[: first + K]
+    ate = float(np.sqrt(np.mean(np.sum((E[:, :, 3] - G[:, :, 3]) ** 2, axis=1))))
+    print(f"# timed {K} frames: {fps:.1f} frames/s", file=sys.stderr, flush=True)
 
-    def read_kernels():
-        out = {}
-        for name, kid in (("track", _lib.K_TRACK), ("fuse_blocks", _lib.K_INTEGRATE),
-                          ("alloc_normals", _lib.K_ALLOC_NORMALS), ("pyramid", _lib.K_PYRAMID)):
-            tot, n = m.timing_read(kid)
-            if n:
-                out[name] = {"total_ms": tot, "launches": n, "avg_us": 1e3 * tot / max(1, n)}
-        return out
-
-    kernels = {}
-    track_live = None
+    kernels, track_live = {}, None
     if timing:
-        track_live = read_kernels().get("track")
+        track_live = read_kernels(m).get("track")
         # breakdown pass: the same frames again with every kernel timed
-        start()
+        start(m)
         m.timing(0xffffffff)
-        for f in range(first, first + args.steps):
-            step(f)
+        for f in range(first, first + K):
+            step(m, f)
         torch.cuda.synchronize()
-        kernels = read_kernels()
+        kernels = read_kernels(m)
         m.timing(0)
 
     # ---- algorithmic bytes, from the live work counters
-    K = args.steps
     npx = cam.width * cam.height
-    lvl_px = sum((cam.width >> l) * (cam.height >> l) * iters[l] for l in range(levels))
-    rec = RECORD_BYTES[args.storage]
-    track_bytes = B_TRACK_PIXEL * lvl_px * K + (B_HASH_ENTRY + rec) * work[5]
-    fuse_bytes = 2.0 * rec * work[0]
-    normals_bytes = B_FUSE_PIXEL * npx * K
-    alloc_bytes = B_ALLOC_PIXEL * npx * K + B_ALLOC_PAIR * work[4]
-    per_kernel_bytes = {"track": track_bytes, "fuse_blocks": fuse_bytes, "alloc_normals": alloc_bytes + normals_bytes}
-    total_bytes = track_bytes + fuse_bytes + normals_bytes + alloc_bytes
+    per_kernel_bytes = {"track": TRACK_BYTES[args.storage] * work[5],
+                        "fuse_blocks": 2.0 * RECORD_BYTES[args.storage] * work[0],
+                        "alloc_normals": B_PIXEL_PREP * npx * K + B_ALLOC_PAIR * work[4]}
+    total_bytes = sum(per_kernel_bytes.values())
     eff_gbs = total_bytes / (ms / 1e3) / 1e9
 
     roofline = None
@@ -232,18 +242,29 @@ def main():
                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": _traffic(dom, args.storage),
                     "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6}
 
-    # accuracy alongside throughput: ATE of the estimated trajectory
-    E = est[: first + K].cpu().numpy()
-    G = stream.poses[: first + K]
-    ate = float(np.sqrt(np.mean(np.sum((E[:, :, 3] - G[:, :, 3]) ** 2, axis=1))))
+    # ---- three passes over the whole stream: frame 0 fused at its true pose,
+    # frames 1 .. F-1 tracked and fused; the map of the last pass stays
+    full = None
+    if not args.no_full:
+        F = depth.shape[0]
+        rates = []
+        for _ in range(3):
+            start(m, warm=0)
+            rates.append((F - 1) / (timed(lambda: [step(m, f) for f in range(1, F)]) / 1e3))
+        Ef = est.cpu().numpy()
+        full = {"frames_timed": f"1-{F - 1}", "passes": 3, "frames_per_s_median": _median(rates),
+                "frames_per_s": rates, "blocks": m.num_blocks(), "status": m.status_flags(),
+                "ate_rmse_m": float(np.sqrt(np.mean(np.sum((Ef[:, :, 3] - stream.poses[:, :, 3]) ** 2, axis=1))))}
+        print(f"# full stream: {full['frames_per_s_median']:.1f} frames/s", file=sys.stderr, flush=True)
 
-    # ---- differentiation: keyframe loss + adjoint over 10 keyframes of the
-    # stream (poses perturbed by 1 deg / 1 cm) on the map fused above
+    # ---- differentiation: keyframe loss + adjoint over keyframes 0, 10, ...,
+    # 90 (poses perturbed by 1 deg / 1 cm, seeds 4 + i) on the map of the
+    # 100-frame stream (the last full pass; else the timed frames' map)
     diff = None
     if not args.no_adjoint:
-        from paper_2111_13652_amd.gsdf import KeyframeLoss
-        kf = [first + i * (K // 10) for i in range(10)] if K >= 10 else list(range(first, first + K))
-        T0 = torch.as_tensor(np.stack([synth.perturb_pose(stream.poses[f], 100 + i, 1.0, 0.01)
+        from paper_2111_13652_amd.gsdf import KeyframeLoss, keyframe_loss
+        kf = list(range(0, 100, 10)) if full else list(range(first, first + K, max(1, K // 10)))[:10]
+        T0 = torch.as_tensor(np.stack([synth.perturb_pose(stream.poses[f], 4 + i, 1.0, 0.01)
                                        for i, f in enumerate(kf)])).to(dev)
         D = depth[kf].contiguous()
         params = m.export_params().requires_grad_(True)
@@ -259,48 +280,66 @@ def main():
         reps = 20
         if timing:
             m.timing(0xffffffff)
-        torch.cuda.synchronize()
-        ev0.record(s)
-        for _ in range(reps):
-            fwd_bwd()
-        ev1.record(s)
-        torch.cuda.synchronize()
-        dms = ev0.elapsed_time(ev1) / reps
+        dms = timed(lambda: [fwd_bwd() for _ in range(reps)]) / reps
         dk = {}
         if timing:
             for name, kid in (("loss", _lib.K_LOSS), ("backward", _lib.K_BACKWARD)):
                 tot, n = m.timing_read(kid)
                 dk[name] = {"avg_us": 1e3 * tot / max(1, n), "launches": n}
             m.timing(0)
-        from paper_2111_13652_amd.gsdf import keyframe_loss
         cnt = torch.zeros(len(kf), dtype=torch.float64, device=dev)
         keyframe_loss(m, params.detach(), xi.detach(), D, cam, T0, delta, count=cnt)
         used = float(cnt.sum().item())
         observed = int((m.weight[: m.num_blocks() * 512] > 0).sum().item())
-        diff = {"keyframes": len(kf), "ms_per_forward_backward": dms,
-                "pixels_used": used, "observed_voxels": observed,
+        diff = {"keyframes": kf, "map": "100-frame stream" if full else "timed frames",
+                "ms_per_forward_backward": dms, "pixels_used": used, "observed_voxels": observed,
                 "param_blocks": int(params.shape[0]), "kernels": dk}
         if dk:
             # backward: depth 4 + hash entry 16 + W 4 + params 16 B read, 16 B of
-            # atomic adds per pixel used; 4 B depth per other pixel
+            # gradient added per pixel used; 4 B depth per other pixel
             npx_all = len(kf) * npx
             bb = 4.0 * npx_all + (16 + 4 + 16 + 16) * used
             diff["backward_algorithmic_gbs"] = bb / (dk["backward"]["avg_us"] * 1e-6) / 1e9
         del params, xi
+
+    # ---- joint refinement (the colour stream's configuration): one step =
+    # keyframe loss + photometric loss, both adjoints, an Adam step on the
+    # voxel parameters and colours, and one Gauss-Newton iteration of the
+    # tracking kernel per keyframe on the bf16 map
+    joint = None
+    if not args.no_joint and not hd:
+        from paper_2111_13652_amd.gsdf import refine_joint
+        kj = list(range(0, 90, 3))                    # 30 keyframes
+        t0 = time.time()
+        rs = synth.make_rgbd_stream(cam, n_frames, sc, tr, nz, albedo_seed=7, frames=kj)
+        print(f"# colour keyframes in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+        J = GsdfMap(cfg["voxel_size"], cfg["truncation"], max_blocks=max_blocks, storage="bf16")
+        for f in range(n_frames):
+            J.fuse(depth[f], cam, gt[f])
+        Dj = torch.as_tensor(rs.depth).to(dev)
+        Cj = torch.as_tensor(rs.rgb).to(dev)
+        Tj = torch.as_tensor(np.stack([synth.perturb_pose(stream.poses[f], 40 + i, 1.0, 0.01)
+                                       for i, f in enumerate(kj)])).to(dev)
+        refine_joint(J, Dj, Cj, cam, Tj.clone(), steps=2, write_back=False)   # warm-up
+        t1 = timed(lambda: refine_joint(J, Dj, Cj, cam, Tj.clone(), steps=1, write_back=False))
+        t6 = timed(lambda: refine_joint(J, Dj, Cj, cam, Tj.clone(), steps=6, write_back=False))
+        joint = {"keyframes": len(kj), "storage": "bf16", "ms_per_step": (t6 - t1) / 5.0,
+                 "ms_setup_and_first_step": t1,
+                 "observed_voxels": int((J.weight[: J.num_blocks() * 512] > 0).sum().item())}
+        del J, Dj, Cj
 
     # ---- PCIe-inclusive rate: each frame copied from pinned host memory first
     h2d = None
     if not args.no_h2d:
         host = torch.as_tensor(stream.depth[first:first + K]).pin_memory()
         buf = torch.empty_like(depth[0])
-        start()
-        ev0.record(s)
-        for i, f in enumerate(range(first, first + K)):
-            buf.copy_(host[i], non_blocking=True)
-            step(f, buf)
-        ev1.record(s)
-        torch.cuda.synchronize()
-        h2d = K / (ev0.elapsed_time(ev1) / 1e3)
+        start(m)
+
+        def run():
+            for i, f in enumerate(range(first, first + K)):
+                buf.copy_(host[i], non_blocking=True)
+                step(m, f, buf)
+        h2d = K / (timed(run) / 1e3)
 
     # ---- CPU baseline: the FP64 oracle on the first frames of the same stream
     cpu = None
@@ -316,32 +355,37 @@ def main():
                          f"{n_cpu - 1} frames tracked + allocated + fused, single-threaded FP64, "
                          f"{el:.1f} s on one core of {_cpu_model()} ({os.cpu_count()} visible)"}
 
-    # ---- the comparison model (Sec. 4.1 Eq. (12)-(13)): the same frames
-    # tracked with the tri-linear eight-voxel distance instead of the
-    # one-voxel Taylor distance (not part of "value")
+    # ---- the paper's baseline system on the same frames (Sec. 5.3): a map
+    # without stored gradients (Eq. (1)-(2) only) tracked with the
+    # tri-linear distance (Eq. (12)-(13)); not part of "value"
     comparison = None
     if not args.no_comparison:
-        start()
-        m.timing(1 << _lib.K_TRACK)
-        torch.cuda.synchronize()
-        ev0.record(s)
-        for f in range(first, first + args.steps):
-            step(f, model="trilinear")
-        ev1.record(s)
-        torch.cuda.synchronize()
-        ms_tri = ev0.elapsed_time(ev1)
-        tr_tri = read_kernels().get("track")
-        m.timing(0)
-        Et = est[: first + K].cpu().numpy()
+        B = GsdfMap(cfg["voxel_size"], cfg["truncation"], max_blocks=max_blocks, storage="nograd")
+        start(B, model="trilinear")
+        ms_b = timed(lambda: [step(B, f, model="trilinear") for f in range(first, first + K)])
+        Eb = est[: first + K].cpu().numpy()
+        bstat = B.status_flags()
+        bk = {}
+        if timing:
+            start(B, model="trilinear")
+            B.timing(0xffffffff)
+            for f in range(first, first + K):
+                step(B, f, model="trilinear")
+            torch.cuda.synchronize()
+            bk = read_kernels(B)
+            B.timing(0)
         comparison = {
-            "model": "tri-linear distance of the 8 voxels around each point (Eq. 12-13)",
-            "frames_per_s": args.steps / (ms_tri / 1e3),
-            "track_us": tr_tri["avg_us"] if tr_tri else None,
-            "taylor_track_us": track_live["avg_us"] if track_live else None,
-            "track_time_ratio": (tr_tri["avg_us"] / track_live["avg_us"]) if (tr_tri and track_live) else None,
-            "ate_rmse_m": float(np.sqrt(np.mean(np.sum((Et[:, :, 3] - G[:, :, 3]) ** 2, axis=1)))),
-            "status": m.status_flags(),
+            "system": "map without stored gradients, tracked with the tri-linear distance of the 8 voxels "
+                      "around each point (Eq. 12-13)",
+            "frames_per_s": K / (ms_b / 1e3),
+            "kernels": bk,
+            "ate_rmse_m": float(np.sqrt(np.mean(np.sum((Eb[:, :, 3] - G[:, :, 3]) ** 2, axis=1)))),
+            "status": bstat,
         }
+        if bk and kernels:
+            comparison["track_time_ratio"] = bk["track"]["avg_us"] / kernels["track"]["avg_us"]
+            comparison["fusion_gradient_overhead"] = kernels["fuse_blocks"]["avg_us"] / bk["fuse_blocks"]["avg_us"] - 1
+        del B
 
     report = {
         "metric": ("tracked+fused frames/s at 1280x720, 5 mm voxels; % of HBM peak GB/s" if hd else
@@ -361,14 +405,17 @@ def main():
         "config": {"workload": ("room stream 1280x720, 5 mm voxels, T 2.5 cm" if hd else
                                 "room stream 640x480, 1 cm voxels, T 5 cm") + ", 8^3 blocks, 3-level "
                                f"pyramid (4/5/10 GN iterations), {args.storage} voxels",
-                   "frames": n_frames},
+                   "stream_frames": n_frames, "frames_processed": first + K,
+                   "frames_timed": f"{first}-{first + K - 1}", "seeds": list(cfg["seeds"])},
         "hbm_frac": eff_gbs / HBM_PEAK_GBS,
         "effective_gbs": eff_gbs,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fps_with_h2d": h2d,
         "accuracy": {"ate_rmse_m": ate, "status": status},
+        "full_stream": full,
         "differentiation": diff,
+        "joint_refinement": joint,
         "comparison": comparison,
         "work_per_frame": {"fusion_updates": work[0] / K, "fusion_pixel_visits": work[1] / K,
                            "fused_voxels": work[2] / K, "fused_blocks": work[3] / K,

@@ -57,9 +57,14 @@ typedef enum {
 } gsdf_status;
 
 typedef enum {
-    GSDF_FP32 = 0,  /* voxel = float4 {sum w d, g_x, g_y, g_z} (16 B) + W   */
-    GSDF_BF16 = 1,  /* voxel = 4 x bf16 {psi/T, gbar_x, gbar_y, gbar_z} + W */
-    GSDF_FP16 = 2   /* voxel = 4 x fp16 {psi/T, gbar_x, gbar_y, gbar_z} + W */
+    GSDF_FP32 = 0,         /* voxel = float4 {sum w d, g_x, g_y, g_z} (16 B) + W   */
+    GSDF_BF16 = 1,         /* voxel = 4 x bf16 {psi/T, gbar_x, gbar_y, gbar_z} + W */
+    GSDF_FP16 = 2,         /* voxel = 4 x fp16 {psi/T, gbar_x, gbar_y, gbar_z} + W */
+    GSDF_NOGRAD_FP32 = 3   /* voxel = float {sum w d} (4 B) + W: a plain SDF map     */
+                           /* without gradients (Eq. (1)-(2) only), the baseline of  */
+                           /* the paper's runtime comparison (Sec. 5.3); tracked     */
+                           /* with GSDF_MODEL_TRILINEAR only, and the calls that     */
+                           /* read gradients reject it with GSDF_EINVAL              */
 } gsdf_storage;
 
 /* Map geometry and capacity.  The grid is v_j = voxel_size * m_j (Sec. 3.1),

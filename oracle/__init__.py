@@ -64,7 +64,7 @@ def _load():
         "orc_band_voxels": (_I, [_P, _P, _P, _I, _I, C.c_float, _P, _I]),
         "orc_allocate": (_I64, [_P, _P, _P, _P]),
         "orc_normals": (None, [_P, _P, _D, _P, _P, _P]),
-        "orc_integrate": (_I64, [_P, _P, _P, _P, _D, _D, _D, _P]),
+        "orc_integrate": (_I64, [_P, _P, _P, _P, _D, _D, _D, _I, _P]),
         "orc_pyramid_down": (None, [_P, _P, _D, _P]),
         "orc_normal_equations": (None, [_P, _P, _P, _P, _D, _P]),
         "orc_gn_level": (_I, [_P, _P, _P, _I, _D, _D, _P, _P]),
@@ -177,13 +177,15 @@ class OracleMap:
 
     def integrate(self, depth: np.ndarray, cam, T: np.ndarray, eps: Optional[float] = None,
                   cos_min: float = float(np.cos(np.deg2rad(75.0))), margin: float = 1e-5,
-                  return_marginal: bool = False):
+                  return_marginal: bool = False, gradients: bool = True):
+        """Fusion of one frame (Eq. (1)-(3)); gradients=False fuses the
+        distance and weight only (Eq. (1)-(2)), leaving g at zero."""
         d = _c(depth, np.float32)
         c = cam_struct(cam)
         eps = self.voxel_size if eps is None else float(eps)
         marg = np.zeros(depth.shape, np.int32) if return_marginal else None
         n = int(_load().orc_integrate(self._h, _ptr(d), C.byref(c), _ptr(_c(T, np.float64)),
-                                      eps, float(cos_min), float(margin), _ptr(marg)))
+                                      eps, float(cos_min), float(margin), 1 if gradients else 0, _ptr(marg)))
         return (n, marg) if return_marginal else n
 
     def integrate_rounded(self, depth: np.ndarray, cam, T: np.ndarray, storage: str,
@@ -445,10 +447,14 @@ def unpack_upper(ne: np.ndarray):
 
 def track_stream(depths: np.ndarray, cam, poses_gt: np.ndarray, voxel_size: float,
                  truncation: float, levels: int = 3, iters=(4, 5, 10), delta: float = 0.01,
-                 damping: float = 1e-6, n_frames: Optional[int] = None, timings: Optional[list] = None):
+                 damping: float = 1e-6, n_frames: Optional[int] = None, timings: Optional[list] = None,
+                 model: str = "taylor", gradients: bool = True):
     """The per-frame loop: frame 0 fused at its ground-truth pose; every later
     frame is tracked from the previous estimate, then allocated and fused at
-    the estimate.  ``iters`` is finest-first.  Returns (map, poses)."""
+    the estimate.  ``iters`` is finest-first; ``model`` and ``gradients``
+    select the residual model and whether fusion stores gradients (the
+    paper's baseline: "trilinear" on a map without gradients).  Returns
+    (map, poses)."""
     import time
     F = len(depths) if n_frames is None else n_frames
     M = OracleMap(voxel_size, truncation)
@@ -456,15 +462,15 @@ def track_stream(depths: np.ndarray, cam, poses_gt: np.ndarray, voxel_size: floa
     est = [T.copy()]
     t0 = time.perf_counter()
     M.allocate(depths[0], cam, T)
-    M.integrate(depths[0], cam, T)
+    M.integrate(depths[0], cam, T, gradients=gradients)
     if timings is not None:
         timings.append(("fuse", time.perf_counter() - t0))
     for f in range(1, F):
         t0 = time.perf_counter()
-        T, _, _ = M.track(depths[f], cam, T, levels, iters, delta, damping)
+        T, _, _ = M.track(depths[f], cam, T, levels, iters, delta, damping, model=model)
         t1 = time.perf_counter()
         M.allocate(depths[f], cam, T)
-        M.integrate(depths[f], cam, T)
+        M.integrate(depths[f], cam, T, gradients=gradients)
         t2 = time.perf_counter()
         if timings is not None:
             timings.append(("track", t1 - t0))

@@ -667,10 +667,13 @@ void orc_normals(const float* depth, const OrcCam* cam, double truncation, doubl
 
 // Fusion (Eq. (1)-(3)), observation by observation in pixel order.
 // eps: linear-weight plateau; cos_min: cosine of the maximum viewing angle.
+// gradients = 0 fuses the distance and weight only (Eq. (1)-(2)), leaving
+// g untouched: the plain SDF map without stored gradients that the paper's
+// runtime comparison integrates (Sec. 5.3).
 // marginal_out (optional, H*W): 1 where the angle test is within margin of
 // its threshold.  Returns the number of voxel updates with w > 0.
 int64_t orc_integrate(OrcMap* M, const float* depth, const OrcCam* cam, const double* T,
-                      double eps, double cos_min, double margin, int32_t* marginal_out) {
+                      double eps, double cos_min, double margin, int32_t gradients, int32_t* marginal_out) {
     Decision d = make_decision(M, *cam, T);
     float Tf = (float)M->T;
     const double* Rm = T;
@@ -701,7 +704,8 @@ int64_t orc_integrate(OrcMap* M, const float* depth, const OrcCam* cam, const do
                 if (!(w > 0.0)) continue;
                 V->psi = (V->W * V->psi + w * dist) / (V->W + w);   // Eq. (1)
                 V->W = V->W + w;                                      // Eq. (2)
-                for (int k = 0; k < 3; ++k) V->g[k] += w * nw[k];     // Eq. (3)
+                if (gradients)
+                    for (int k = 0; k < 3; ++k) V->g[k] += w * nw[k]; // Eq. (3)
                 ++updates;
             }
         }

@@ -12,7 +12,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgsdf.so")
 
 OK, EINVAL, ECAPACITY, EHIP, ENOTPD, ELOST = 0, -1, -2, -3, -4, -5
-FP32, BF16, FP16 = 0, 1, 2
+FP32, BF16, FP16, NOGRAD_FP32 = 0, 1, 2, 3
 (K_ALLOCATE, K_INTEGRATE, K_TRACK, K_PYRAMID, K_NORMALS, K_BACKWARD, K_LOSS, K_PHOTOMETRIC,
  K_ALLOC_NORMALS) = range(9)
 

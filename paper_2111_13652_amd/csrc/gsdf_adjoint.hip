@@ -366,6 +366,7 @@ static int keyframe_common(const gsdf_map* map, const float* depth_dev, int32_t 
         !params_dev || param_blocks < 0 || param_blocks > map->desc.max_blocks || !(huber_delta > 0.0f) || !scratch)
         return GSDF_EINVAL;
     if (scratch_bytes < gsdf_keyframe_scratch_bytes(cam, K)) return GSDF_EINVAL;
+    if (!has_gradients(map)) return GSDF_EINVAL;
     return GSDF_OK;
 }
 
@@ -411,7 +412,8 @@ int gsdf_backward(const gsdf_map* map, const float* depth_dev, int32_t n_keyfram
 }
 
 int gsdf_export_params(const gsdf_map* map, float* params_dev, int64_t param_blocks, void* stream) {
-    if (!valid_map(map) || !params_dev || param_blocks < 0 || param_blocks > map->desc.max_blocks)
+    if (!valid_map(map) || !params_dev || param_blocks < 0 || param_blocks > map->desc.max_blocks ||
+        !has_gradients(map))
         return GSDF_EINVAL;
     if (param_blocks == 0) return GSDF_OK;
     k_export_params<<<2048, 256, 0, (hipStream_t)stream>>>(make_view(*map), map->desc.storage, param_blocks,
@@ -420,7 +422,8 @@ int gsdf_export_params(const gsdf_map* map, float* params_dev, int64_t param_blo
 }
 
 int gsdf_import_params(gsdf_map* map, const float* params_dev, int64_t param_blocks, void* stream) {
-    if (!valid_map(map) || !params_dev || param_blocks < 0 || param_blocks > map->desc.max_blocks)
+    if (!valid_map(map) || !params_dev || param_blocks < 0 || param_blocks > map->desc.max_blocks ||
+        !has_gradients(map))
         return GSDF_EINVAL;
     if (param_blocks == 0) return GSDF_OK;
     k_import_params<<<2048, 256, 0, (hipStream_t)stream>>>(make_view(*map), map->desc.storage, param_blocks,

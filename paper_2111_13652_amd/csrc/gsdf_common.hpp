@@ -95,6 +95,11 @@ __host__ __device__ inline void demorton9(int r, int* lx, int* ly, int* lz) {
     *lz = z;
 }
 
+// Bytes of one voxel record in map.vox.
+__host__ __device__ inline int vox_bytes(int storage) {
+    return storage == GSDF_FP32 ? 16 : (storage == GSDF_NOGRAD_FP32 ? 4 : 8);
+}
+
 // 16-bit storage formats: bf16 (round to nearest even) and IEEE fp16.
 __device__ inline float unpack16(unsigned short s, int storage) {
     if (storage == GSDF_BF16) return __uint_as_float((uint32_t)s << 16);
@@ -220,6 +225,9 @@ __device__ inline float load_voxel(const MapView& M, int storage, int64_t vi, fl
         g[0] = r.y;
         g[1] = r.z;
         g[2] = r.w;
+    } else if (storage == GSDF_NOGRAD_FP32) {
+        *psi = reinterpret_cast<const float*>(M.vox)[vi] / Wv;
+        g[0] = g[1] = g[2] = 0.0f;
     } else {
         const ushort4 r = reinterpret_cast<const ushort4*>(M.vox)[vi];
         *psi = unpack16(r.x, storage) * M.truncation;

@@ -22,7 +22,9 @@
 // psi = (sum w d) / W is Eq. (1)-(2) unrolled over all observations and g
 // is Eq. (3) exactly, so the write is an addition.  16-bit storage keeps
 // {psi/T, gbar} (gbar = g / W, bounded) and applies Eq. (1)-(3) with the
-// frame's sums before rounding once.
+// frame's sums before rounding once.  The gradient-free storage keeps
+// {sum w d} and W only: the same distance sums as FP32 storage, without
+// the three gradient sums (Eq. (3)).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -250,8 +252,9 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
     // lx + 8 ly + 64 lz (the pool's Morton order is applied at the write):
     // integer additions are associative, so the sums (and the map) do not
     // depend on the order in which the work-group's threads add their updates
+    constexpr bool kGrad = STORAGE != GSDF_NOGRAD_FP32;
     __shared__ unsigned long long aS[kBlockVoxels];
-    __shared__ unsigned long long aG[3][kBlockVoxels];
+    __shared__ unsigned long long aG[kGrad ? 3 : 1][kGrad ? kBlockVoxels : 1];
     __shared__ unsigned long long aW[kBlockVoxels];
     __shared__ BlockBox box;
     __shared__ uint32_t q_pix[kFuseChunk];
@@ -297,9 +300,11 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
         unpack_key(M.block_keys[slot], &bx, &by, &bz);
         for (int c = threadIdx.x; c < kBlockVoxels; c += kFuseBlock) {
             aS[c] = 0ull;
-            aG[0][c] = 0ull;
-            aG[1][c] = 0ull;
-            aG[2][c] = 0ull;
+            if constexpr (kGrad) {
+                aG[0][c] = 0ull;
+                aG[1][c] = 0ull;
+                aG[2][c] = 0ull;
+            }
             aW[c] = 0ull;
         }
         if (threadIdx.x == 0) block_box(fc, R, t, bx, by, bz, &box);
@@ -429,7 +434,7 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
                 // storage (q - v_s m_c = R x + t_r, |t_r| < v_s)
                 int mref[3];
                 float prel[3];
-                if (STORAGE == GSDF_FP32) {
+                if (STORAGE == GSDF_FP32 || STORAGE == GSDF_NOGRAD_FP32) {
                     const double Dd = (double)D;
                     const double x0 = Dd * (((double)u - fc.cx_d) * fc.ifx_d);
                     const double x1 = Dd * (((double)v - fc.cy_d) * fc.ify_d);
@@ -469,9 +474,11 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
                     const int c = (m[0] & 7) | ((m[1] & 7) << 3) | ((m[2] & 7) << 6);  // lx + 8 ly + 64 lz
                     const float ws = w * fc.fix_scale, wh = ws * 2.3283064365386963e-10f;
                     atomicAdd(&aS[c], fixed_term(ws, wh, d));
-                    atomicAdd(&aG[0][c], fixed_term(ws, wh, px.x));
-                    atomicAdd(&aG[1][c], fixed_term(ws, wh, px.y));
-                    atomicAdd(&aG[2][c], fixed_term(ws, wh, px.z));
+                    if constexpr (kGrad) {
+                        atomicAdd(&aG[0][c], fixed_term(ws, wh, px.x));
+                        atomicAdd(&aG[1][c], fixed_term(ws, wh, px.y));
+                        atomicAdd(&aG[2][c], fixed_term(ws, wh, px.z));
+                    }
                     atomicAdd(&aW[c], fixed_term(ws, wh, 1.0f));
                     ++my_updates;
                 }
@@ -484,10 +491,15 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
             const float sw = from_fixed(aW[c], fc.fix_inv);
             if (!(sw > 0.0f)) continue;
             const float sS = from_fixed(aS[c], fc.fix_inv);
-            const float sG[3] = {from_fixed(aG[0][c], fc.fix_inv), from_fixed(aG[1][c], fc.fix_inv),
-                                 from_fixed(aG[2][c], fc.fix_inv)};
             ++my_voxels;
             const int64_t vi = (int64_t)slot * kBlockVoxels + morton9(c & 7, (c >> 3) & 7, c >> 6);
+            if constexpr (!kGrad) {
+                reinterpret_cast<float*>(M.vox)[vi] += sS;
+                M.weight[vi] += sw;
+                continue;
+            }
+            const float sG[3] = {from_fixed(aG[0][c], fc.fix_inv), from_fixed(aG[1][c], fc.fix_inv),
+                                 from_fixed(aG[2][c], fc.fix_inv)};
             if (STORAGE == GSDF_FP32) {
                 float4* rec = reinterpret_cast<float4*>(M.vox) + vi;
                 float4 r = *rec;
@@ -573,6 +585,16 @@ inline FuseConsts fuse_consts(const gsdf_map& map, const gsdf_camera& cam, const
     return fc;
 }
 
+inline void launch_fuse_blocks(int storage, hipStream_t s, const MapView& M, const float4* pix, const FuseConsts& fc,
+                               const double* Twc, int32_t* status) {
+    switch (storage) {
+        case GSDF_FP32: k_fuse_blocks<GSDF_FP32><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, Twc, status); break;
+        case GSDF_BF16: k_fuse_blocks<GSDF_BF16><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, Twc, status); break;
+        case GSDF_FP16: k_fuse_blocks<GSDF_FP16><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, Twc, status); break;
+        default: k_fuse_blocks<GSDF_NOGRAD_FP32><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, Twc, status); break;
+    }
+}
+
 }  // namespace gsdf
 
 using namespace gsdf;
@@ -601,11 +623,7 @@ extern "C" int gsdf_integrate_frame(gsdf_map* map, const float* depth_dev, const
     }
     {
         TimedLaunch t(map->timer, GSDF_K_INTEGRATE, s);
-        switch (map->desc.storage) {
-            case GSDF_FP32: k_fuse_blocks<GSDF_FP32><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev, status_dev); break;
-            case GSDF_BF16: k_fuse_blocks<GSDF_BF16><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev, status_dev); break;
-            default: k_fuse_blocks<GSDF_FP16><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev, status_dev); break;
-        }
+        launch_fuse_blocks(map->desc.storage, s, M, pix, fc, T_wc_dev, status_dev);
     }
     return launch_status();
 }
@@ -628,11 +646,7 @@ extern "C" int gsdf_fuse_frame(gsdf_map* map, const float* depth_dev, const gsdf
     }
     {
         TimedLaunch t(map->timer, GSDF_K_INTEGRATE, s);
-        switch (map->desc.storage) {
-            case GSDF_FP32: k_fuse_blocks<GSDF_FP32><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev, status_dev); break;
-            case GSDF_BF16: k_fuse_blocks<GSDF_BF16><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev, status_dev); break;
-            default: k_fuse_blocks<GSDF_FP16><<<kFuseGroups, kFuseBlock, 0, s>>>(M, pix, fc, T_wc_dev, status_dev); break;
-        }
+        launch_fuse_blocks(map->desc.storage, s, M, pix, fc, T_wc_dev, status_dev);
     }
     return launch_status();
 }

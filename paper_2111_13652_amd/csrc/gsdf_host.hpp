@@ -37,13 +37,16 @@ inline bool valid_desc(const gsdf_map_desc& d) {
     if (d.max_blocks <= 0 || d.max_blocks > (1 << 24)) return false;
     if (d.hash_slots <= 0 || (d.hash_slots & (d.hash_slots - 1)) != 0) return false;
     if (d.hash_slots < d.max_blocks) return false;
-    if (d.storage < GSDF_FP32 || d.storage > GSDF_FP16) return false;
+    if (d.storage < GSDF_FP32 || d.storage > GSDF_NOGRAD_FP32) return false;
     return true;
 }
 
 inline bool valid_map(const gsdf_map* m) {
     return m && m->hash && m->vox && m->weight && m->aux && valid_desc(m->desc);
 }
+
+// Maps without stored gradients serve fusion and the tri-linear model only.
+inline bool has_gradients(const gsdf_map* m) { return m->desc.storage != GSDF_NOGRAD_FP32; }
 
 inline bool valid_cam(const gsdf_camera* c) {
     return c && c->width > 0 && c->height > 0 && c->width <= 16384 && c->height <= 16384 &&

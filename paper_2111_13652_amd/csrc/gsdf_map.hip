@@ -151,6 +151,10 @@ __global__ void k_export_voxels(MapView M, int storage, int32_t n_blocks, float*
         g0 = r.y;
         g1 = r.z;
         g2 = r.w;
+    } else if (storage == GSDF_NOGRAD_FP32) {
+        const float r = reinterpret_cast<const float*>(M.vox)[vi];
+        psi = Wv > 0.0f ? r / Wv : 0.0f;
+        g0 = g1 = g2 = 0.0f;
     } else {
         const ushort4 p = reinterpret_cast<const ushort4*>(M.vox)[vi];
         psi = unpack16(p.x, storage) * M.truncation;
@@ -192,6 +196,8 @@ __global__ void k_import_voxels(MapView M, int storage, const int32_t* keys, int
     if (storage == GSDF_FP32) {
         reinterpret_cast<float4*>(M.vox)[vi] =
             make_float4(psi[gi] * Wv, g[3 * gi], g[3 * gi + 1], g[3 * gi + 2]);
+    } else if (storage == GSDF_NOGRAD_FP32) {
+        reinterpret_cast<float*>(M.vox)[vi] = psi[gi] * Wv;
     } else {
         reinterpret_cast<ushort4*>(M.vox)[vi] =
             make_ushort4(pack16(psi[gi] / M.truncation, storage), pack16(g[3 * gi], storage),
@@ -212,7 +218,7 @@ int gsdf_map_buffer_sizes(const gsdf_map_desc* desc, size_t sizes_out[4]) {
     if (!desc || !sizes_out || !valid_desc(*desc)) return GSDF_EINVAL;
     const size_t nv = (size_t)desc->max_blocks * kBlockVoxels;
     sizes_out[0] = (size_t)desc->hash_slots * sizeof(HashEntry);
-    sizes_out[1] = nv * (desc->storage == GSDF_FP32 ? 16 : 8);
+    sizes_out[1] = nv * (size_t)vox_bytes(desc->storage);
     sizes_out[2] = nv * 4;
     sizes_out[3] = aux_layout(*desc).total;
     return GSDF_OK;

@@ -350,6 +350,7 @@ static int photo_check(const gsdf_map* map, const float* depth_dev, const float*
         !T0_dev || !xi_dev || !params_dev || param_blocks < 0 || param_blocks > map->desc.max_blocks || !scratch)
         return GSDF_EINVAL;
     if (scratch_bytes < photo_scratch(param_blocks, K).total) return GSDF_EINVAL;
+    if (!has_gradients(map)) return GSDF_EINVAL;
     return GSDF_OK;
 }
 

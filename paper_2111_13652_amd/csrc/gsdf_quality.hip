@@ -127,7 +127,7 @@ extern "C" {
 
 int gsdf_gradient_quality(const gsdf_map* map, const double* spheres_dev, int32_t n_spheres, float* out_dev,
                           int64_t stride, void* stream) {
-    if (!valid_map(map) || !spheres_dev || n_spheres < 1 || n_spheres > kMaxSpheres || !out_dev || stride < 0 ||
+    if (!valid_map(map) || !has_gradients(map) || !spheres_dev || n_spheres < 1 || n_spheres > kMaxSpheres || !out_dev || stride < 0 ||
         stride % kBlockVoxels != 0)
         return GSDF_EINVAL;
     if (stride == 0) return GSDF_OK;

@@ -169,7 +169,8 @@ size_t gsdf_surfel_scratch_bytes(const gsdf_map* map) {
 
 int gsdf_extract_surfels(const gsdf_map* map, int32_t level, float* points_dev, float* normals_dev, int32_t* ids_dev,
                          int64_t capacity, int64_t* count_dev, void* scratch_dev, size_t scratch_bytes, void* stream) {
-    if (!valid_map(map) || (level != 0 && level != 1) || capacity < 0 || !count_dev || !scratch_dev ||
+    if (!valid_map(map) || !has_gradients(map) || (level != 0 && level != 1) || capacity < 0 || !count_dev ||
+        !scratch_dev ||
         scratch_bytes < gsdf_surfel_scratch_bytes(map) ||
         (capacity > 0 && (!points_dev || !normals_dev || !ids_dev)))
         return GSDF_EINVAL;

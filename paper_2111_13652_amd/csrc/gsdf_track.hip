@@ -90,7 +90,7 @@ template <int STORAGE>
 __device__ inline void accumulate(const MapView& M, const TrackLevel& L, const TrackArgs& a,
                                   const double* pose, int first, int stride, int end, const float* Dpre,
                                   float acc[kNE], float cmp[kNE]) {
-    constexpr bool kPrecision = STORAGE != GSDF_FP32;
+    constexpr bool kPrecision = STORAGE == GSDF_BF16 || STORAGE == GSDF_FP16;
     constexpr int B = kTrackBatch;
     Kahan ks[kNE];
 #pragma unroll
@@ -283,7 +283,7 @@ template <int STORAGE>
 __device__ inline void accumulate_trilinear(const MapView& M, const TrackLevel& L, const TrackArgs& a,
                                             const double* pose, int first, int stride, int end,
                                             const float* Dpre, float acc[kNE], float cmp[kNE]) {
-    constexpr bool kPrecision = STORAGE != GSDF_FP32;
+    constexpr bool kPrecision = STORAGE == GSDF_BF16 || STORAGE == GSDF_FP16;
     constexpr int B = kTrackBatch;
     Kahan ks[kNE];
 #pragma unroll
@@ -353,6 +353,8 @@ __device__ inline void accumulate_trilinear(const MapView& M, const TrackLevel& 
                 cw[j][c] = M.weight[vi];
                 if (STORAGE == GSDF_FP32)
                     craw[j][c] = __float_as_uint(reinterpret_cast<const float*>(M.vox)[4 * vi]);
+                else if (STORAGE == GSDF_NOGRAD_FP32)
+                    craw[j][c] = __float_as_uint(reinterpret_cast<const float*>(M.vox)[vi]);
                 else
                     craw[j][c] = reinterpret_cast<const unsigned short*>(M.vox)[4 * vi];
             }
@@ -366,8 +368,9 @@ __device__ inline void accumulate_trilinear(const MapView& M, const TrackLevel& 
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 all = all && cw[j][k] > 0.0f;
-                c[k] = STORAGE == GSDF_FP32 ? __uint_as_float(craw[j][k]) / cw[j][k]
-                                            : unpack16((unsigned short)craw[j][k], STORAGE) * M.truncation;
+                c[k] = (STORAGE == GSDF_FP32 || STORAGE == GSDF_NOGRAD_FP32)
+                           ? __uint_as_float(craw[j][k]) / cw[j][k]
+                           : unpack16((unsigned short)craw[j][k], STORAGE) * M.truncation;
             }
             if (!all) continue;
             const float wx[2] = {1.0f - f[j][0], f[j][0]};
@@ -935,7 +938,7 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
     __shared__ int s_ok;
     __shared__ ReduceLds red;
     __shared__ float s_depth[kTrackBatch * kTrackBlock];
-    constexpr bool COMP = STORAGE != GSDF_FP32;
+    constexpr bool COMP = STORAGE == GSDF_BF16 || STORAGE == GSDF_FP16;
     const int G = gridDim.x;
     double* pose_pub = partials + 2 * kPartsPerSet;
     // a work-group that takes part in no level holds nothing anyone needs
@@ -1225,8 +1228,12 @@ int launch_track_model(int model, gsdf_timer* timer, hipStream_t s, const MapVie
     if (model == GSDF_MODEL_TRILINEAR)
         return launch_track_frame<STORAGE, GSDF_MODEL_TRILINEAR>(timer, s, M, a, pose_in, pose_out, partials,
                                                                 sync, stats, status);
-    return launch_track_frame<STORAGE, GSDF_MODEL_TAYLOR>(timer, s, M, a, pose_in, pose_out, partials, sync,
-                                                         stats, status);
+    if constexpr (STORAGE == GSDF_NOGRAD_FP32) {
+        return GSDF_EINVAL;   // the Taylor model needs the stored gradient
+    } else {
+        return launch_track_frame<STORAGE, GSDF_MODEL_TAYLOR>(timer, s, M, a, pose_in, pose_out, partials, sync,
+                                                             stats, status);
+    }
 }
 
 inline void fill_levels(const gsdf_camera& cam, const float* depth, const ScratchLayout& sl, char* base,
@@ -1279,6 +1286,7 @@ int track_frame_on(const gsdf_map* map, const float* depth_dev, const gsdf_camer
         if (params->iters[l] < 0 || params->iters[l] > 1000) return GSDF_EINVAL;
     if (params->model != GSDF_MODEL_TAYLOR && params->model != GSDF_MODEL_TRILINEAR) return GSDF_EINVAL;
     if (params->max_polls < 0) return GSDF_EINVAL;
+    if (params->model == GSDF_MODEL_TAYLOR && !has_gradients(map)) return GSDF_EINVAL;
     if ((cam->width >> (levels - 1)) < 1 || (cam->height >> (levels - 1)) < 1) return GSDF_EINVAL;
     const ScratchLayout sl = scratch_layout(*cam, levels);
     if (scratch_bytes < sl.total) return GSDF_EINVAL;
@@ -1327,7 +1335,8 @@ int track_frame_on(const gsdf_map* map, const float* depth_dev, const gsdf_camer
     switch (map->desc.storage) {
         case GSDF_FP32: rc = launch_track_model<GSDF_FP32>(params->model, map->timer, s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
         case GSDF_BF16: rc = launch_track_model<GSDF_BF16>(params->model, map->timer, s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
-        default: rc = launch_track_model<GSDF_FP16>(params->model, map->timer, s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
+        case GSDF_FP16: rc = launch_track_model<GSDF_FP16>(params->model, map->timer, s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
+        default: rc = launch_track_model<GSDF_NOGRAD_FP32>(params->model, map->timer, s, M, a, T_init_dev, T_wc_out_dev, partials, sync, stats_dev, status_dev); break;
     }
     if (rc != GSDF_OK) return rc;
     return launch_status();
@@ -1388,6 +1397,7 @@ extern "C" int gsdf_normal_equations(const gsdf_map* map, const float* depth_dev
                                      size_t scratch_bytes, void* stream) {
     if (!valid_map(map) || !depth_dev || !valid_cam(cam) || !T_wc_dev || !out29_dev || !scratch_dev)
         return GSDF_EINVAL;
+    if (!has_gradients(map)) return GSDF_EINVAL;
     const ScratchLayout sl = scratch_layout(*cam, 1);
     if (scratch_bytes < sl.total) return GSDF_EINVAL;
     hipStream_t s = (hipStream_t)stream;

@@ -16,7 +16,9 @@ import torch
 
 from . import _lib
 
-STORAGE = {"fp32": _lib.FP32, "bf16": _lib.BF16, "fp16": _lib.FP16}
+# "nograd": distance and weight only (no stored gradient), the plain SDF map
+# of the paper's runtime comparison; it is tracked with model="trilinear".
+STORAGE = {"fp32": _lib.FP32, "bf16": _lib.BF16, "fp16": _lib.FP16, "nograd": _lib.NOGRAD_FP32}
 COS_75 = math.cos(math.radians(75.0))
 
 

@@ -500,10 +500,17 @@ def smooth_trajectory(seed: int, n_frames: int, max_step_m: float = 0.02,
 # --------------------------------------------------------------------------
 CONFIG_SPHERE = dict(cam=Camera(131.0, 131.0, 79.5, 59.5, 160, 120, 0.0, float("inf")),
                      voxel_size=0.02, truncation=0.10)
+# ``seeds``: (scene, trajectory, noise) of each stream.  The 1280x720
+# stream uses trajectory 7: the trajectories of seeds 5 and 6 pass, after
+# about 240 frames, through views of a single wall or the floor, where a
+# plane leaves three degrees of freedom of the pose unobserved and every
+# tracker slides; 7 is the first seed from 5 on whose 500 frames all keep
+# the point-to-plane information of the view well conditioned (the check
+# is tests/test_synth.py::test_hd_trajectory_keeps_the_pose_observable).
 CONFIG_ROOM = dict(cam=Camera(525.0, 525.0, 319.5, 239.5, 640, 480, 0.4, 4.0),
-                   voxel_size=0.01, truncation=0.05)
+                   voxel_size=0.01, truncation=0.05, seeds=(1, 2, 3))
 CONFIG_ROOM_HD = dict(cam=Camera(920.0, 920.0, 639.5, 359.5, 1280, 720, 0.4, 4.0),
-                      voxel_size=0.005, truncation=0.025)
+                      voxel_size=0.005, truncation=0.025, seeds=(1, 7, 6))
 
 # Gradient-quality experiment: 1 cm voxels, truncation 10 voxels.
 CONFIG_SPHERES = dict(cam=Camera(525.0, 525.0, 319.5, 239.5, 640, 480, 0.4, 4.0),
@@ -547,26 +554,27 @@ def make_stream(cam: Camera, n_frames: int, scene_seed: int = 1, traj_seed: int 
 
 def make_rgbd_stream(cam: Camera, n_frames: int, scene_seed: int = 1, traj_seed: int = 2,
                      noise_seed: Optional[int] = 3, albedo_seed: int = 4, color_noise: float = 0.005,
-                     n_objects: int = 20) -> Stream:
+                     n_objects: int = 20, frames: Optional[Sequence[int]] = None) -> Stream:
     """The room stream with colour: the depth exactly as ``make_stream`` (same
     seeds give the same depth), plus Lambertian colour of seeded per-object
     albedo fields with Gaussian noise ``color_noise`` (second child seed of
-    each frame), clipped to [0, 1]."""
+    each frame), clipped to [0, 1].  ``frames`` as for ``make_stream``."""
     poses = smooth_trajectory(traj_seed, n_frames)
     scene = room_scene(scene_seed, poses[:, :, 3], n_objects=n_objects)
     alb = make_albedo(scene, albedo_seed)
     kids = np.random.SeedSequence(noise_seed).spawn(n_frames) if noise_seed is not None else None
-    depth = np.empty((n_frames, cam.height, cam.width), np.float32)
-    rgb = np.empty((n_frames, cam.height, cam.width, 3), np.float32)
-    for i in range(n_frames):
+    which = list(range(n_frames)) if frames is None else [int(f) for f in frames]
+    depth = np.empty((len(which), cam.height, cam.width), np.float32)
+    rgb = np.empty((len(which), cam.height, cam.width, 3), np.float32)
+    for j, i in enumerate(which):
         z, col = render_rgbd(scene, cam, poses[i], alb)
         if kids is not None:
             z = add_depth_noise(z, np.random.Generator(np.random.PCG64(kids[i])))
             g = np.random.Generator(np.random.PCG64(kids[i].spawn(1)[0]))
             col = np.clip(col + g.standard_normal(col.shape).astype(np.float32) * np.float32(color_noise),
                           0.0, 1.0)
-        depth[i] = to_depth_image(z, cam)
-        rgb[i] = col
+        depth[j] = to_depth_image(z, cam)
+        rgb[j] = col
     return Stream(cam=cam, depth=depth, poses=poses, scene=scene, rgb=rgb, albedo=alb)
 
 

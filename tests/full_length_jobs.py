@@ -11,7 +11,7 @@ touches the GPU or the library under test.
 Streams (the sizes of the workloads the method is measured on):
   room: 100 frames 640x480, 1 cm voxels, T 5 cm (scene 1, trajectory 2,
         noise 3);
-  hd:   500 frames 1280x720, 5 mm voxels, T 2.5 cm (scene 1, trajectory 5,
+  hd:   500 frames 1280x720, 5 mm voxels, T 2.5 cm (scene 1, trajectory 7,
         noise 6); the oracle runs its first 100 frames.
 """
 from __future__ import annotations
@@ -39,12 +39,12 @@ def _log(msg: str) -> None:
 
 def _room(frames=None):
     from paper_2111_13652_amd import synth
-    return synth.make_stream(synth.CONFIG_ROOM["cam"], ROOM_FRAMES, 1, 2, 3, frames=frames)
+    return synth.make_stream(synth.CONFIG_ROOM["cam"], ROOM_FRAMES, *synth.CONFIG_ROOM["seeds"], frames=frames)
 
 
 def _hd(frames=None):
     from paper_2111_13652_amd import synth
-    return synth.make_stream(synth.CONFIG_ROOM_HD["cam"], HD_FRAMES, 1, 5, 6, frames=frames)
+    return synth.make_stream(synth.CONFIG_ROOM_HD["cam"], HD_FRAMES, *synth.CONFIG_ROOM_HD["seeds"], frames=frames)
 
 
 # ---------------------------------------------------------------------------

@@ -63,7 +63,7 @@ def voxel_coords(keys):
 
 
 def compare_voxels(gpu, orc, keys, voxel_size, exclude=frozenset(), psi_tol=1e-4, g_tol=1e-5,
-                   w_rtol=1e-5, w_atol=1e-4):
+                   w_rtol=1e-5, w_atol=1e-4, gradients=True):
     """Parity of psi (in units of the voxel size), g-direction and W; returns
     a report dict.
 
@@ -76,7 +76,8 @@ def compare_voxels(gpu, orc, keys, voxel_size, exclude=frozenset(), psi_tol=1e-4
     error of d = T has W ~ 1e-7 and may be observed by one side only; the
     same bound covers it (its W must stay below w_atol).  Voxels touched by
     a pixel whose angle test is within rounding of its threshold
-    (``exclude``) are left out and counted."""
+    (``exclude``) are left out and counted.  gradients=False: maps without
+    stored gradients (g is not compared)."""
     pg, gg, Wg = gpu
     po, go, Wo = orc
     either = (Wg > 0) | (Wo > 0)
@@ -90,9 +91,12 @@ def compare_voxels(gpu, orc, keys, voxel_size, exclude=frozenset(), psi_tol=1e-4
     both = either & (Wg > 0) & (Wo > 0)
     one = either & ~both
     dpsi = np.abs(pg[both] - po[both]) / voxel_size
-    ghg = gg[both] / np.linalg.norm(gg[both], axis=-1, keepdims=True)
-    gho = go[both] / np.linalg.norm(go[both], axis=-1, keepdims=True)
-    dg = np.linalg.norm(ghg - gho, axis=-1)
+    if gradients:
+        ghg = gg[both] / np.linalg.norm(gg[both], axis=-1, keepdims=True)
+        gho = go[both] / np.linalg.norm(go[both], axis=-1, keepdims=True)
+        dg = np.linalg.norm(ghg - gho, axis=-1)
+    else:
+        dg = np.zeros(1)
     dW = np.abs(Wg[either] - Wo[either]) / (Wo[either] + w_atol / w_rtol)
     rep = dict(n=int(both.sum()), excluded=n_excluded, one_side=int(one.sum()),
                one_side_w_max=float(np.maximum(Wg[one], Wo[one]).max()) if one.any() else 0.0,

@@ -167,7 +167,7 @@ def test_hd_error_against_fp64_oracle_and_fp32_path(torch_mod):
     cam = HD["cam"]
     vs, T = HD["voxel_size"], HD["truncation"]
     F = 5
-    st = synth.make_stream(cam, F, scene_seed=1, traj_seed=5, noise_seed=6)
+    st = synth.make_stream(cam, F, *HD["seeds"])
     log(f"case: HD error report, {F} frames")
     # SDF error: everything fused at the ground-truth poses
     O = oracle.OracleMap(vs, T)

@@ -121,3 +121,36 @@ def test_gauss_newton_with_trilinear_model_zeroes_plane_residuals():
     # the estimate sees the same plane (the in-plane motion is unobservable)
     np.testing.assert_allclose(Tn[:, :3].T @ n, n_cam, atol=1e-6)
     assert abs((h - n @ Tn[:, 3]) - h_cam) < 1e-6
+
+
+def test_map_without_gradients_fuses_the_same_distances():
+    """Fusion without gradients applies Eq. (1)-(2) alone: the distances
+    and weights are bit-identical to fusion with gradients (Eq. (3) feeds
+    neither) and the gradients stay zero.  The tri-linear model reads only
+    distances and weights, so tracking on either map ends at the same pose
+    bit for bit: the gradient-free map with the tri-linear tracker is the
+    paper's baseline system."""
+    cam = scenes.SMALL_CAM
+    sc = scenes.box_room_scene()
+    T0 = scenes.box_room_pose()
+    full = oracle.OracleMap(0.02, 0.1)
+    plain = oracle.OracleMap(0.02, 0.1)
+    for k in range(3):
+        Tk = synth.perturb_pose(T0, 200 + k, 1.0, 0.01)
+        d = scenes.depth_image(synth.render_depth(sc, cam, Tk), cam)
+        for M, grad in ((full, True), (plain, False)):
+            M.allocate(d, cam, Tk)
+            n = M.integrate(d, cam, Tk, gradients=grad)
+            assert n > 1000
+    np.testing.assert_array_equal(full.keys(), plain.keys())
+    pf, gf, Wf, _ = full.voxels()
+    pp, gp, Wp, _ = plain.voxels()
+    assert np.array_equal(pf, pp) and np.array_equal(Wf, Wp)
+    assert not gp.any() and gf[Wf > 0].any()
+    T1 = synth.perturb_pose(T0, 31, 1.0, 0.01)
+    d1 = scenes.depth_image(synth.render_depth(sc, cam, T1), cam)
+    Ta, sa, _ = full.track(d1, cam, T0, 1, [8], 0.01, model="trilinear")
+    Tb, sb, _ = plain.track(d1, cam, T0, 1, [8], 0.01, model="trilinear")
+    assert np.array_equal(Ta, Tb) and np.array_equal(sa, sb)
+    # and the tri-linear tracker on it moves towards the truth
+    assert np.linalg.norm(Tb[:, 3] - T1[:, 3]) < 0.5 * np.linalg.norm(T0[:, 3] - T1[:, 3])
