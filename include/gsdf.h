@@ -309,11 +309,15 @@ int gsdf_keyframe_loss(const gsdf_map* map, const float* depth_dev, int32_t n_ke
  * stored between the two calls).  With s_i = grad_loss_dev[i]
  * (K float32, device), rho' the Huber derivative and g^ = g/|g|:
  *   dparams[j] += sum s_i rho'(r) {1, (I - g^ g^T)(q - v_j) / |g_j|}
- *     (scatter-added at the voxel's slot: clear dparams_dev first),
+ *     (added to what dparams_dev holds: clear it first),
  *   dxi_dev[i] = Jl(xi_i)^T sum_k s_i rho'(r_k) [g^ ; q x g^]
  *     (K x 6 float64, overwritten; Jl the left Jacobian of SE(3)),
  *   loss_dev (optional) as gsdf_keyframe_loss.
- * Same argument rules as gsdf_keyframe_loss. */
+ * The voxel sums are exact (fixed point) and each voxel is written by one
+ * thread, so the results are the same bits on every run.  freeze = 1 reads
+ * the association from assoc_dev; with freeze = 0 each pixel's nearest
+ * voxel is used and assoc_dev is neither read nor written (the loss call
+ * writes it).  Other argument rules as for gsdf_keyframe_loss. */
 int gsdf_backward(const gsdf_map* map, const float* depth_dev, int32_t n_keyframes,
                   const gsdf_camera* cam, const double* T0_dev, const double* xi_dev,
                   const float* params_dev, int64_t param_blocks, float huber_delta,

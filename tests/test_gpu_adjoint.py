@@ -104,6 +104,39 @@ def _check_against_oracle(torch, O, G, st, idx, seed):
         np.testing.assert_array_equal(gpu != 0, orc != 0)
 
 
+def test_adjoint_with_its_own_association_matches_the_oracle(torch_mod, room_stream, maps):
+    """freeze = 0: the GPU finds each pixel's nearest voxel itself (as the
+    oracle does), so both sides sum over the same pixels unless a point lies
+    within rounding of a cell boundary; gradients within the same bars."""
+    torch = torch_mod
+    from paper_2111_13652_amd.gsdf import KeyframeLoss, voxel_order
+    O, G = maps
+    st = room_stream
+    depth, T0, xi = _keyframes(st, (5, 7, 9), 31)
+    K = len(depth)
+    log(f"case: {K} keyframes, association found by each side")
+    gk = G.keys()
+    Lo, dpsi_o, dg_o, dxi_o = O.loss_grad(depth.astype(np.float64), st.cam, T0, xi, DELTA, keys=gk)
+    params = G.export_params(len(gk)).requires_grad_(True)
+    X = dev(xi).requires_grad_(True)
+    L = KeyframeLoss.apply(params, X, G, dev(depth), st.cam, dev(T0), DELTA)
+    L.sum().backward()
+    np.testing.assert_allclose(L.detach().cpu().numpy().sum(), Lo, rtol=1e-6)
+    dxi_g = X.grad.cpu().numpy()
+    for i in range(K):
+        err = np.abs(dxi_g[i] - dxi_o[i]).max() / np.abs(dxi_o[i]).max()
+        log(f"  dxi[{i}] rel err {err:.2e}")
+        assert err < 1e-5
+    dp = params.grad.cpu().numpy()[:, voxel_order(), :]
+    for name, gpu, orc in (("dpsi", dp[..., 0], dpsi_o), ("dg", dp[..., 1:], dg_o)):
+        scale = np.abs(orc).max()
+        err = np.abs(gpu - orc)
+        bad = err > 1e-4 * np.abs(orc) + 1e-6 * scale
+        log(f"  {name}: max abs err {err.max():.2e} (scale {scale:.2e}), outside bar {int(bad.sum())}")
+        assert not bad.any()
+        np.testing.assert_array_equal(gpu != 0, orc != 0)
+
+
 def test_gradients_match_central_differences_of_the_gpu_loss(torch_mod, room_stream, maps):
     torch = torch_mod
     from paper_2111_13652_amd.gsdf import KeyframeLoss, keyframe_loss

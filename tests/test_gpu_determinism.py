@@ -42,3 +42,33 @@ def test_frame_path_is_bit_reproducible(stream, storage):
     err = np.linalg.norm(p1[:, :, 3] - stream.poses[:, :, 3], axis=1).max()
     log(f"  identical; largest position error against the truth {err:.2e} m")
     assert err < 5e-3
+
+
+@pytest.mark.parametrize("freeze", [False, True])
+def test_adjoint_is_bit_reproducible(stream, freeze):
+    """gsdf_backward twice on the same inputs: the voxel gradients (exact
+    fixed-point sums, one writer per voxel) and the twist gradients (fixed
+    summation order) are the same bits."""
+    import torch
+    from paper_2111_13652_amd.gsdf import GsdfMap, KeyframeLoss
+    st = stream
+    G = GsdfMap(0.01, 0.05, 60000)
+    for f in range(6):
+        G.fuse(dev(st.depth[f]), st.cam, dev(st.poses[f]))
+    idx = [6, 7, 8, 9]
+    T0 = dev(np.stack([synth.perturb_pose(st.poses[f], 60 + i, 1.0, 0.01) for i, f in enumerate(idx)]))
+    D = dev(st.depth[idx])
+    A = torch.zeros((len(idx), st.cam.height, st.cam.width, 3), dtype=torch.int32, device="cuda")
+    log(f"case: adjoint twice, 4 keyframes, freeze={freeze}")
+    if freeze:   # the association of the loss pass, reused
+        KeyframeLoss.apply(G.export_params(), torch.zeros((len(idx), 6), dtype=torch.float64, device="cuda"),
+                           G, D, st.cam, T0, 0.01, A, False)
+    out = []
+    for _ in range(2):
+        params = G.export_params().requires_grad_(True)
+        xi = torch.full((len(idx), 6), 1e-3, dtype=torch.float64, device="cuda").requires_grad_(True)
+        KeyframeLoss.apply(params, xi, G, D, st.cam, T0, 0.01, A if freeze else None, freeze).sum().backward()
+        torch.cuda.synchronize()
+        out.append((params.grad.clone(), xi.grad.clone()))
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    assert out[0][0].abs().sum().item() > 0
