@@ -278,8 +278,11 @@ int gsdf_voxel_order(int32_t order_out[512]);
 int gsdf_compose_poses(int32_t n, const double* T0_dev, const double* xi_dev, double* T_out_dev,
                        void* stream);
 
-/* Scratch bytes of gsdf_keyframe_loss / gsdf_backward. */
-size_t gsdf_keyframe_scratch_bytes(const gsdf_camera* cam, int32_t n_keyframes);
+/* Scratch bytes of gsdf_keyframe_loss / gsdf_backward for K keyframes and
+ * a parameter buffer of param_blocks rows (scratch sized for the map's
+ * max_blocks serves every param_blocks).  0 when the arguments are invalid
+ * or K x W x H exceeds INT32_MAX (pixels are numbered in int32). */
+size_t gsdf_keyframe_scratch_bytes(const gsdf_camera* cam, int32_t n_keyframes, int64_t param_blocks);
 
 /* Keyframe loss (Sec. 4.1 Eq. (5), (14); Huber penalty of Sec. 5.1): for
  * each keyframe i, L_i = sum over its valid pixels of rho_delta(r) with
@@ -295,7 +298,7 @@ size_t gsdf_keyframe_scratch_bytes(const gsdf_camera* cam, int32_t n_keyframes);
  *     reads them instead of searching (for finite differences);
  *   loss_dev: K float64 (device); count_dev (optional): K float64 pixels used.
  * Errors: GSDF_EINVAL for bad sizes, null buffers, freeze without assoc or
- * scratch smaller than gsdf_keyframe_scratch_bytes. */
+ * scratch smaller than gsdf_keyframe_scratch_bytes(cam, K, param_blocks). */
 int gsdf_keyframe_loss(const gsdf_map* map, const float* depth_dev, int32_t n_keyframes,
                        const gsdf_camera* cam, const double* T0_dev, const double* xi_dev,
                        const float* params_dev, int64_t param_blocks, float huber_delta,
@@ -314,7 +317,8 @@ int gsdf_keyframe_loss(const gsdf_map* map, const float* depth_dev, int32_t n_ke
  *     (K x 6 float64, overwritten; Jl the left Jacobian of SE(3)),
  *   loss_dev (optional) as gsdf_keyframe_loss.
  * The voxel sums are exact (fixed point) and each voxel is written by one
- * thread, so the results are the same bits on every run.  freeze = 1 reads
+ * thread; the keyframe sums are reduced in a fixed order; so the results
+ * are the same bits on every run.  freeze = 1 reads
  * the association from assoc_dev; with freeze = 0 each pixel's nearest
  * voxel is used and assoc_dev is neither read nor written (the loss call
  * writes it).  Other argument rules as for gsdf_keyframe_loss. */

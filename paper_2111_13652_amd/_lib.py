@@ -75,7 +75,7 @@ _SIGNATURES = {
     "gsdf_import_params": (_I, [C.POINTER(Map), _P, C.c_int64, _P]),
     "gsdf_voxel_order": (_I, [_P]),
     "gsdf_compose_poses": (_I, [_I32, _P, _P, _P, _P]),
-    "gsdf_keyframe_scratch_bytes": (_SZ, [C.POINTER(Camera), _I32]),
+    "gsdf_keyframe_scratch_bytes": (_SZ, [C.POINTER(Camera), _I32, C.c_int64]),
     "gsdf_keyframe_loss": (_I, [C.POINTER(Map), _P, _I32, C.POINTER(Camera), _P, _P, _P, C.c_int64,
                                 C.c_float, _P, _I32, _P, _P, _P, _SZ, _P]),
     "gsdf_backward": (_I, [C.POINTER(Map), _P, _I32, C.POINTER(Camera), _P, _P, _P, C.c_int64,

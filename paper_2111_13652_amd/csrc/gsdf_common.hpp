@@ -238,6 +238,19 @@ __device__ inline float load_voxel(const MapView& M, int storage, int64_t vi, fl
     return Wv;
 }
 
+// XCD-aware order of work-groups: MI355X dispatches work-groups to its 8
+// XCDs in turn (b on XCD b mod 8), each XCD with its own L2.  band_rank(b,
+// n) is a permutation of 0 .. n-1 that gives the work-groups of one XCD
+// consecutive ranks, so that work-groups that read neighbouring data (the
+// same map blocks) share an L2.
+constexpr int kXcds = 8;
+__device__ inline int band_rank(int b, int n) {
+    const int x = b % kXcds;
+    int start = 0;
+    for (int y = 0; y < x; ++y) start += (n - y + kXcds - 1) / kXcds;   // work-groups on XCD y
+    return start + b / kXcds;
+}
+
 // Pool slot of block (bx,by,bz), or -1.  Linear probing; an empty slot ends
 // the search.  Only valid after the kernel that inserted the key finished.
 __device__ inline int32_t hash_find(const MapView& M, int bx, int by, int bz) {

@@ -58,5 +58,6 @@ inline int launch_status() {
 }
 
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace gsdf

@@ -903,18 +903,10 @@ __device__ inline int level_groups(const TrackLevel& L, int G) {
 }
 
 // Rank in the image of member b of n: the members split the level's pixels
-// into n contiguous chunks, and rank orders them so that the members on one
-// XCD take neighbouring chunks.  MI355X dispatches work-groups to its 8 XCDs
-// in turn (b on XCD b mod 8), each XCD with its own L2, so each L2 then
-// holds the voxels seen by one band of the image instead of the whole
-// visible map.  Any n gives a permutation of 0 .. n-1.
-constexpr int kXcds = 8;
-__device__ inline int band_rank(int b, int n) {
-    const int x = b % kXcds;
-    int start = 0;
-    for (int y = 0; y < x; ++y) start += (n - y + kXcds - 1) / kXcds;   // members on XCD y
-    return start + b / kXcds;
-}
+// into n contiguous chunks, and band_rank (XCD-aware order of work-groups)
+// orders them so that the members on one XCD take neighbouring chunks; each
+// L2 then holds the voxels seen by one band of the image instead of the
+// whole visible map.
 
 // The whole coarse-to-fine Gauss-Newton of one frame (one launch, one work-group per CU).
 //

@@ -241,7 +241,7 @@ class GsdfMap:
     def _keyframe_scratch(self, c: _lib.Camera, K: int) -> torch.Tensor:
         key = ("kf", c.width, c.height, K)
         if key not in self._scratch:
-            n = _lib.load().gsdf_keyframe_scratch_bytes(C.byref(c), int(K))
+            n = _lib.load().gsdf_keyframe_scratch_bytes(C.byref(c), int(K), self.max_blocks)
             if n == 0:
                 raise ValueError("invalid camera / keyframe count")
             self._scratch[key] = torch.empty(int(n), dtype=torch.uint8, device=self.device)

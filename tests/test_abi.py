@@ -73,8 +73,12 @@ def test_voxel_order_and_differentiable_calls_validate_without_gpu():
         idx = np.sort(order[cube == k])
         assert idx[-1] - idx[0] == 7
     cam = _lib.Camera(525.0, 525.0, 319.5, 239.5, 640, 480, 0.4, 4.0)
-    assert lib.gsdf_keyframe_scratch_bytes(C.byref(cam), 10) > 0
-    assert lib.gsdf_keyframe_scratch_bytes(C.byref(cam), 0) == 0
+    assert lib.gsdf_keyframe_scratch_bytes(C.byref(cam), 10, 40000) > lib.gsdf_keyframe_scratch_bytes(
+        C.byref(cam), 10, 100) > 0
+    assert lib.gsdf_keyframe_scratch_bytes(C.byref(cam), 0, 100) == 0
+    assert lib.gsdf_keyframe_scratch_bytes(C.byref(cam), 10, -1) == 0
+    # pixels are numbered in int32: K x W x H beyond INT32_MAX is refused
+    assert lib.gsdf_keyframe_scratch_bytes(C.byref(cam), 7000, 100) == 0
     assert lib.gsdf_keyframe_loss(None, None, 1, C.byref(cam), None, None, None, 0, 0.01, None, 0, None,
                                   None, None, 0, None) == _lib.EINVAL
     assert lib.gsdf_backward(None, None, 1, C.byref(cam), None, None, None, 0, 0.01, None, 0, None,

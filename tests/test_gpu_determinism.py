@@ -72,3 +72,31 @@ def test_adjoint_is_bit_reproducible(stream, freeze):
         out.append((params.grad.clone(), xi.grad.clone()))
     assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
     assert out[0][0].abs().sum().item() > 0
+
+
+def test_adjoint_over_several_scan_tiles_is_unchanged(stream):
+    """Parameter rows beyond the map's blocks are unobserved: padding the
+    buffer to more than three scan tiles of block counts (4096 blocks each)
+    changes no bit of the gradients of the real rows and gives zero
+    gradients on the padding."""
+    import torch
+    from paper_2111_13652_amd.gsdf import GsdfMap, KeyframeLoss
+    st = stream
+    G = GsdfMap(0.01, 0.05, 20000)
+    for f in range(6):
+        G.fuse(dev(st.depth[f]), st.cam, dev(st.poses[f]))
+    idx = [6, 8]
+    T0 = dev(np.stack([synth.perturb_pose(st.poses[f], 70 + i, 1.0, 0.01) for i, f in enumerate(idx)]))
+    D = dev(st.depth[idx])
+    nb = G.num_blocks()
+    log(f"case: adjoint, 2 keyframes, {nb} parameter rows and 3 x 4096 + 5 rows")
+    out = []
+    for rows in (nb, 3 * 4096 + 5):
+        params = G.export_params(rows).requires_grad_(True)
+        xi = torch.full((len(idx), 6), 1e-3, dtype=torch.float64, device="cuda").requires_grad_(True)
+        KeyframeLoss.apply(params, xi, G, D, st.cam, T0, 0.01).sum().backward()
+        torch.cuda.synchronize()
+        out.append((params.grad.clone(), xi.grad.clone()))
+    assert torch.equal(out[0][0], out[1][0][:nb]) and torch.equal(out[0][1], out[1][1])
+    assert not out[1][0][nb:].any()
+    assert out[0][0].abs().sum().item() > 0
