@@ -31,7 +31,7 @@ namespace gsdf {
 
 constexpr int kNE = 30;          // 21 H + 6 b + energy + used + valid
 constexpr int kPartStride = 32;  // doubles per work-group partial
-constexpr int kTrackBlock = 256;
+constexpr int kTrackBlock = 512;
 constexpr int kMaxGroups = 2048;
 constexpr unsigned kJoinPolls = 1u << 24;   // default bounds of the waits
 constexpr unsigned kTagPolls = 1u << 20;
@@ -428,19 +428,24 @@ __device__ inline void accumulate_trilinear(const MapView& M, const TrackLevel& 
 }
 
 // Work-group sum: every thread writes its kNE sums to LDS (one transpose),
-// then 8 threads per entry add 32 values each with independent LDS reads,
-// and the first kNE threads combine the 8 parts and store the work-group
-// partial with device-scope stores.  (Cross-lane shuffles of doubles would
-// chain ~180 dependent LDS permutes per wave.)  The plain path adds in
-// float64; the precision form (COMP) uses compensated float32 at every
-// stage.  The storing threads are lanes of wave 0, so thread 0 (which takes
-// the arrival ticket, where there is one) waits for their completion before
-// signalling.
+// then 8 threads per entry add kRedChunk values each with independent LDS
+// reads, and the first kNE threads combine the 8 parts and store the
+// work-group partial with device-scope stores.  (Cross-lane shuffles of
+// doubles would chain ~180 dependent LDS permutes per wave.)  Each entry's
+// row is 8 chunks of kRedChunk values, kRedPad floats apart, so that the 8
+// lanes of one 16-byte read pass (the 8 chunks of an entry) fall in
+// different banks.  The plain path adds in float64; the precision form
+// (COMP) uses compensated float32 at every stage.  The storing threads are
+// lanes of wave 0, so thread 0 (which takes the arrival ticket, where there
+// is one) waits for their completion before signalling.
+constexpr int kRedChunk = kTrackBlock / 8;
+constexpr int kRedPad = kRedChunk + 4;
 struct ReduceLds {
-    float v[kNE][kTrackBlock];
+    float v[kNE][8 * kRedPad];
     double part[kNE][8];
     double tot[kNE];
 };
+__device__ inline int red_slot(int t) { return (t / kRedChunk) * kRedPad + t % kRedChunk; }
 
 // Partials and leaf sums of the tracking kernel carry the iteration they
 // belong to: the low 16 bits of each float64 word (a relative change below
@@ -457,19 +462,20 @@ __device__ inline double untag_word(unsigned long long w) { return __longlong_as
 template <bool COMP>
 __device__ inline void store_partial(const float acc[kNE], const float cmp[kNE], double* partial,
                                      ReduceLds& r, unsigned long long tag = 0) {
+    const int slot = red_slot(threadIdx.x);
 #pragma unroll
-    for (int k = 0; k < kNE; ++k) r.v[k][threadIdx.x] = COMP ? acc[k] - cmp[k] : acc[k];
+    for (int k = 0; k < kNE; ++k) r.v[k][slot] = COMP ? acc[k] - cmp[k] : acc[k];
     __syncthreads();
     if (threadIdx.x < kNE * 8) {
         const int k = threadIdx.x >> 3, p = threadIdx.x & 7;
-        const float4* src = reinterpret_cast<const float4*>(&r.v[k][p * (kTrackBlock / 8)]);
-        float4 q[kTrackBlock / 32];
+        const float4* src = reinterpret_cast<const float4*>(&r.v[k][p * kRedPad]);
+        float4 q[kRedChunk / 4];
 #pragma unroll
-        for (int j = 0; j < kTrackBlock / 32; ++j) q[j] = src[j];
+        for (int j = 0; j < kRedChunk / 4; ++j) q[j] = src[j];
         if (COMP) {
             Kahan ks;
 #pragma unroll
-            for (int j = 0; j < kTrackBlock / 32; ++j) {
+            for (int j = 0; j < kRedChunk / 4; ++j) {
                 ks.add(q[j].x);
                 ks.add(q[j].y);
                 ks.add(q[j].z);
@@ -479,7 +485,7 @@ __device__ inline void store_partial(const float acc[kNE], const float cmp[kNE],
         } else {
             double s = 0.0;
 #pragma unroll
-            for (int j = 0; j < kTrackBlock / 32; ++j)
+            for (int j = 0; j < kRedChunk / 4; ++j)
                 s += ((double)q[j].x + (double)q[j].y) + ((double)q[j].z + (double)q[j].w);
             r.part[k][p] = s;
         }
@@ -1185,7 +1191,7 @@ inline int normal_eq_groups(int npx) {
 // Work-group count of the tracking kernel: one per CU of the current
 // device (queried on every call; the runtime answers from its own device
 // table).  The work-groups wait for each other, so all of them must be
-// resident at once.  A work-group needs 256 threads (one wave per SIMD) and
+// resident at once.  A work-group needs 512 threads (two waves per SIMD) and
 // less LDS than a CU holds (checked below at compile time), so an idle CU
 // always takes one.  The kernel is launched like any other on the stream (a
 // cooperative launch costs about 15 us more per frame in dispatch, measured
@@ -1193,7 +1199,7 @@ inline int normal_eq_groups(int npx) {
 // work-groups start late, and every wait is bounded, so the worst case is a
 // frame that fails with GSDF_EHIP.
 constexpr size_t kTrackLds = sizeof(ReduceLds) + sizeof(float) * kTrackBatch * kTrackBlock + 16 * sizeof(double);
-static_assert(kTrackLds <= 64 * 1024, "the tracking work-group must fit one CU's LDS");
+static_assert(kTrackLds <= 160 * 1024, "the tracking work-group must fit one CU's LDS (160 KB on gfx950)");
 inline int track_groups() {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
