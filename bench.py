@@ -18,6 +18,9 @@ Prints one JSON line.  Besides the contract's keys:
   "kernels"       per-kernel event times from a second pass over the timed
                   frames with every kernel timed (not part of "value": events
                   around every launch cost about 9 % of the frame rate);
+  "track_iterations"  where a tracking launch's time goes, per pyramid
+                  level: work-group 0's wall-clock stamps after its pixel
+                  sums, its part of the exchange, the total and the solve;
   "full_stream"   three passes over the whole 100-frame stream (median);
   "differentiation"  forward + adjoint over keyframes 0, 10, ..., 90 on the
                   100-frame map;
@@ -62,7 +65,17 @@ B_ALLOC_PAIR = 16.0
 # for a plain 256 MiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  A
 # figure is reported only while the kernel's sources still hash to the
 # values they had when the counters were taken.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    "track": {
+        "bytes": 10249212,
+        "sources": {
+            "gsdf_track.hip": "eb3c44df7287c3a6a4710cb0f81a2b4e9048a8308b67f556f8cf3ed68912f20b",
+            "gsdf_common.hpp": "efda03b524d911e68a0b8c49aa56de3c855f2706a6411dfa9f09707c6bdd46cd",
+            "gsdf_host.hpp": "699a644f6155d591caffb7f5edc3cd6c971c32bc580d070b327d1d31c947ff6e",
+            "gsdf_se3.hpp": "13c15ea94701e1129da7175cf338be9aa9cc57bf8857172577cef813f6209733"
+        }
+    }
+}
 
 
 def _traffic(kernel: str, storage: str):
@@ -219,6 +232,37 @@ def main():
         torch.cuda.synchronize()
         kernels = read_kernels(m)
         m.timing(0)
+
+    # ---- per-iteration breakdown of the tracking launch: the same frames
+    # again, work-group 0 stamping the device wall clock after its pixel
+    # sums, its part of the exchange, the total and the solve (outside the
+    # timed region)
+    iteration_clocks = None
+    if timing:
+        from paper_2111_13652_amd.gsdf import wall_clock_khz
+        n_it = sum(iters[:levels])
+        clk = torch.zeros((K, 4 * n_it), dtype=torch.int64, device=dev)
+        start(m)
+        for j, f in enumerate(range(first, first + K)):
+            m.track(depth[f], cam, est[f], levels=levels, iters=iters, delta=delta, init=est[f - 1], clocks=clk[j])
+            m.fuse(depth[f], cam, est[f])
+        torch.cuda.synchronize()
+        t = np.median(clk.cpu().numpy().reshape(K, n_it, 4).astype(np.float64), axis=0) * (1e3 / wall_clock_khz())
+        prev = np.concatenate([[0.0], t[:-1, 3]])
+        parts = np.stack([t[:, 0] - prev, t[:, 1] - t[:, 0], t[:, 2] - t[:, 1], t[:, 3] - t[:, 2]], axis=1)
+        lv, i0 = [], 0
+        for l in range(levels - 1, -1, -1):   # levels run coarse to fine
+            n = iters[l]
+            if n:
+                mean = parts[i0:i0 + n].mean(axis=0)
+                lv.append({"level": l, "iterations": n, "pixel_sums_us": mean[0], "exchange_us": mean[1],
+                           "total_us": mean[2], "solve_us": mean[3]})
+            i0 += n
+        iteration_clocks = {"frames": K, "work_group": 0, "frame_us": float(t[-1, 3]), "levels": lv,
+                            "meaning": "per iteration (mean over the level's iterations, median over frames): "
+                                       "pixel sums = accumulate + the wait for the work-group's own waves; "
+                                       "exchange = partial stored and (leaf leaders) the leaf's partials summed "
+                                       "and stored; total = the leaf sums read; solve = 6x6 solve and pose update"}
 
     # ---- algorithmic bytes, from the live work counters
     npx = cam.width * cam.height
@@ -422,6 +466,7 @@ def main():
                            "alloc_pairs": work[4] / K, "track_valid_px_iters": work[5] / K,
                            "track_used_px_iters": work[6] / K},
         "kernels": kernels,
+        "track_iterations": iteration_clocks,
     }
     print(json.dumps(report), flush=True)
 

@@ -127,6 +127,13 @@ typedef struct gsdf_track_params {
                              /* groups before the frame is given up with          */
                              /* GSDF_EHIP; 0 = the library default (2^20 for the  */
                              /* per-iteration sums, 2^24 for a level boundary)    */
+    uint64_t* iter_clocks;   /* optional (device, 4 per iteration in execution    */
+                             /* order): ticks of the device wall clock since the  */
+                             /* launch started, as work-group 0 sees them after   */
+                             /* its pixel sums, after its part of the exchange    */
+                             /* (its partial stored, and for a leaf leader the    */
+                             /* leaf sum too), after the total, after the solve;  */
+                             /* rate from gsdf_wall_clock_khz.  NULL: not taken   */
 } gsdf_track_params;
 
 /* Residual model of tracking (Sec. 4.1). */
@@ -195,6 +202,10 @@ int gsdf_integrate_frame(gsdf_map* map, const float* depth_dev, const gsdf_camer
 int gsdf_fuse_frame(gsdf_map* map, const float* depth_dev, const gsdf_camera* cam, const double* T_wc_dev,
                     const gsdf_fuse_params* params, void* scratch_dev, size_t scratch_bytes,
                     int32_t* status_dev, void* stream);
+
+/* Host call: rate of the device wall clock that iter_clocks counts, in kHz
+ * (100000 on MI355X), for the current device. */
+int gsdf_wall_clock_khz(int32_t* khz_out);
 
 /* Scratch bytes gsdf_track_frame / gsdf_normal_equations need for `cam`. */
 size_t gsdf_track_scratch_bytes(const gsdf_camera* cam, int32_t levels);

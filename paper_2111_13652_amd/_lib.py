@@ -42,7 +42,7 @@ class FuseParams(C.Structure):
 class TrackParams(C.Structure):
     _fields_ = [("levels", C.c_int32), ("iters", C.c_int32 * 4), ("huber_delta", C.c_float),
                 ("damping", C.c_double), ("min_inlier_frac", C.c_float), ("model", C.c_int32),
-                ("max_polls", C.c_int32)]
+                ("max_polls", C.c_int32), ("iter_clocks", C.c_void_p)]
 
 
 _P = C.c_void_p
@@ -56,6 +56,7 @@ _SIGNATURES = {
     "gsdf_map_num_blocks": (_I, [C.POINTER(Map), _P, _P]),
     "gsdf_allocate_blocks": (_I, [C.POINTER(Map), _P, C.POINTER(Camera), _P, _P, _P]),
     "gsdf_integrate_scratch_bytes": (_SZ, [C.POINTER(Camera)]),
+    "gsdf_wall_clock_khz": (_I, [C.POINTER(_I32)]),
     "gsdf_integrate_frame": (_I, [C.POINTER(Map), _P, C.POINTER(Camera), _P, C.POINTER(FuseParams), _P,
                                   _SZ, _P, _P]),
     "gsdf_fuse_frame": (_I, [C.POINTER(Map), _P, C.POINTER(Camera), _P, C.POINTER(FuseParams), _P,

@@ -52,6 +52,7 @@ struct TrackArgs {
     float min_inlier_frac;
     unsigned tag_polls;    // bound on the polls of one tagged word
     unsigned join_polls;   // bound on the polls of the level-boundary pose
+    unsigned long long* clocks;   // optional per-iteration wall-clock stamps of work-group 0
 };
 
 // Compensated (Kahan) float32 accumulation: after any number of add()s,
@@ -958,6 +959,9 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
     }
     int gi = 0;           // global iteration index
     int have = 0;         // iterations the pose in s_pose reflects
+    // per-iteration stamps (work-group 0, thread 0), when asked for
+    const bool stamp = a.clocks && blockIdx.x == 0 && threadIdx.x == 0;
+    const unsigned long long t0 = stamp ? wall_clock64() : 0ull;
     for (int l = a.levels - 1; l >= 0; --l) {
         if (a.iters[l] == 0) continue;
         const TrackLevel L = a.lv[l];
@@ -1011,15 +1015,18 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
             else
                 accumulate<STORAGE>(M, L, a, P, first, kTrackBlock, c1, s_depth, acc, cmp);
             const unsigned long long tag = (unsigned long long)(gi + 1);
+            if (stamp) a.clocks[4 * gi] = wall_clock64() - t0;
             // every member: the same sum of the leaf sums, the same solve
-            if (!contribute<COMP>(acc, cmp, part, leafpart, Gl, sync, a.tag_polls, red, tag) ||
-                !total_leaves<COMP>(leafpart, nleaf, tag, sync, a.tag_polls, red)) {
+            const bool part_ok = contribute<COMP>(acc, cmp, part, leafpart, Gl, sync, a.tag_polls, red, tag);
+            if (stamp) a.clocks[4 * gi + 1] = wall_clock64() - t0;
+            if (!part_ok || !total_leaves<COMP>(leafpart, nleaf, tag, sync, a.tag_polls, red)) {
                 if (threadIdx.x == 0) {
                     __hip_atomic_store(&sync[kSyncAbort], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     raise_status(status, GSDF_EHIP);
                 }
                 return;
             }
+            if (stamp) a.clocks[4 * gi + 2] = wall_clock64() - t0;
             if (threadIdx.x < 64) {
                 const bool solved = solve_update_wave(red.tot, a.damping, s_pose);
                 if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1033,6 +1040,7 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
                     }
                     add_stat(M, kStatTrackValid, (unsigned long long)t[29]);
                     add_stat(M, kStatTrackUsed, (unsigned long long)t[28]);
+                    if (stamp) a.clocks[4 * gi + 3] = wall_clock64() - t0;
                 }
             }
             __syncthreads();
@@ -1263,6 +1271,16 @@ inline void fill_levels(const gsdf_camera& cam, const float* depth, const Scratc
 
 using namespace gsdf;
 
+extern "C" int gsdf_wall_clock_khz(int32_t* khz_out) {
+    if (!khz_out) return GSDF_EINVAL;
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
+        return GSDF_EHIP;
+    *khz_out = khz;
+    return GSDF_OK;
+}
+
 extern "C" size_t gsdf_track_scratch_bytes(const gsdf_camera* cam, int32_t levels) {
     if (!valid_cam(cam) || levels < 1 || levels > 4) return 0;
     return scratch_layout(*cam, levels).total;
@@ -1306,6 +1324,7 @@ int track_frame_on(const gsdf_map* map, const float* depth_dev, const gsdf_camer
     a.min_inlier_frac = params->min_inlier_frac;
     a.tag_polls = params->max_polls > 0 ? (unsigned)params->max_polls : kTagPolls;
     a.join_polls = params->max_polls > 0 ? (unsigned)params->max_polls : kJoinPolls;
+    a.clocks = reinterpret_cast<unsigned long long*>(params->iter_clocks);
 
     {
         PyramidArgs p;
@@ -1414,6 +1433,7 @@ extern "C" int gsdf_normal_equations(const gsdf_map* map, const float* depth_dev
     a.min_inlier_frac = 0.0f;
     a.tag_polls = kTagPolls;
     a.join_polls = kJoinPolls;
+    a.clocks = nullptr;
     PyramidArgs p = {};
     p.levels = 1;
     p.sync = sync;

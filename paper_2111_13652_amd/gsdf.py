@@ -182,13 +182,16 @@ class GsdfMap:
     def track(self, depth: torch.Tensor, cam, pose: torch.Tensor, levels: int = 3,
               iters: Sequence[int] = (4, 5, 10), delta: float = 0.01, damping: float = 1e-6,
               min_inlier_frac: float = 0.1, stats: Optional[torch.Tensor] = None,
-              init: Optional[torch.Tensor] = None, model: str = "taylor", max_polls: int = 0) -> None:
+              init: Optional[torch.Tensor] = None, model: str = "taylor", max_polls: int = 0,
+              clocks: Optional[torch.Tensor] = None) -> None:
         """Coarse-to-fine tracking; ``pose`` (3x4 float64, device) receives
         the estimate, starting from ``init`` (default: ``pose`` itself, updated
         in place).  ``iters[l]`` iterations at level l (0 = finest).  ``model``:
         "taylor" (one voxel, Eq. (14)-(16)) or "trilinear" (eight voxels,
         Eq. (12)-(13), the comparison model).  ``max_polls`` bounds each
-        wait between work-groups (0: the library default)."""
+        wait between work-groups (0: the library default).  ``clocks``
+        (int64, device, 4 per iteration): per-iteration wall-clock stamps of
+        work-group 0 (see wall_clock_khz)."""
         c = camera(cam)
         _need(depth, torch.float32, (c.height, c.width), "depth")
         _need(pose, torch.float64, (3, 4), "pose")
@@ -200,8 +203,13 @@ class GsdfMap:
             _need(stats, torch.float32, None, "stats")
             if stats.numel() < 2 * sum(it[:levels]):
                 raise ValueError("stats too small")
+        if clocks is not None:
+            _need(clocks, torch.int64, None, "clocks")
+            if clocks.numel() < 4 * sum(it[:levels]):
+                raise ValueError("clocks too small")
         p = _lib.TrackParams(int(levels), (C.c_int32 * 4)(*it[:4]), float(delta), float(damping),
-                             float(min_inlier_frac), {"taylor": 0, "trilinear": 1}[model], int(max_polls))
+                             float(min_inlier_frac), {"taylor": 0, "trilinear": 1}[model], int(max_polls),
+                             _ptr(clocks))
         scratch = self._scratch_for(c, levels)
         _lib.check(_lib.load().gsdf_track_frame(C.byref(self._map), _ptr(depth), C.byref(c),
                                                  C.byref(p), _ptr(init), _ptr(pose), _ptr(stats), _ptr(scratch),
@@ -341,6 +349,13 @@ def _kf_args(gmap: GsdfMap, depth, cam, T0, xi, params, assoc):
     if assoc is not None:
         _need(assoc, torch.int32, (K, c.height, c.width, 3), "assoc")
     return c, K
+
+
+def wall_clock_khz() -> int:
+    """Rate of the device wall clock that the tracking stamps count, in kHz."""
+    khz = C.c_int32(0)
+    _lib.check(_lib.load().gsdf_wall_clock_khz(C.byref(khz)), "wall_clock_khz")
+    return int(khz.value)
 
 
 def keyframe_loss(gmap: GsdfMap, params: torch.Tensor, xi: torch.Tensor, depth: torch.Tensor, cam,

@@ -100,3 +100,30 @@ def test_adjoint_over_several_scan_tiles_is_unchanged(stream):
     assert torch.equal(out[0][0], out[1][0][:nb]) and torch.equal(out[0][1], out[1][1])
     assert not out[1][0][nb:].any()
     assert out[0][0].abs().sum().item() > 0
+
+
+def test_iteration_clocks_change_no_bit_of_the_pose(stream):
+    """Tracking with the per-iteration wall-clock stamps (work-group 0) gives
+    the pose of the same call without them, bit for bit; the stamps are
+    non-decreasing (four per iteration) and positive."""
+    import torch
+    from paper_2111_13652_amd.gsdf import GsdfMap, wall_clock_khz
+    st = stream
+    G = GsdfMap(0.01, 0.05, 60000)
+    for f in range(4):
+        G.fuse(dev(st.depth[f]), st.cam, dev(st.poses[f]))
+    log("case: tracking frame 4 with and without iteration clocks (3 levels, 4/5/10)")
+    clk = torch.zeros(4 * 19, dtype=torch.int64, device="cuda")
+    P1 = dev(st.poses[3].copy())
+    P2 = dev(st.poses[3].copy())
+    G.track(dev(st.depth[4]), st.cam, P1)
+    G.track(dev(st.depth[4]), st.cam, P2, clocks=clk)
+    torch.cuda.synchronize()
+    assert torch.equal(P1, P2)
+    c = clk.cpu().numpy()
+    assert (c > 0).all() and (np.diff(c) >= 0).all()
+    khz = wall_clock_khz()
+    assert khz > 0
+    log(f"  launch {c[-1] * 1e3 / khz:.1f} us by work-group 0's clock ({khz} kHz)")
+    with pytest.raises(ValueError):
+        G.track(dev(st.depth[4]), st.cam, P2, clocks=clk[:10])
