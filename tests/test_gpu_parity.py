@@ -259,6 +259,63 @@ def test_fuse_frame_equals_allocate_then_integrate(torch_mod, room_stream, stora
     assert A.status_flags() == [] and B.status_flags() == []
 
 
+def _tile_block_counts(depth, cam, vs, T):
+    """Distinct blocks touched by the ray bands of each 16x16 pixel tile
+    (the binary32 band rule of gsdf_allocate_blocks at the identity pose,
+    every sample counted; a repeated voxel never adds a block)."""
+    f32 = np.float32
+    H, W = depth.shape
+    ns = int(np.floor(2 * T / (vs / 2) + 0.5)) + 1
+    v, u = np.mgrid[0:H, 0:W]
+    xr = (u.astype(f32) - f32(cam.cx)) * f32(1 / cam.fx)
+    yr = (v.astype(f32) - f32(cam.cy)) * f32(1 / cam.fy)
+    D = depth.astype(f32)
+    ty, tx = v // 16, u // 16
+    seen = set()
+    for k in range(ns):
+        z = (D - f32(T)) + f32(k) * f32(vs / 2)
+        m = [np.floor(q * f32(1 / vs) + f32(0.5)).astype(np.int64) >> 3 for q in (z * xr, z * yr, z)]
+        seen.update(zip(ty.ravel(), tx.ravel(), m[0].ravel(), m[1].ravel(), m[2].ravel()))
+    counts = {}
+    for t in seen:
+        counts[t[:2]] = counts.get(t[:2], 0) + 1
+    return counts
+
+
+def test_fuse_frame_when_tiles_touch_more_blocks_than_their_key_set(torch_mod):
+    """A tilted plane seen through 0.5 mm voxels and a 15 mm band: every
+    16x16 tile's bands cross about 3000 distinct blocks, more than the
+    allocation's 1024-key LDS set per tile holds, so keys go to the global
+    table directly; gsdf_fuse_frame still leaves the map that
+    gsdf_allocate_blocks + gsdf_integrate_frame leave, bit for bit."""
+    cam = synth.Camera(60.0, 60.0, 31.5, 31.5, 64, 64, 0.1, 4.0)
+    v, u = np.mgrid[0:64, 0:64]
+    depth = (0.5 / (1.0 - 0.3 * (u - cam.cx) / cam.fx)).astype(np.float32)
+    vs, T = 0.0005, 0.015
+    counts = _tile_block_counts(depth, cam, vs, T)
+    log(f"case: tilted plane 64x64, 0.5 mm voxels, T 15 mm; blocks per tile {min(counts.values())}"
+        f"-{max(counts.values())}")
+    assert min(counts.values()) > 1024
+    pose = np.hstack([np.eye(3), np.zeros((3, 1))])
+    A = _gpu_map(vs, T, max_blocks=1 << 16)
+    B = _gpu_map(vs, T, max_blocks=1 << 16)
+    D, P = dev(depth), dev(pose)
+    A.allocate(D, cam, P)
+    A.integrate(D, cam, P)
+    B.fuse(D, cam, P)
+    ka, kb = A.keys(), B.keys()
+    assert len(ka) > 40000
+    oa, ob = np.lexsort(ka.T[::-1]), np.lexsort(kb.T[::-1])
+    np.testing.assert_array_equal(ka[oa], kb[ob])
+    va, vb = A.voxels(len(ka)), B.voxels(len(kb))
+    for xa, xb in zip(va, vb):
+        np.testing.assert_array_equal(xa[oa], xb[ob])
+    c = A.counters()
+    np.testing.assert_array_equal(c, B.counters())
+    assert c[0] > 0
+    assert A.status_flags() == [] and B.status_flags() == []
+
+
 @pytest.mark.parametrize("levels,iters", [(3, (4, 0, 10)), (3, (0, 5, 10)), (3, (4, 5, 0)), (4, (2, 2, 3, 6))])
 def test_track_level_schedules(torch_mod, room_stream, levels, iters):
     """Schedules with skipped or extra levels: work-groups join later levels
