@@ -1,8 +1,10 @@
 """The differentiable form on the GPU through the C ABI: keyframe loss and
-its adjoint (per-voxel psi/g gradients scatter-added at the voxel's slot,
-keyframe twist gradients through the SE(3) left Jacobian) against the FP64
-oracle, against central finite differences of the GPU loss itself, and as
-the driver of keyframe pose refinement."""
+its adjoint (per-voxel psi/g gradients summed per map block and added at
+the voxel's slot, keyframe twist gradients through the SE(3) left Jacobian)
+against the FP64 oracle, against central finite differences of the GPU loss
+itself, and as the driver of keyframe pose refinement.  The cases cover
+ragged tiles, more keyframes than the adjoint keeps in LDS, and more pixel
+tiles than work-groups per keyframe."""
 import numpy as np
 import pytest
 
@@ -66,6 +68,25 @@ def test_loss_and_gradients_on_a_ragged_image(torch_mod):
     st = synth.make_stream(cam, 8, 1, 2, 3)
     O, G = _oracle_and_gpu_maps(st, range(4))
     _check_against_oracle(torch_mod, O, G, st, (4, 5, 7), 13)
+
+
+def test_loss_and_gradients_with_more_keyframes_than_the_lds_pose_table(torch_mod):
+    """68 keyframes (the adjoint keeps at most 64 keyframe poses in LDS and
+    reads the others from memory) on an 80x60 image."""
+    cam = synth.Camera(65.6, 65.6, 39.5, 29.5, 80, 60, 0.4, 4.0)
+    st = synth.make_stream(cam, 8, 1, 2, 3)
+    O, G = _oracle_and_gpu_maps(st, range(4))
+    _check_against_oracle(torch_mod, O, G, st, [4, 5, 6, 7] * 17, 17)
+
+
+def test_loss_and_gradients_on_an_image_of_more_than_512_tiles(torch_mod):
+    """A 1056x800 image: 33 x 25 = 825 tiles of 32x32 pixels, more than the
+    512 work-groups per keyframe of the pixel passes, so a work-group takes
+    two tiles."""
+    cam = synth.Camera(866.0, 866.0, 527.5, 399.5, 1056, 800, 0.4, 4.0)
+    st = synth.make_stream(cam, 6, 1, 2, 3)
+    O, G = _oracle_and_gpu_maps(st, range(3))
+    _check_against_oracle(torch_mod, O, G, st, (3, 5), 19)
 
 
 def _check_against_oracle(torch, O, G, st, idx, seed):
