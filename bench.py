@@ -67,10 +67,10 @@ B_ALLOC_PAIR = 16.0
 # values they had when the counters were taken.
 MEASURED_TRAFFIC = {
     "track": {
-        "bytes": 10249212,
+        "bytes": 8445557,
         "sources": {
-            "gsdf_track.hip": "eb3c44df7287c3a6a4710cb0f81a2b4e9048a8308b67f556f8cf3ed68912f20b",
-            "gsdf_common.hpp": "efda03b524d911e68a0b8c49aa56de3c855f2706a6411dfa9f09707c6bdd46cd",
+            "gsdf_track.hip": "bf1db70084a2e555e64e6ab3237bb84c877e6b1dafb1d0b6cacbe6531d8a97a4",
+            "gsdf_common.hpp": "5b726ce79643b29c9a682a0b6bcd966907429c824ecb04562facf2ef58d23989",
             "gsdf_host.hpp": "699a644f6155d591caffb7f5edc3cd6c971c32bc580d070b327d1d31c947ff6e",
             "gsdf_se3.hpp": "13c15ea94701e1129da7175cf338be9aa9cc57bf8857172577cef813f6209733"
         }

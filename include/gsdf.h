@@ -134,6 +134,11 @@ typedef struct gsdf_track_params {
                              /* (its partial stored, and for a leaf leader the    */
                              /* leaf sum too), after the total, after the solve;  */
                              /* rate from gsdf_wall_clock_khz.  NULL: not taken   */
+    int32_t exchange_device_scope; /* nonzero: every per-iteration partial sum   */
+                             /* goes through device-scope memory instead of the   */
+                             /* L2 of the XCD its leaf shares (the same sums in   */
+                             /* the same order, so the same pose bits; slower).   */
+                             /* 0 is the normal setting                           */
 } gsdf_track_params;
 
 /* Residual model of tracking (Sec. 4.1). */

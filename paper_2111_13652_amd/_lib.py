@@ -42,7 +42,7 @@ class FuseParams(C.Structure):
 class TrackParams(C.Structure):
     _fields_ = [("levels", C.c_int32), ("iters", C.c_int32 * 4), ("huber_delta", C.c_float),
                 ("damping", C.c_double), ("min_inlier_frac", C.c_float), ("model", C.c_int32),
-                ("max_polls", C.c_int32), ("iter_clocks", C.c_void_p)]
+                ("max_polls", C.c_int32), ("iter_clocks", C.c_void_p), ("exchange_device_scope", C.c_int32)]
 
 
 _P = C.c_void_p

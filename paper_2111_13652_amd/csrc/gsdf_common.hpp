@@ -251,6 +251,9 @@ __device__ inline int band_rank(int b, int n) {
     return start + b / kXcds;
 }
 
+// Hardware id (0..7) of the XCD the calling wave runs on (register XCC_ID).
+__device__ inline unsigned xcc_id() { return (unsigned)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xfu; }
+
 // Pool slot of block (bx,by,bz), or -1.  Linear probing; an empty slot ends
 // the search.  Only valid after the kernel that inserted the key finished.
 __device__ inline int32_t hash_find(const MapView& M, int bx, int by, int bz) {

@@ -10,9 +10,10 @@
 // of H = sum w J J^T, the 6 of b = sum w J r, the energy, the count of
 // pixels used and the count of valid pixels.  From there every sum is
 // float64: LDS across the waves of a work-group, then one partial per
-// work-group, then one sum per leaf of kLeaf work-groups (added by the
-// first work-group of the leaf once every partial of the leaf carries the
-// iteration's tag).  Every work-group then reads the leaf sums the same
+// work-group, then one sum per leaf, a leaf being the work-groups that run
+// on one XCD (added by the first work-group of the leaf once every partial
+// of the leaf carries the iteration's tag; the partials stay in that XCD's
+// L2).  Every work-group then reads the leaf sums the same
 // way, adds them in the same fixed order and solves the 6x6 system itself,
 // so all of them hold the bit-identical new pose without a round trip
 // through a publisher; work-group 0 writes the final pose.
@@ -53,6 +54,7 @@ struct TrackArgs {
     unsigned tag_polls;    // bound on the polls of one tagged word
     unsigned join_polls;   // bound on the polls of the level-boundary pose
     unsigned long long* clocks;   // optional per-iteration wall-clock stamps of work-group 0
+    int device_scope;      // every partial through device-scope memory (same sums, slower)
 };
 
 // Compensated (Kahan) float32 accumulation: after any number of add()s,
@@ -460,9 +462,11 @@ __device__ inline unsigned long long tag_word(double v, unsigned long long tag) 
 }
 __device__ inline double untag_word(unsigned long long w) { return __longlong_as_double((long long)(w & ~kTagMask)); }
 
+// A tagged partial (tag != 0) is stored at work-group scope when `local`
+// (its reader runs on the same XCD), else at device scope.
 template <bool COMP>
 __device__ inline void store_partial(const float acc[kNE], const float cmp[kNE], double* partial,
-                                     ReduceLds& r, unsigned long long tag = 0) {
+                                     ReduceLds& r, unsigned long long tag = 0, bool local = false) {
     const int slot = red_slot(threadIdx.x);
 #pragma unroll
     for (int k = 0; k < kNE; ++k) r.v[k][slot] = COMP ? acc[k] - cmp[k] : acc[k];
@@ -503,7 +507,10 @@ __device__ inline void store_partial(const float acc[kNE], const float cmp[kNE],
 #pragma unroll
             for (int p = 0; p < 8; ++p) s += r.part[threadIdx.x][p];
         }
-        if (tag)
+        if (tag && local)
+            __hip_atomic_store(reinterpret_cast<unsigned long long*>(&partial[threadIdx.x]), tag_word(s, tag),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else if (tag)
             __hip_atomic_store(reinterpret_cast<unsigned long long*>(&partial[threadIdx.x]), tag_word(s, tag),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         else
@@ -685,11 +692,22 @@ __device__ inline bool solve_update_wave(const double* ne, double damping, doubl
 
 // Memory ordering between work-groups.  Everything one work-group hands to
 // another (partial sums, leaf sums, the published pose, tickets and flags) is
-// written and read only with device-scope atomic operations, which the
-// hardware keeps coherent per location across the XCDs without cache
-// maintenance.  A tagged word (the tracking kernel's partials and leaf
-// sums) needs nothing more: it is written by one 64-bit store, so a reader
-// that sees its tag sees its value.  Elsewhere ordering is all that is
+// read only with device-scope atomic loads, and written with device-scope
+// atomic stores, which the hardware keeps coherent per location across the
+// XCDs without cache maintenance: such a store writes through the writer's
+// L2, such a load does not return a line its L2 holds clean.  One exception
+// keeps a hop inside an XCD: the tracking kernel's partials go to their
+// leaf's first work-group, which runs on the same XCD, and are stored at
+// work-group scope.  That store leaves the line dirty in the XCD's L2, and
+// a device-scope load from the same XCD returns a dirty line of its own L2
+// (measured on MI355X: a store-to-load round trip of 0.46 us between two
+// work-groups on one XCD against 0.85 us with device-scope stores, and
+// 1.2 us between XCDs).  A work-group that does not find itself on its leaf
+// leader's XCD (the leader publishes its hardware XCC id) stores its
+// partials at device scope instead, so the exchange never depends on the
+// dispatch order for its correctness.  A tagged word (the tracking kernel's
+// partials and leaf sums) needs nothing more: it is written by one 64-bit
+// store, so a reader that sees its tag sees its value.  Elsewhere ordering is all that is
 // needed: a producer waits until its device-scope stores have completed
 // before it signals (s_waitcnt on all counters, below), and a consumer
 // issues its loads only after the signal's value has returned.  A
@@ -699,20 +717,24 @@ __device__ inline bool solve_update_wave(const double* ne, double damping, doubl
 // which this kernel does not exchange.
 __device__ inline void complete_device_stores() { __builtin_amdgcn_s_waitcnt(0); }
 
-// Reduction across work-groups: a two-level tree, kLeaf work-groups to a
-// leaf.  Single-launch reductions (the normal equations) use arrival
-// tickets (device-scope atomics on one address serialise, so a single
-// ticket for hundreds of work-groups would cost tens of microseconds): the
-// last work-group of a leaf adds the leaf's partials, the last leaf adds
-// the leaf sums.  The tracking kernel uses no tickets: its partials and
-// leaf sums are tagged with their iteration (below), the first work-group
-// of each leaf polls its leaf's partials, and every member polls the leaf
-// sums.  Sync words: the tickets, the iteration count of the pose published
-// at level boundaries for work-groups that join, and an abort flag.  The
-// pyramid kernel clears them and the tagged words before each tracking
-// launch.
+// Reduction across work-groups: a two-level tree.  Single-launch
+// reductions (the normal equations) take kLeaf consecutive work-groups to a
+// leaf and use arrival tickets (device-scope atomics on one address
+// serialise, so a single ticket for hundreds of work-groups would cost tens
+// of microseconds): the last work-group of a leaf adds the leaf's
+// partials, the last leaf adds the leaf sums.  The tracking kernel uses no
+// tickets and one leaf per XCD: work-group b runs on XCD b mod 8 (the
+// dispatcher deals work-groups to the XCDs in turn), its partial goes to
+// slot (b mod 8) * kPerXcd + b / 8, so a leaf's partials are consecutive,
+// and work-group b mod 8 leads the leaf.  Partials and leaf sums are tagged
+// with their iteration (below), the leader polls its leaf's partials, and
+// every member polls the leaf sums.  Sync words: the tickets, the iteration
+// count of the pose published at level boundaries for work-groups that
+// join, an abort flag, and each tracking leaf leader's XCC id.  The pyramid
+// kernel clears them and the tagged words before each tracking launch.
 constexpr int kLeaf = 16;
 constexpr int kMaxLeaves = kMaxGroups / kLeaf;
+constexpr int kPerXcd = kMaxGroups / kXcds;
 // one set of partials: a partial per work-group, then one per leaf
 constexpr size_t kPartsPerSet = (size_t)(kMaxGroups + kMaxLeaves) * kPartStride;
 // Leaf tickets are kTicketStride words (256 B) apart: device-scope atomics
@@ -723,7 +745,8 @@ enum {
     kSyncRoot = kSyncLeaf + 2 * kMaxLeaves * kTicketStride,  // [2]
     kSyncPub = kSyncRoot + 2,                               // iterations reflected by the published pose
     kSyncAbort = kSyncPub + 1,
-    kSyncWords = kSyncAbort + 1
+    kSyncXcc = kSyncAbort + 1,                              // [kXcds] 1 + XCC id of each tracking leaf leader
+    kSyncWords = kSyncXcc + kXcds
 };
 
 // Arrival, thread 0 only.  leaf_arrive: true for the last of the kLeaf
@@ -861,19 +884,22 @@ __device__ inline bool total_leaves(const double* leafpart, int nleaf, unsigned 
     return true;
 }
 
-// A member's share of an iteration: store the tagged work-group partial;
-// the first work-group of each leaf adds the leaf's partials as they carry
-// the tag and stores the tagged leaf sum (device scope).  False (in every
-// thread of a leaf's first work-group) on timeout or abort.
+// A member's share of an iteration of the tracking kernel (members are
+// work-groups 0 .. groups-1): store the tagged work-group partial in its
+// XCD's slot (at work-group scope when `local`: on the leader's XCD); the
+// leader of each XCD's leaf adds the leaf's partials as they carry the tag
+// and stores the tagged leaf sum (device scope).  False (in every thread of
+// a leader) on timeout or abort.
 template <bool COMP>
 __device__ inline bool contribute(const float acc[kNE], const float cmp[kNE], double* part, double* leafpart,
                                   int groups, const unsigned* sync, unsigned max_polls, ReduceLds& r,
-                                  unsigned long long tag) {
-    store_partial<COMP>(acc, cmp, part + (size_t)blockIdx.x * kPartStride, r, tag);
-    if (blockIdx.x % kLeaf != 0) return true;
-    const int leaf = blockIdx.x / kLeaf;
-    const int leaf_size = min(kLeaf, groups - leaf * kLeaf);
-    if (!total_leaves<COMP>(part + (size_t)leaf * kLeaf * kPartStride, leaf_size, tag, sync, max_polls, r))
+                                  unsigned long long tag, bool local) {
+    const int leaf = blockIdx.x % kXcds;
+    store_partial<COMP>(acc, cmp, part + (size_t)(leaf * kPerXcd + blockIdx.x / kXcds) * kPartStride, r, tag,
+                        local);
+    if (blockIdx.x >= kXcds) return true;
+    const int leaf_size = (groups - leaf + kXcds - 1) / kXcds;
+    if (!total_leaves<COMP>(part + (size_t)leaf * kPerXcd * kPartStride, leaf_size, tag, sync, max_polls, r))
         return false;
     // r.tot holds the leaf sum in every thread; lanes of wave 0 store it
     if (threadIdx.x < kNE)
@@ -934,7 +960,7 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
                                                               double* pose_out, double* partials, unsigned* sync,
                                                               float* stats, int32_t* status) {
     __shared__ double s_pose[12];
-    __shared__ int s_ok;
+    __shared__ int s_ok, s_local;
     __shared__ ReduceLds red;
     __shared__ float s_depth[kTrackBatch * kTrackBlock];
     constexpr bool COMP = STORAGE == GSDF_BF16 || STORAGE == GSDF_FP16;
@@ -945,6 +971,12 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
     for (int l = 0; l < a.levels; ++l)
         if (a.iters[l] > 0) span = max(span, level_groups(a.lv[l], G));
     if ((int)blockIdx.x >= span) return;
+    // the leaders publish their XCD; a member compares it with its own
+    // before its first partial (at that point the leader's store has long
+    // been visible, so the comparison costs one load)
+    if (blockIdx.x < kXcds && threadIdx.x == 0)
+        __hip_atomic_store(&sync[kSyncXcc + blockIdx.x], xcc_id() + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int local = a.device_scope ? 0 : (blockIdx.x < kXcds ? 1 : -1);   // -1: not known yet
     // pose_in may be pose_out: every work-group still running reads it here,
     // before its first contribution, and work-group 0 writes the result only
     // after the last iteration, which needs all of those contributions
@@ -966,7 +998,7 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
         if (a.iters[l] == 0) continue;
         const TrackLevel L = a.lv[l];
         const int Gl = level_groups(L, G);
-        const int nleaf = (Gl + kLeaf - 1) / kLeaf;
+        const int nleaf = Gl < kXcds ? Gl : kXcds;
         if ((int)blockIdx.x >= Gl) {
             // not a member: skip the level
             gi += a.iters[l];
@@ -1016,8 +1048,23 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
                 accumulate<STORAGE>(M, L, a, P, first, kTrackBlock, c1, s_depth, acc, cmp);
             const unsigned long long tag = (unsigned long long)(gi + 1);
             if (stamp) a.clocks[4 * gi] = wall_clock64() - t0;
+            if (local < 0) {
+                // on the leader's XCD?  A bounded wait; if it ends without an
+                // answer the partials simply go through device scope
+                if (threadIdx.x == 0) {
+                    const unsigned* w = &sync[kSyncXcc + blockIdx.x % kXcds];
+                    unsigned v, spins = 0;
+                    while ((v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0u &&
+                           ++spins <= a.tag_polls)
+                        __builtin_amdgcn_s_sleep(1);
+                    s_local = v == xcc_id() + 1u ? 1 : 0;
+                }
+                __syncthreads();
+                local = s_local;
+            }
             // every member: the same sum of the leaf sums, the same solve
-            const bool part_ok = contribute<COMP>(acc, cmp, part, leafpart, Gl, sync, a.tag_polls, red, tag);
+            const bool part_ok =
+                contribute<COMP>(acc, cmp, part, leafpart, Gl, sync, a.tag_polls, red, tag, local != 0);
             if (stamp) a.clocks[4 * gi + 1] = wall_clock64() - t0;
             if (!part_ok || !total_leaves<COMP>(leafpart, nleaf, tag, sync, a.tag_polls, red)) {
                 if (threadIdx.x == 0) {
@@ -1325,6 +1372,7 @@ int track_frame_on(const gsdf_map* map, const float* depth_dev, const gsdf_camer
     a.tag_polls = params->max_polls > 0 ? (unsigned)params->max_polls : kTagPolls;
     a.join_polls = params->max_polls > 0 ? (unsigned)params->max_polls : kJoinPolls;
     a.clocks = reinterpret_cast<unsigned long long*>(params->iter_clocks);
+    a.device_scope = params->exchange_device_scope ? 1 : 0;
 
     {
         PyramidArgs p;
@@ -1434,6 +1482,7 @@ extern "C" int gsdf_normal_equations(const gsdf_map* map, const float* depth_dev
     a.tag_polls = kTagPolls;
     a.join_polls = kJoinPolls;
     a.clocks = nullptr;
+    a.device_scope = 1;
     PyramidArgs p = {};
     p.levels = 1;
     p.sync = sync;

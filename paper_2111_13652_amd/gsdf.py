@@ -183,7 +183,7 @@ class GsdfMap:
               iters: Sequence[int] = (4, 5, 10), delta: float = 0.01, damping: float = 1e-6,
               min_inlier_frac: float = 0.1, stats: Optional[torch.Tensor] = None,
               init: Optional[torch.Tensor] = None, model: str = "taylor", max_polls: int = 0,
-              clocks: Optional[torch.Tensor] = None) -> None:
+              clocks: Optional[torch.Tensor] = None, device_scope: bool = False) -> None:
         """Coarse-to-fine tracking; ``pose`` (3x4 float64, device) receives
         the estimate, starting from ``init`` (default: ``pose`` itself, updated
         in place).  ``iters[l]`` iterations at level l (0 = finest).  ``model``:
@@ -191,7 +191,9 @@ class GsdfMap:
         Eq. (12)-(13), the comparison model).  ``max_polls`` bounds each
         wait between work-groups (0: the library default).  ``clocks``
         (int64, device, 4 per iteration): per-iteration wall-clock stamps of
-        work-group 0 (see wall_clock_khz)."""
+        work-group 0 (see wall_clock_khz).  ``device_scope``: every
+        per-iteration partial through device-scope memory rather than its
+        XCD's L2 (same result bits, slower; for checking the exchange)."""
         c = camera(cam)
         _need(depth, torch.float32, (c.height, c.width), "depth")
         _need(pose, torch.float64, (3, 4), "pose")
@@ -209,7 +211,7 @@ class GsdfMap:
                 raise ValueError("clocks too small")
         p = _lib.TrackParams(int(levels), (C.c_int32 * 4)(*it[:4]), float(delta), float(damping),
                              float(min_inlier_frac), {"taylor": 0, "trilinear": 1}[model], int(max_polls),
-                             _ptr(clocks))
+                             _ptr(clocks), int(bool(device_scope)))
         scratch = self._scratch_for(c, levels)
         _lib.check(_lib.load().gsdf_track_frame(C.byref(self._map), _ptr(depth), C.byref(c),
                                                  C.byref(p), _ptr(init), _ptr(pose), _ptr(stats), _ptr(scratch),

@@ -127,3 +127,25 @@ def test_iteration_clocks_change_no_bit_of_the_pose(stream):
     log(f"  launch {c[-1] * 1e3 / khz:.1f} us by work-group 0's clock ({khz} kHz)")
     with pytest.raises(ValueError):
         G.track(dev(st.depth[4]), st.cam, P2, clocks=clk[:10])
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+def test_exchange_through_device_scope_gives_the_same_pose(stream, storage):
+    """The per-iteration partials normally stay in the L2 of the XCD their
+    leaf runs on; sent through device-scope memory instead (the path a
+    work-group takes when it is not on its leaf leader's XCD) they are the
+    same sums added in the same order: the pose is the same bits."""
+    import torch
+    from paper_2111_13652_amd.gsdf import GsdfMap
+    st = stream
+    G = GsdfMap(0.01, 0.05, 60000, storage=storage)
+    for f in range(4):
+        G.fuse(dev(st.depth[f]), st.cam, dev(st.poses[f]))
+    log(f"case: tracking frame 4 through each XCD's L2 and through device scope, {storage}")
+    P1 = dev(st.poses[3].copy())
+    P2 = dev(st.poses[3].copy())
+    G.track(dev(st.depth[4]), st.cam, P1)
+    G.track(dev(st.depth[4]), st.cam, P2, device_scope=True)
+    torch.cuda.synchronize()
+    assert G.status_flags() == []
+    assert torch.equal(P1, P2)
