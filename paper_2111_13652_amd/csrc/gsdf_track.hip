@@ -10,10 +10,10 @@
 // of H = sum w J J^T, the 6 of b = sum w J r, the energy, the count of
 // pixels used and the count of valid pixels.  From there every sum is
 // float64: LDS across the waves of a work-group, then one partial per
-// work-group, then one sum per leaf, a leaf being the work-groups that run
-// on one XCD (added by the first work-group of the leaf once every partial
-// of the leaf carries the iteration's tag; the partials stay in that XCD's
-// L2).  Every work-group then reads the leaf sums the same
+// work-group, then one sum per leaf, a leaf being up to 16 work-groups that
+// run on one XCD (added by the first work-group of the leaf once every
+// partial of the leaf carries the iteration's tag; the partials stay in
+// that XCD's L2).  Every work-group then reads the leaf sums the same
 // way, adds them in the same fixed order and solves the 6x6 system itself,
 // so all of them hold the bit-identical new pose without a round trip
 // through a publisher; work-group 0 writes the final pose.
@@ -723,18 +723,33 @@ __device__ inline void complete_device_stores() { __builtin_amdgcn_s_waitcnt(0);
 // serialise, so a single ticket for hundreds of work-groups would cost tens
 // of microseconds): the last work-group of a leaf adds the leaf's
 // partials, the last leaf adds the leaf sums.  The tracking kernel uses no
-// tickets and one leaf per XCD: work-group b runs on XCD b mod 8 (the
-// dispatcher deals work-groups to the XCDs in turn), its partial goes to
-// slot (b mod 8) * kPerXcd + b / 8, so a leaf's partials are consecutive,
-// and work-group b mod 8 leads the leaf.  Partials and leaf sums are tagged
-// with their iteration (below), the leader polls its leaf's partials, and
-// every member polls the leaf sums.  Sync words: the tickets, the iteration
-// count of the pose published at level boundaries for work-groups that
-// join, an abort flag, and each tracking leaf leader's XCC id.  The pyramid
+// tickets and leaves of up to kXcdLeaf work-groups of one XCD: work-group b
+// runs on XCD x = b mod 8 (the dispatcher deals work-groups to the XCDs in
+// turn) as the i-th (i = b / 8) of that XCD; its partial goes to slot
+// x * kPerXcd + i, it belongs to leaf (i / kXcdLeaf) * 8 + x, and the
+// member with i mod kXcdLeaf = 0 leads the leaf.  A leaf's partials are
+// consecutive, and the leaves of a level are numbered 0 .. nleaf-1 without
+// gaps.  Partials and leaf sums are tagged with their iteration (below),
+// the leader polls its leaf's partials, and every member polls the leaf
+// sums.  Sync words: the tickets, the iteration count of the pose published
+// at level boundaries for work-groups that join, an abort flag, and each
+// tracking leaf leader's XCC id.  The pyramid
 // kernel clears them and the tagged words before each tracking launch.
 constexpr int kLeaf = 16;
 constexpr int kMaxLeaves = kMaxGroups / kLeaf;
 constexpr int kPerXcd = kMaxGroups / kXcds;
+// Work-groups per tracking leaf.  Measured on MI355X (one work-group per CU,
+// 32 per XCD): 16 beats 32 and 8 by 2.3 us per launch at 640x480 and by
+// 5.3-6 us at 1280x720.
+constexpr int kXcdLeaf = 16;
+static_assert((kMaxGroups / kXcdLeaf) <= kMaxLeaves, "tracking leaves must fit the leaf sums");
+__device__ inline int xcd_leaf(int b) { return (b / kXcds / kXcdLeaf) * kXcds + b % kXcds; }
+__device__ inline bool xcd_leader(int b) { return (b / kXcds) % kXcdLeaf == 0; }
+// leaves of a level with n members (consecutive numbers from 0)
+__device__ inline int xcd_leaves(int n) {
+    constexpr int span = kXcds * kXcdLeaf;
+    return kXcds * (n / span) + min(kXcds, n % span);
+}
 // one set of partials: a partial per work-group, then one per leaf
 constexpr size_t kPartsPerSet = (size_t)(kMaxGroups + kMaxLeaves) * kPartStride;
 // Leaf tickets are kTicketStride words (256 B) apart: device-scope atomics
@@ -745,8 +760,8 @@ enum {
     kSyncRoot = kSyncLeaf + 2 * kMaxLeaves * kTicketStride,  // [2]
     kSyncPub = kSyncRoot + 2,                               // iterations reflected by the published pose
     kSyncAbort = kSyncPub + 1,
-    kSyncXcc = kSyncAbort + 1,                              // [kXcds] 1 + XCC id of each tracking leaf leader
-    kSyncWords = kSyncXcc + kXcds
+    kSyncXcc = kSyncAbort + 1,                              // [kMaxLeaves] 1 + XCC id of each tracking leaf leader
+    kSyncWords = kSyncXcc + kMaxLeaves
 };
 
 // Arrival, thread 0 only.  leaf_arrive: true for the last of the kLeaf
@@ -887,20 +902,20 @@ __device__ inline bool total_leaves(const double* leafpart, int nleaf, unsigned 
 // A member's share of an iteration of the tracking kernel (members are
 // work-groups 0 .. groups-1): store the tagged work-group partial in its
 // XCD's slot (at work-group scope when `local`: on the leader's XCD); the
-// leader of each XCD's leaf adds the leaf's partials as they carry the tag
-// and stores the tagged leaf sum (device scope).  False (in every thread of
+// leader of each leaf adds the leaf's partials as they carry the tag and
+// stores the tagged leaf sum (device scope).  False (in every thread of
 // a leader) on timeout or abort.
 template <bool COMP>
 __device__ inline bool contribute(const float acc[kNE], const float cmp[kNE], double* part, double* leafpart,
                                   int groups, const unsigned* sync, unsigned max_polls, ReduceLds& r,
                                   unsigned long long tag, bool local) {
-    const int leaf = blockIdx.x % kXcds;
-    store_partial<COMP>(acc, cmp, part + (size_t)(leaf * kPerXcd + blockIdx.x / kXcds) * kPartStride, r, tag,
-                        local);
-    if (blockIdx.x >= kXcds) return true;
-    const int leaf_size = (groups - leaf + kXcds - 1) / kXcds;
-    if (!total_leaves<COMP>(part + (size_t)leaf * kPerXcd * kPartStride, leaf_size, tag, sync, max_polls, r))
-        return false;
+    const int b = blockIdx.x;
+    double* mine = part + (size_t)((b % kXcds) * kPerXcd + b / kXcds) * kPartStride;
+    store_partial<COMP>(acc, cmp, mine, r, tag, local);
+    if (!xcd_leader(b)) return true;
+    const int leaf = xcd_leaf(b);
+    const int leaf_size = min(kXcdLeaf, (groups - b + kXcds - 1) / kXcds);
+    if (!total_leaves<COMP>(mine, leaf_size, tag, sync, max_polls, r)) return false;
     // r.tot holds the leaf sum in every thread; lanes of wave 0 store it
     if (threadIdx.x < kNE)
         __hip_atomic_store(reinterpret_cast<unsigned long long*>(&leafpart[(size_t)leaf * kPartStride + threadIdx.x]),
@@ -974,9 +989,11 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
     // the leaders publish their XCD; a member compares it with its own
     // before its first partial (at that point the leader's store has long
     // been visible, so the comparison costs one load)
-    if (blockIdx.x < kXcds && threadIdx.x == 0)
-        __hip_atomic_store(&sync[kSyncXcc + blockIdx.x], xcc_id() + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int local = a.device_scope ? 0 : (blockIdx.x < kXcds ? 1 : -1);   // -1: not known yet
+    const bool leader = xcd_leader(blockIdx.x);
+    if (leader && threadIdx.x == 0)
+        __hip_atomic_store(&sync[kSyncXcc + xcd_leaf(blockIdx.x)], xcc_id() + 1u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    int local = a.device_scope ? 0 : (leader ? 1 : -1);   // -1: not known yet
     // pose_in may be pose_out: every work-group still running reads it here,
     // before its first contribution, and work-group 0 writes the result only
     // after the last iteration, which needs all of those contributions
@@ -998,7 +1015,7 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
         if (a.iters[l] == 0) continue;
         const TrackLevel L = a.lv[l];
         const int Gl = level_groups(L, G);
-        const int nleaf = Gl < kXcds ? Gl : kXcds;
+        const int nleaf = xcd_leaves(Gl);
         if ((int)blockIdx.x >= Gl) {
             // not a member: skip the level
             gi += a.iters[l];
@@ -1052,7 +1069,7 @@ __global__ __launch_bounds__(kTrackBlock) void k_track_frame(MapView M, TrackArg
                 // on the leader's XCD?  A bounded wait; if it ends without an
                 // answer the partials simply go through device scope
                 if (threadIdx.x == 0) {
-                    const unsigned* w = &sync[kSyncXcc + blockIdx.x % kXcds];
+                    const unsigned* w = &sync[kSyncXcc + xcd_leaf(blockIdx.x)];
                     unsigned v, spins = 0;
                     while ((v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0u &&
                            ++spins <= a.tag_polls)
