@@ -179,6 +179,9 @@ struct BlockBox {
     float inv_bw;             // 1 / rectangle width
 };
 
+// Called by lanes 0..7 of wave 0 together, one box corner each (on one
+// lane the eight projections are a long dependent float64 chain); lane 0
+// writes the result.
 __device__ inline void block_box(const FuseConsts& fc, const double* R, const double* t, int bx,
                                  int by, int bz, BlockBox* B) {
     const int b[3] = {bx, by, bz};
@@ -196,31 +199,46 @@ __device__ inline void block_box(const FuseConsts& fc, const double* R, const do
     for (int i = 0; i < 3; ++i) {
         lo[i] -= margin;
         hi[i] += margin;
-        B->lo[i] = (float)(lo[i] - t[i]);
-        B->hi[i] = (float)(hi[i] - t[i]);
     }
-    double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300, zlo = 1e300, zhi = -1e300;
-    bool behind = false;
-    for (int c = 0; c < 8; ++c) {
+    // corner c of the box: its camera-frame point and pixel; the extremes
+    // over the 8 corners by shuffles within the 8 lanes
+    double umin, umax, vmin, vmax, zlo, zhi;
+    bool behind;
+    {
+        const int c = threadIdx.x & 7;
         const double X[3] = {(c & 1) ? hi[0] : lo[0], (c & 2) ? hi[1] : lo[1], (c & 4) ? hi[2] : lo[2]};
         double pc[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j)
             pc[j] = R[j] * (X[0] - t[0]) + R[3 + j] * (X[1] - t[1]) + R[6 + j] * (X[2] - t[2]);
-        zlo = fmin(zlo, pc[2]);
-        zhi = fmax(zhi, pc[2]);
-        if (pc[2] <= 1e-6) behind = true;
-        if (behind) continue;
         // reciprocal (hardware estimate and one Newton step) instead of two
         // divisions: the rectangle is widened by a pixel on each side anyway
+        // (a corner behind the camera gives a meaningless value here, and
+        // the whole image is used then)
         double iz = __builtin_amdgcn_rcp(pc[2]);
         iz = fma(iz, fma(-pc[2], iz, 1.0), iz);
         const double u = fc.fx_d * pc[0] * iz + fc.cx_d;
         const double v = fc.fy_d * pc[1] * iz + fc.cy_d;
-        umin = fmin(umin, u);
-        umax = fmax(umax, u);
-        vmin = fmin(vmin, v);
-        vmax = fmax(vmax, v);
+        umin = umax = u;
+        vmin = vmax = v;
+        zlo = zhi = pc[2];
+        behind = pc[2] <= 1e-6;
+#pragma unroll
+        for (int m = 1; m < 8; m <<= 1) {
+            umin = fmin(umin, __shfl_xor(umin, m, 8));
+            umax = fmax(umax, __shfl_xor(umax, m, 8));
+            vmin = fmin(vmin, __shfl_xor(vmin, m, 8));
+            vmax = fmax(vmax, __shfl_xor(vmax, m, 8));
+            zlo = fmin(zlo, __shfl_xor(zlo, m, 8));
+            zhi = fmax(zhi, __shfl_xor(zhi, m, 8));
+            behind = behind || __shfl_xor((int)behind, m, 8);
+        }
+    }
+    if (threadIdx.x != 0) return;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        B->lo[i] = (float)(lo[i] - t[i]);
+        B->hi[i] = (float)(hi[i] - t[i]);
     }
     B->zmin = (float)zlo;
     B->zmax = (float)zhi;
@@ -307,7 +325,7 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
             }
             aW[c] = 0ull;
         }
-        if (threadIdx.x == 0) block_box(fc, R, t, bx, by, bz, &box);
+        if (threadIdx.x < 8) block_box(fc, R, t, bx, by, bz, &box);
         __syncthreads();
 
         const int bw = box.u1 - box.u0 + 1;
