@@ -504,41 +504,64 @@ __global__ __launch_bounds__(kFuseBlock) void k_fuse_blocks(MapView M, const flo
             __syncthreads();
         }
 
-        // write the voxels this frame changed: this work-group owns the block
-        for (int c = threadIdx.x; c < kBlockVoxels; c += kFuseBlock) {
-            const float sw = from_fixed(aW[c], fc.fix_inv);
-            if (!(sw > 0.0f)) continue;
-            const float sS = from_fixed(aS[c], fc.fix_inv);
+        // write the voxels this frame changed: this work-group owns the block.
+        // A thread reads all of its voxels before it writes any, so their
+        // loads are in flight together.
+        constexpr int kPerThread = kBlockVoxels / kFuseBlock;
+        static_assert(kBlockVoxels % kFuseBlock == 0, "every thread writes the same number of voxels");
+        float sw[kPerThread], sS[kPerThread], sG[kPerThread][3], Wold[kPerThread], d1[kPerThread];
+        int64_t vi[kPerThread];
+        bool on[kPerThread];
+        float4 r32[kPerThread];
+        ushort4 r16[kPerThread];
+#pragma unroll
+        for (int j = 0; j < kPerThread; ++j) {
+            const int c = threadIdx.x + j * kFuseBlock;
+            sw[j] = from_fixed(aW[c], fc.fix_inv);
+            on[j] = sw[j] > 0.0f;
+            if (!on[j]) continue;
+            sS[j] = from_fixed(aS[c], fc.fix_inv);
+            vi[j] = (int64_t)slot * kBlockVoxels + morton9(c & 7, (c >> 3) & 7, c >> 6);
+            if constexpr (kGrad) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) sG[j][i] = from_fixed(aG[i][c], fc.fix_inv);
+            }
+            if constexpr (!kGrad)
+                d1[j] = reinterpret_cast<const float*>(M.vox)[vi[j]];
+            else if (STORAGE == GSDF_FP32)
+                r32[j] = reinterpret_cast<const float4*>(M.vox)[vi[j]];
+            else
+                r16[j] = reinterpret_cast<const ushort4*>(M.vox)[vi[j]];
+            Wold[j] = M.weight[vi[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < kPerThread; ++j) {
+            if (!on[j]) continue;
             ++my_voxels;
-            const int64_t vi = (int64_t)slot * kBlockVoxels + morton9(c & 7, (c >> 3) & 7, c >> 6);
             if constexpr (!kGrad) {
-                reinterpret_cast<float*>(M.vox)[vi] += sS;
-                M.weight[vi] += sw;
+                reinterpret_cast<float*>(M.vox)[vi[j]] = d1[j] + sS[j];
+                M.weight[vi[j]] = Wold[j] + sw[j];
                 continue;
             }
-            const float sG[3] = {from_fixed(aG[0][c], fc.fix_inv), from_fixed(aG[1][c], fc.fix_inv),
-                                 from_fixed(aG[2][c], fc.fix_inv)};
             if (STORAGE == GSDF_FP32) {
-                float4* rec = reinterpret_cast<float4*>(M.vox) + vi;
-                float4 r = *rec;
-                r.x += sS;
-                r.y += sG[0];
-                r.z += sG[1];
-                r.w += sG[2];
-                *rec = r;
-                M.weight[vi] += sw;
+                float4 r = r32[j];
+                r.x += sS[j];
+                r.y += sG[j][0];
+                r.z += sG[j][1];
+                r.w += sG[j][2];
+                reinterpret_cast<float4*>(M.vox)[vi[j]] = r;
+                M.weight[vi[j]] = Wold[j] + sw[j];
             } else {
-                ushort4* rec = reinterpret_cast<ushort4*>(M.vox) + vi;
-                const ushort4 p = *rec;
-                const float Wold = M.weight[vi];
-                const float Wn = Wold + sw;
-                const float psi = (Wold * unpack16(p.x, STORAGE) * M.truncation + sS) / Wn;
-                const float g0 = (Wold * unpack16(p.y, STORAGE) + sG[0]) / Wn;
-                const float g1 = (Wold * unpack16(p.z, STORAGE) + sG[1]) / Wn;
-                const float g2 = (Wold * unpack16(p.w, STORAGE) + sG[2]) / Wn;
-                *rec = make_ushort4(pack16(psi / M.truncation, STORAGE), pack16(g0, STORAGE),
-                                    pack16(g1, STORAGE), pack16(g2, STORAGE));
-                M.weight[vi] = Wn;
+                const ushort4 p = r16[j];
+                const float Wn = Wold[j] + sw[j];
+                const float psi = (Wold[j] * unpack16(p.x, STORAGE) * M.truncation + sS[j]) / Wn;
+                const float g0 = (Wold[j] * unpack16(p.y, STORAGE) + sG[j][0]) / Wn;
+                const float g1 = (Wold[j] * unpack16(p.z, STORAGE) + sG[j][1]) / Wn;
+                const float g2 = (Wold[j] * unpack16(p.w, STORAGE) + sG[j][2]) / Wn;
+                reinterpret_cast<ushort4*>(M.vox)[vi[j]] =
+                    make_ushort4(pack16(psi / M.truncation, STORAGE), pack16(g0, STORAGE), pack16(g1, STORAGE),
+                                 pack16(g2, STORAGE));
+                M.weight[vi[j]] = Wn;
             }
         }
         if (threadIdx.x == 0) M.touched_flag[slot] = 0;
