@@ -347,7 +347,7 @@ def main():
         del params, xi
 
     # ---- joint refinement (the colour stream's configuration): one step =
-    # keyframe loss + photometric loss, both adjoints, an Adam step on the
+    # the two adjoints (each also returns its loss), an Adam step on the
     # voxel parameters and colours, and one Gauss-Newton iteration of the
     # tracking kernel per keyframe on the bf16 map
     joint = None

@@ -14,11 +14,15 @@
 // left increment of T_i [-a ; a x p_j], mapped through Jl(xi_i)^T.
 // The mean colour of Sec. 4.2 Eq. (21) uses the same visibility.
 //
-// Work layout: one work-group per map block (512 voxels, two per thread),
-// looping over the keyframes, so each voxel's psi and colour gradients are
-// summed in registers and written once, without atomics; per keyframe the
-// work-group's pose sums go to a partial that a second kernel reduces in a
-// fixed order.  Projection and visibility are decided in float64 (they are
+// Work layout: one work-group per map block, looping over the keyframes, so
+// each voxel's psi and colour gradients are summed in registers and written
+// once, without atomics; per keyframe the work-group's pose sums go to a
+// partial that a second kernel reduces in a fixed order.  Few of a block's
+// 512 voxels take part (those holding the surface: about 5 % on a room
+// map), so the work-group first lists them in voxel order and hands the
+// r-th to thread r mod 256 (two per thread at most): the projection and
+// sampling then run on dense lanes, and waves with nothing to do skip the
+// keyframe loop's work.  Projection and visibility are decided in float64 (they are
 // discrete decisions), samples and gradients are float32.
 #include <hip/hip_runtime.h>
 
@@ -131,32 +135,73 @@ __global__ __launch_bounds__(kPhotoBlock) void k_photometric(MapView M, PhotoArg
                                                             float* __restrict__ out_count,
                                                             const float* __restrict__ counts,
                                                             double* __restrict__ partials) {
-    __shared__ double s_red[kPhotoPart][kPhotoBlock / 64];
-    __shared__ int s_any;
+    constexpr int kWaves = kPhotoBlock / 64;
+    __shared__ double s_red[kPhotoPart][kWaves];
+    __shared__ int s_wcount[2][kWaves];
+    __shared__ short s_list[kBlockVoxels];
     const int64_t slot = blockIdx.x;
     const int32_t nb = M.counters[kNumBlocks] < M.max_blocks ? M.counters[kNumBlocks] : M.max_blocks;
-    PhotoVoxel V[2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // 1. the voxels that take part, listed in voxel order (c = t, then 256 + t)
+    bool take[2];
+    unsigned long long bal[2];
     for (int h = 0; h < 2; ++h) {
-        V[h].ok = false;
-        if (slot < nb) photo_voxel(M, a, params, MODE == 2 ? nullptr : colors, slot, threadIdx.x + h * kPhotoBlock, &V[h]);
-        if (MODE == 3 && V[h].ok) {
-            // upstream gradient per sample of the mean: G_j / N_j
-            const float n = counts[slot * kBlockVoxels + threadIdx.x + h * kPhotoBlock];
-            if (n > 0.0f) {
+        const int c = threadIdx.x + h * kPhotoBlock;
+        PhotoVoxel Q;
+        Q.ok = false;
+        if (slot < nb) photo_voxel(M, a, params, nullptr, slot, c, &Q);
+        if (MODE == 3 && Q.ok && !(counts[slot * kBlockVoxels + c] > 0.0f)) Q.ok = false;
+        take[h] = Q.ok;
+        if (MODE == 2 && !Q.ok) {
+            // not seen by construction: zero mean and count
+            const int64_t vi = slot * kBlockVoxels + c;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) V[h].rho[c] /= n;
-            } else {
-                V[h].ok = false;
-            }
+            for (int k = 0; k < 3; ++k) out_colors[3 * vi + k] = 0.0f;
+            if (out_count) out_count[vi] = 0.0f;
+        }
+        bal[h] = __ballot(take[h]);
+        if (lane == 0) s_wcount[h][wave] = __popcll(bal[h]);
+    }
+    __syncthreads();
+    // rank of a listed voxel: the voxels of the earlier (h, wave) groups,
+    // then those of the earlier lanes of its own
+    int base[2] = {0, 0}, n_act = 0;
+    for (int h = 0; h < 2; ++h)
+        for (int w = 0; w < kWaves; ++w) {
+            if (w == wave) base[h] = n_act;
+            n_act += s_wcount[h][w];
+        }
+    for (int h = 0; h < 2; ++h)
+        if (take[h])
+            s_list[base[h] + __popcll(bal[h] & ((1ull << lane) - 1ull))] = (short)(threadIdx.x + h * kPhotoBlock);
+    __syncthreads();
+    if (n_act == 0) {
+        // nothing in this block is seen: zero pose partials
+        if (MODE != 2)
+            for (int i = threadIdx.x; i < a.K * kPhotoPart; i += kPhotoBlock)
+                partials[((size_t)(i / kPhotoPart) * a.param_blocks + slot) * kPhotoPart + i % kPhotoPart] = 0.0;
+        return;
+    }
+    // 2. thread t takes the listed voxels t and t + 256
+    PhotoVoxel V[2];
+    int vc[2];
+    for (int h = 0; h < 2; ++h) {
+        const int r = threadIdx.x + h * kPhotoBlock;
+        V[h].ok = false;
+        vc[h] = 0;
+        if (r >= n_act) continue;
+        vc[h] = s_list[r];
+        photo_voxel(M, a, params, MODE == 2 ? nullptr : colors, slot, vc[h], &V[h]);
+        if (MODE == 3) {
+            // upstream gradient per sample of the mean: G_j / N_j
+            const float n = counts[slot * kBlockVoxels + vc[h]];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) V[h].rho[c] /= n;
         }
     }
-    if (threadIdx.x == 0) s_any = 0;
-    __syncthreads();
-    if (V[0].ok || V[1].ok) s_any = 1;
-    __syncthreads();
-    const bool any = s_any != 0;
+    // waves holding a listed voxel (uniform per wave)
+    const bool any = wave * 64 < n_act;
     const size_t npx = (size_t)a.W * a.H;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     float gpsi[2] = {0.0f, 0.0f}, grho[2][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
     float csum[2][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}}, cnt[2] = {0.0f, 0.0f};
 
@@ -240,17 +285,18 @@ __global__ __launch_bounds__(kPhotoBlock) void k_photometric(MapView M, PhotoArg
         __syncthreads();
     }
     for (int h = 0; h < 2; ++h) {
-        const int64_t vi = slot * kBlockVoxels + threadIdx.x + h * kPhotoBlock;
+        if (!V[h].ok) continue;
+        const int64_t vi = slot * kBlockVoxels + vc[h];
         if (MODE == 2) {
             const float n = cnt[h];
 #pragma unroll
             for (int c = 0; c < 3; ++c) out_colors[3 * vi + c] = n > 0.0f ? csum[h][c] / n : 0.0f;
             if (out_count) out_count[vi] = n;
-        } else if (MODE == 1 && V[h].ok) {
+        } else if (MODE == 1) {
             dparams[4 * vi] += gpsi[h];
 #pragma unroll
             for (int c = 0; c < 3; ++c) dcolors[3 * vi + c] += grho[h][c];
-        } else if (MODE == 3 && V[h].ok) {
+        } else if (MODE == 3) {
             dparams[4 * vi] += gpsi[h];
         }
     }

@@ -644,10 +644,46 @@ def photometric_ba(gmap: GsdfMap, depth: torch.Tensor, rgb: torch.Tensor, cam, T
     return poses, params.detach(), torch.stack(losses).cpu().numpy()
 
 
+def joint_loss_and_grads(gmap: GsdfMap, params: torch.Tensor, colors: torch.Tensor, xi: torch.Tensor,
+                         depth: torch.Tensor, rgb: torch.Tensor, cam, T0: torch.Tensor, delta: float = 0.01,
+                         photo_delta: float = 0.1, photo_weight: float = 0.01):
+    """The joint refinement objective sum_i (L_i + P_i), the SDF keyframe
+    loss (KeyframeLoss) plus the photometric loss (PhotometricLoss), and its
+    gradients in the voxel parameters, the voxel colours and the twists,
+    from the two adjoint calls alone with unit upstream gradients (each also
+    returns its loss, so no separate loss pass runs).  The gradients are
+    those of (KeyframeLoss.apply(...).sum() + PhotometricLoss.apply(...).sum())
+    through autograd, bit for bit.  Returns (loss (float64 scalar tensor),
+    dparams, dcolors, dxi)."""
+    params = params.detach()
+    colors = colors.detach()
+    xi = xi.detach()
+    c, K = _kf_args(gmap, depth, cam, T0, xi, params, None)
+    ones = torch.ones(K, dtype=torch.float32, device=depth.device)
+    dparams = torch.zeros_like(params)
+    dxi_s = torch.empty_like(xi)
+    loss_s = torch.empty(K, dtype=torch.float64, device=depth.device)
+    scratch = gmap._keyframe_scratch(c, K)
+    _lib.check(_lib.load().gsdf_backward(
+        C.byref(gmap._map), _ptr(depth), K, C.byref(c), _ptr(T0), _ptr(xi), _ptr(params),
+        int(params.shape[0]), float(delta), None, 0, _ptr(ones), _ptr(dparams), _ptr(dxi_s), _ptr(loss_s),
+        _ptr(scratch), scratch.numel(), _stream()), "keyframe_backward")
+    cp, _, pscratch = _photo_args(gmap, depth, rgb, cam, T0, xi, params, colors)
+    dcolors = torch.zeros_like(colors)
+    dxi_p = torch.empty_like(xi)
+    loss_p = torch.empty(K, dtype=torch.float64, device=depth.device)
+    _lib.check(_lib.load().gsdf_photometric_backward(
+        C.byref(gmap._map), _ptr(depth), _ptr(rgb), K, C.byref(cp), _ptr(T0), _ptr(xi), _ptr(params),
+        _ptr(colors), int(params.shape[0]), float(photo_delta), float(photo_weight), _ptr(ones), _ptr(dparams),
+        _ptr(dcolors), _ptr(dxi_p), _ptr(loss_p), _ptr(pscratch), pscratch.numel(), _stream()),
+        "photometric_backward")
+    return loss_s.sum() + loss_p.sum(), dparams, dcolors, dxi_s + dxi_p
+
+
 def refine_joint(gmap: GsdfMap, depth: torch.Tensor, rgb: torch.Tensor, cam, T0: torch.Tensor,
                  steps: int = 50, delta: float = 0.01, photo_delta: float = 0.1, photo_weight: float = 0.01,
                  lr_psi: float = 2e-5, lr_color: float = 1e-2, pose_solver: str = "gn", lr_pose: float = 4e-3,
-                 write_back: bool = True):
+                 write_back: bool = True, fused: bool = True):
     """Joint refinement over keyframes of the voxel distances and gradients,
     the voxel colours and the keyframe poses on the sum of the SDF keyframe
     loss and the photometric loss.  Each step takes an Adam step on the
@@ -659,6 +695,10 @@ def refine_joint(gmap: GsdfMap, depth: torch.Tensor, rgb: torch.Tensor, cam, T0:
     Colours start from the Eq. (21) mean at the initial poses.  The default
     photometric weight (delta / photo_delta)^2 prices a residual at either
     Huber threshold equally; learning rates decay on a cosine schedule.
+    ``fused`` takes each step's loss and gradients from the adjoint calls
+    alone (joint_loss_and_grads); ``fused=False`` composes KeyframeLoss and
+    PhotometricLoss through autograd (a loss pass, then the adjoints): the
+    same gradients, so the same steps.
     Returns (poses (K,3,4), params, colours, losses)."""
     K = depth.shape[0]
     params = gmap.export_params().detach().clone()
@@ -680,10 +720,18 @@ def refine_joint(gmap: GsdfMap, depth: torch.Tensor, rgb: torch.Tensor, cam, T0:
     for _ in range(steps):
         opt.zero_grad(set_to_none=True)
         xi = (ad @ xc.unsqueeze(-1)).squeeze(-1)
-        loss = (KeyframeLoss.apply(params, xi, gmap, depth, cam, T, delta).sum()
-                + PhotometricLoss.apply(params, colors, xi, gmap, depth, rgb, cam, T, photo_delta,
-                                        photo_weight).sum())
-        loss.backward()
+        if fused:
+            loss, dparams, dcolors, dxi = joint_loss_and_grads(gmap, params, colors, xi, depth, rgb, cam, T,
+                                                               delta, photo_delta, photo_weight)
+            params.grad = dparams
+            colors.grad = dcolors
+            if pose_solver == "adam":
+                xc.grad = (ad.transpose(1, 2) @ dxi.unsqueeze(-1)).squeeze(-1)
+        else:
+            loss = (KeyframeLoss.apply(params, xi, gmap, depth, cam, T, delta).sum()
+                    + PhotometricLoss.apply(params, colors, xi, gmap, depth, rgb, cam, T, photo_delta,
+                                            photo_weight).sum())
+            loss.backward()
         opt.step()
         sched.step()
         losses.append(loss.detach())

@@ -212,3 +212,37 @@ def test_photometric_ba_recovers_keyframe_poses(torch_mod):
         for (ra, ta), (rb, tb) in zip(after[1:], before[1:]):
             assert ra < 0.3 * rb and ta < 0.6 * tb
     assert G.status_flags() == []
+
+
+@pytest.mark.parametrize("solver", ["gn", "adam"])
+def test_fused_joint_steps_are_the_autograd_steps(torch_mod, rgbd_stream, solver):
+    """refine_joint with each step's loss and gradients from the two adjoint
+    calls alone (fused) and with KeyframeLoss + PhotometricLoss composed
+    through autograd: the same poses, parameters and colours, bit for bit,
+    after 5 steps (the losses agree to rounding: each path sums them in its
+    own pass)."""
+    torch = torch_mod
+    from paper_2111_13652_amd.gsdf import GsdfMap, refine_joint
+    st = rgbd_stream
+    idx = [4, 6, 8]
+    T0 = dev(np.stack([synth.perturb_pose(st.poses[f], 90 + i, 1.0, 0.01) for i, f in enumerate(idx)]))
+    out = []
+    log(f"case: joint refinement, 3 keyframes, 5 steps, {solver} poses, fused and through autograd")
+    for fused in (True, False):
+        G = GsdfMap(0.01, 0.05, 60000, storage="bf16")
+        for f in range(4):
+            G.fuse(dev(st.depth[f]), st.cam, dev(st.poses[f]))
+        P, p, c, losses = refine_joint(G, dev(st.depth[idx]), dev(st.rgb[idx]), st.cam, T0, steps=5,
+                                       pose_solver=solver, fused=fused)
+        torch.cuda.synchronize()
+        assert G.status_flags() == []
+        # parameter rows are in pool-slot order, which depends on the order
+        # blocks were inserted: compare them by block key
+        keys = G.keys()
+        o = torch.as_tensor(np.lexsort(keys.T[::-1]), device=p.device)
+        out.append((P, keys[o.cpu().numpy()], p[o], c[o], losses))
+    (P1, k1, p1, c1, l1), (P2, k2, p2, c2, l2) = out
+    np.testing.assert_array_equal(k1, k2)
+    assert torch.equal(P1, P2) and torch.equal(p1, p2) and torch.equal(c1, c2)
+    np.testing.assert_allclose(l1, l2, rtol=1e-9)
+    log("  identical; losses", l1[0], "->", l1[-1])
