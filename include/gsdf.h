@@ -264,6 +264,30 @@ int gsdf_normal_equations(const gsdf_map* map, const float* depth_dev, const gsd
                           const double* T_wc_dev, float huber_delta, double* out29_dev,
                           void* scratch_dev, size_t scratch_bytes, void* stream);
 
+/* One damped Gauss-Newton step of the tracking energy (Sec. 4.1 Eq. (5),
+ * (14)-(16); Sec. 5.1) at full resolution for each of n_keyframes keyframes
+ * on the current map, as joint refinement takes it once per step: for
+ * keyframe i, with depth depth_dev + i*H*W (K x H x W float32, device) and
+ * pose T_dev + 12 i (K x 12 float64, row-major 3x4 camera-to-world,
+ * device, updated in place), the step gsdf_track_frame takes with one level
+ * and one iteration (Huber threshold huber_delta, mu = damping * trace(H)/6
+ * added to H's diagonal, left SE(3) update), in two launches for all
+ * keyframes.  The normal equations are summed in another fixed order than
+ * gsdf_track_frame's, so the poses agree with K such calls to rounding, and
+ * are the same bits on every run.  Sticky bits in *status_dev:
+ * GSDF_ENOTPD when a keyframe's system is not positive definite (its pose
+ * unchanged), GSDF_ELOST when fewer than min_inlier_frac of a keyframe's
+ * valid pixels found an observed voxel, GSDF_EINVAL for a non-finite pose
+ * (left unchanged).  scratch_dev: at least gsdf_gn_scratch_bytes(cam, K)
+ * bytes (contents on entry do not matter).  Returns GSDF_EINVAL for bad
+ * sizes, null buffers, huber_delta <= 0, damping < 0, K outside
+ * 1..65535 or a map without gradients. */
+size_t gsdf_gn_scratch_bytes(const gsdf_camera* cam, int32_t n_keyframes);
+int gsdf_gn_step_keyframes(const gsdf_map* map, const float* depth_dev, int32_t n_keyframes,
+                           const gsdf_camera* cam, double* T_dev, float huber_delta, double damping,
+                           float min_inlier_frac, void* scratch_dev, size_t scratch_bytes,
+                           int32_t* status_dev, void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* Differentiable form: keyframe loss and its adjoint                      */
 /* ---------------------------------------------------------------------- */

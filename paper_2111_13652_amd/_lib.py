@@ -69,6 +69,9 @@ _SIGNATURES = {
     "gsdf_track_frame_noalloc": (_I, [C.POINTER(Map), _P, C.POINTER(Camera), C.POINTER(TrackParams), _P, _P, _P,
                                       _P, _P]),
     "gsdf_normal_equations": (_I, [C.POINTER(Map), _P, C.POINTER(Camera), _P, C.c_float, _P, _P, _SZ, _P]),
+    "gsdf_gn_scratch_bytes": (_SZ, [C.POINTER(Camera), _I32]),
+    "gsdf_gn_step_keyframes": (_I, [C.POINTER(Map), _P, _I32, C.POINTER(Camera), _P, C.c_float, C.c_double,
+                                    C.c_float, _P, _SZ, _P, _P]),
     "gsdf_export_keys": (_I, [C.POINTER(Map), _P, _P, _P]),
     "gsdf_export_voxels": (_I, [C.POINTER(Map), _I32, _P, _P, _P, _P]),
     "gsdf_import_blocks": (_I, [C.POINTER(Map), _P, _I32, _P, _P, _P, _P, _P]),

@@ -1153,6 +1153,69 @@ __global__ __launch_bounds__(kTrackBlock) void k_normal_equations(MapView M, Tra
         for (int k = 0; k < 29; ++k) out29[k] = ne[k];
 }
 
+// One damped Gauss-Newton step at full resolution for each of K keyframes
+// (the step k_track_frame takes with one level and one iteration), in two
+// launches.  k_gn_partials: work-group (b, k) accumulates the normal
+// equations of its strided share of keyframe k's pixels at pose k and
+// stores its partial in slot k * gridDim.x + b.  k_gn_solve: work-group k
+// adds keyframe k's partials in a fixed order and takes the solve and the
+// left update of k_track_frame.  The keyframes' pixel work shares one
+// launch, so a refinement step pays two launches instead of two per
+// keyframe.
+template <int STORAGE>
+__global__ __launch_bounds__(kTrackBlock) void k_gn_partials(MapView M, TrackArgs a, const double* poses,
+                                                            double* partials) {
+    __shared__ ReduceLds red;
+    constexpr bool COMP = STORAGE == GSDF_BF16 || STORAGE == GSDF_FP16;
+    const int k = blockIdx.y;
+    double P[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) P[i] = poses[12 * k + i];
+    TrackLevel L = a.lv[0];
+    const int npx = L.W * L.H;
+    L.depth += (size_t)k * npx;
+    float acc[kNE], cmp[kNE];
+    if (pose_finite(P)) {
+        accumulate<STORAGE>(M, L, a, P, blockIdx.x * kTrackBlock + threadIdx.x, gridDim.x * kTrackBlock, npx,
+                            nullptr, acc, cmp);
+    } else {
+        // the solve leaves this keyframe as it is and reports it
+#pragma unroll
+        for (int e = 0; e < kNE; ++e) acc[e] = cmp[e] = 0.0f;
+    }
+    store_partial<COMP>(acc, cmp, partials + ((size_t)k * gridDim.x + blockIdx.x) * kPartStride, red);
+}
+
+template <int STORAGE>
+__global__ __launch_bounds__(kTrackBlock) void k_gn_solve(MapView M, double* poses, const double* partials,
+                                                         int groups, double damping, float min_inlier_frac,
+                                                         int32_t* status) {
+    __shared__ ReduceLds red;
+    __shared__ double s_pose[12];
+    constexpr bool COMP = STORAGE == GSDF_BF16 || STORAGE == GSDF_FP16;
+    const int k = blockIdx.x;
+    if (threadIdx.x < 12) s_pose[threadIdx.x] = poses[12 * k + threadIdx.x];
+    __syncthreads();
+    if (!pose_finite(s_pose)) {   // the same pose for every thread: a uniform exit
+        if (threadIdx.x == 0) raise_status(status, GSDF_EINVAL);
+        return;
+    }
+    double ne[kNE];
+    total_partials<COMP>(partials + (size_t)k * groups * kPartStride, groups, ne, red);
+    if (threadIdx.x < 64) {
+        const bool solved = solve_update_wave(red.tot, damping, s_pose);
+        if (threadIdx.x == 0) {
+            const double* t = red.tot;
+            if (!solved) raise_status(status, GSDF_ENOTPD);
+            if (t[28] < (double)min_inlier_frac * t[29]) raise_status(status, GSDF_ELOST);
+            add_stat(M, kStatTrackValid, (unsigned long long)t[29]);
+            add_stat(M, kStatTrackUsed, (unsigned long long)t[28]);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 12) poses[12 * k + threadIdx.x] = s_pose[threadIdx.x];
+}
+
 // All pyramid levels in one launch, each by the 2x2 rule in binary32: the
 // mean of four valid depths whose spread is within the truncation, else 0.
 // A work-group covers a 16x16 tile of level 1 (from level 0 in global
@@ -1254,6 +1317,9 @@ inline ScratchLayout scratch_layout(const gsdf_camera& c, int levels) {
     s.total = o;
     return s;
 }
+
+// Keyframes of one batched Gauss-Newton step (the grid's y extent).
+constexpr int kMaxGnKeyframes = 65535;
 
 inline int normal_eq_groups(int npx) {
     int g = ceil_div(npx, kTrackBlock * 2);   // about two pixels per thread
@@ -1510,6 +1576,63 @@ extern "C" int gsdf_normal_equations(const gsdf_map* map, const float* depth_dev
         case GSDF_FP32: k_normal_equations<GSDF_FP32><<<g, kTrackBlock, 0, s>>>(M, a, T_wc_dev, partials, sync, out29_dev); break;
         case GSDF_BF16: k_normal_equations<GSDF_BF16><<<g, kTrackBlock, 0, s>>>(M, a, T_wc_dev, partials, sync, out29_dev); break;
         default: k_normal_equations<GSDF_FP16><<<g, kTrackBlock, 0, s>>>(M, a, T_wc_dev, partials, sync, out29_dev); break;
+    }
+    return launch_status();
+}
+
+extern "C" size_t gsdf_gn_scratch_bytes(const gsdf_camera* cam, int32_t n_keyframes) {
+    if (!valid_cam(cam) || n_keyframes <= 0 || n_keyframes > kMaxGnKeyframes) return 0;
+    return align256((size_t)n_keyframes * normal_eq_groups(cam->width * cam->height) * kPartStride *
+                    sizeof(double));
+}
+
+extern "C" int gsdf_gn_step_keyframes(const gsdf_map* map, const float* depth_dev, int32_t n_keyframes,
+                                      const gsdf_camera* cam, double* T_dev, float huber_delta, double damping,
+                                      float min_inlier_frac, void* scratch_dev, size_t scratch_bytes,
+                                      int32_t* status_dev, void* stream) {
+    if (!valid_map(map) || !depth_dev || !valid_cam(cam) || !T_dev || !scratch_dev || !status_dev)
+        return GSDF_EINVAL;
+    if (n_keyframes <= 0 || n_keyframes > kMaxGnKeyframes) return GSDF_EINVAL;
+    if (!(huber_delta > 0.0f) || !(damping >= 0.0)) return GSDF_EINVAL;
+    if (!has_gradients(map)) return GSDF_EINVAL;
+    if (scratch_bytes < gsdf_gn_scratch_bytes(cam, n_keyframes)) return GSDF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const ScratchLayout sl = scratch_layout(*cam, 1);
+    TrackArgs a;
+    fill_levels(*cam, depth_dev, sl, nullptr, 1, &a);
+    a.levels = 1;
+    for (int l = 0; l < 4; ++l) a.iters[l] = l == 0 ? 1 : 0;
+    a.zmin = cam->zmin;
+    a.zmax = cam->zmax;
+    a.delta = huber_delta;
+    a.inv_vs = 1.0 / map->desc.voxel_size;
+    a.vs = map->desc.voxel_size;
+    a.damping = damping;
+    a.min_inlier_frac = min_inlier_frac;
+    a.tag_polls = kTagPolls;
+    a.join_polls = kJoinPolls;
+    a.clocks = nullptr;
+    a.device_scope = 1;
+    const int g = normal_eq_groups(cam->width * cam->height);
+    const dim3 grid(g, n_keyframes);
+    double* partials = (double*)scratch_dev;
+    const MapView M = make_view(*map);
+    switch (map->desc.storage) {
+        case GSDF_FP32:
+            k_gn_partials<GSDF_FP32><<<grid, kTrackBlock, 0, s>>>(M, a, T_dev, partials);
+            k_gn_solve<GSDF_FP32><<<n_keyframes, kTrackBlock, 0, s>>>(M, T_dev, partials, g, damping, min_inlier_frac,
+                                                                     status_dev);
+            break;
+        case GSDF_BF16:
+            k_gn_partials<GSDF_BF16><<<grid, kTrackBlock, 0, s>>>(M, a, T_dev, partials);
+            k_gn_solve<GSDF_BF16><<<n_keyframes, kTrackBlock, 0, s>>>(M, T_dev, partials, g, damping, min_inlier_frac,
+                                                                     status_dev);
+            break;
+        default:
+            k_gn_partials<GSDF_FP16><<<grid, kTrackBlock, 0, s>>>(M, a, T_dev, partials);
+            k_gn_solve<GSDF_FP16><<<n_keyframes, kTrackBlock, 0, s>>>(M, T_dev, partials, g, damping, min_inlier_frac,
+                                                                     status_dev);
+            break;
     }
     return launch_status();
 }

@@ -218,6 +218,31 @@ class GsdfMap:
                                                  scratch.numel(), _ptr(self.status), _stream()),
                    "track_frame")
 
+    def gn_step_keyframes(self, depth: torch.Tensor, cam, poses: torch.Tensor, delta: float = 0.01,
+                          damping: float = 1e-6, min_inlier_frac: float = 0.1) -> None:
+        """One damped Gauss-Newton step at full resolution for each keyframe
+        (``depth`` (K, H, W) float32, ``poses`` (K, 3, 4) float64, updated in
+        place): the step of ``track(..., levels=1, iters=(1,))`` for all
+        keyframes in two launches (sums in another fixed order, so equal to
+        the per-keyframe calls to rounding)."""
+        c = camera(cam)
+        if depth.dim() != 3:
+            raise ValueError("depth must be (K, H, W)")
+        K = depth.shape[0]
+        _need(depth, torch.float32, (K, c.height, c.width), "depth")
+        _need(poses, torch.float64, (K, 3, 4), "poses")
+        key = ("gn", c.width, c.height, K)
+        if key not in self._scratch:
+            n = _lib.load().gsdf_gn_scratch_bytes(C.byref(c), K)
+            if n == 0:
+                raise ValueError("invalid keyframe count for the Gauss-Newton step")
+            self._scratch[key] = torch.empty(int(n), dtype=torch.uint8, device=self.device)
+        scratch = self._scratch[key]
+        _lib.check(_lib.load().gsdf_gn_step_keyframes(C.byref(self._map), _ptr(depth), K, C.byref(c), _ptr(poses),
+                                                      float(delta), float(damping), float(min_inlier_frac),
+                                                      _ptr(scratch), scratch.numel(), _ptr(self.status), _stream()),
+                   "gn_step_keyframes")
+
     def normal_equations(self, depth: torch.Tensor, cam, pose: torch.Tensor, delta: float) -> torch.Tensor:
         c = camera(cam)
         _need(depth, torch.float32, (c.height, c.width), "depth")
@@ -690,7 +715,7 @@ def refine_joint(gmap: GsdfMap, depth: torch.Tensor, rgb: torch.Tensor, cam, T0:
     voxel parameters and colours (gradients from both adjoint kernels), then
     updates the poses: ``pose_solver="gn"`` writes the parameters into the
     map (rounded to its storage format) and takes one Gauss-Newton
-    iteration of the tracking kernel per keyframe on the updated map;
+    iteration per keyframe on the updated map (gn_step_keyframes);
     ``"adam"`` moves camera-frame pose variables by Adam on the joint loss.
     Colours start from the Eq. (21) mean at the initial poses.  The default
     photometric weight (delta / photo_delta)^2 prices a residual at either
@@ -737,8 +762,7 @@ def refine_joint(gmap: GsdfMap, depth: torch.Tensor, rgb: torch.Tensor, cam, T0:
         losses.append(loss.detach())
         if pose_solver == "gn":
             gmap.import_params(params.detach())
-            for i in range(K):
-                gmap.track(depth[i], cam, T[i], levels=1, iters=(1,), delta=delta)
+            gmap.gn_step_keyframes(depth, cam, T, delta=delta)
     if pose_solver == "adam":
         T = compose_left((ad @ xc.detach().unsqueeze(-1)).squeeze(-1), T0)
     if write_back:
