@@ -466,7 +466,7 @@ def refine_keyframes(gmap: GsdfMap, depth: torch.Tensor, cam, T0: torch.Tensor, 
     groups = [{"params": [xc], "lr": lr_pose}]
     if lr_geom > 0:
         groups.append({"params": [params], "lr": lr_geom})
-    opt = torch.optim.Adam(groups)
+    opt = torch.optim.Adam(groups, fused=depth.is_cuda)
     sched = torch.optim.lr_scheduler.CosineAnnealingLR(opt, steps)
     losses = []
     for _ in range(steps):
@@ -650,7 +650,7 @@ def photometric_ba(gmap: GsdfMap, depth: torch.Tensor, rgb: torch.Tensor, cam, T
     groups = [{"params": [xc], "lr": lr_pose}]
     if optimise_psi:
         groups.append({"params": [params], "lr": lr_psi})
-    opt = torch.optim.Adam(groups)
+    opt = torch.optim.Adam(groups, fused=depth.is_cuda)
     sched = torch.optim.lr_scheduler.CosineAnnealingLR(opt, steps)
     losses = []
     for _ in range(steps):
@@ -739,7 +739,8 @@ def refine_joint(gmap: GsdfMap, depth: torch.Tensor, rgb: torch.Tensor, cam, T0:
         groups.append({"params": [xc], "lr": lr_pose})
     elif pose_solver != "gn":
         raise ValueError("pose_solver must be 'gn' or 'adam'")
-    opt = torch.optim.Adam(groups)
+    # PyTorch's fused Adam: one kernel per parameter group and dtype a step
+    opt = torch.optim.Adam(groups, fused=depth.is_cuda)
     sched = torch.optim.lr_scheduler.CosineAnnealingLR(opt, steps)
     losses = []
     for _ in range(steps):
