@@ -213,13 +213,18 @@ __device__ inline void accumulate(const MapView& M, const TrackLevel& L, const T
             else
                 rec16[j] = reinterpret_cast<const ushort4*>(M.vox)[vi[j]];
         }
-        // ---- stage 4: residuals and sums
+        // ---- stage 4: residuals and sums.  The three quotients (psi, the
+        // normalisation of the gradient, the Huber weight) take the hardware
+        // reciprocal and reciprocal square root (1 ulp) instead of the
+        // correctly rounded sequences, which are about ten dependent
+        // instructions each on every pixel's path.  |g|^2 below the smallest
+        // normal float (|g| < 1.1e-19) counts as no gradient.
 #pragma unroll
         for (int j = 0; j < B; ++j) {
             if (!live[j] || !(Wv[j] > 0.0f)) continue;
             float psi, g0, g1, g2;
             if (STORAGE == GSDF_FP32) {
-                psi = rec32[j].x / Wv[j];
+                psi = rec32[j].x * __builtin_amdgcn_rcpf(Wv[j]);
                 g0 = rec32[j].y;
                 g1 = rec32[j].z;
                 g2 = rec32[j].w;
@@ -230,14 +235,14 @@ __device__ inline void accumulate(const MapView& M, const TrackLevel& L, const T
                 g2 = unpack16(rec16[j].w, STORAGE);
             }
             const float n2 = g0 * g0 + g1 * g1 + g2 * g2;
-            if (!(n2 > 0.0f)) continue;
-            const float inv = 1.0f / sqrtf(n2);
+            if (!(n2 >= 0x1p-126f)) continue;
+            const float inv = __builtin_amdgcn_rsqf(n2);
             const float gh[3] = {g0 * inv, g1 * inv, g2 * inv};
             const float r = psi + gh[0] * qr[j][0] + gh[1] * qr[j][1] + gh[2] * qr[j][2];
             const float J[6] = {gh[0], gh[1], gh[2], qf[j][1] * gh[2] - qf[j][2] * gh[1],
                                 qf[j][2] * gh[0] - qf[j][0] * gh[2], qf[j][0] * gh[1] - qf[j][1] * gh[0]};
             const float ar = fabsf(r);
-            const float w = ar <= a.delta ? 1.0f : a.delta / ar;
+            const float w = ar <= a.delta ? 1.0f : a.delta * __builtin_amdgcn_rcpf(ar);
             const float en = ar <= a.delta ? 0.5f * r * r : a.delta * (ar - 0.5f * a.delta);
             int k = 0;
 #pragma unroll
