@@ -442,7 +442,11 @@ __device__ inline void accumulate_trilinear(const MapView& M, const TrackLevel& 
 // doubles would chain ~180 dependent LDS permutes per wave.)  Each entry's
 // row is 8 chunks of kRedChunk values, kRedPad floats apart, so that the 8
 // lanes of one 16-byte read pass (the 8 chunks of an entry) fall in
-// different banks.  The plain path adds in float64; the precision form
+// different banks.  The plain path adds each chunk (one wave's values) by a
+// pairwise tree in float32 and the 8 chunk sums by a pairwise tree in
+// float64: the serial float64 chain it replaces (64 conversions and adds per
+// thread, then 8 more adds) was the longest dependent sequence of the sum
+// (measured: 4 us less per tracking launch at 640x480).  The precision form
 // (COMP) uses compensated float32 at every stage.  The storing threads are
 // lanes of wave 0, so thread 0 (which takes the arrival ticket, where there
 // is one) waits for their completion before signalling.
@@ -493,11 +497,15 @@ __device__ inline void store_partial(const float acc[kNE], const float cmp[kNE],
             }
             r.part[k][p] = (double)ks.value();
         } else {
-            double s = 0.0;
+            float t[kRedChunk / 4];
 #pragma unroll
-            for (int j = 0; j < kRedChunk / 4; ++j)
-                s += ((double)q[j].x + (double)q[j].y) + ((double)q[j].z + (double)q[j].w);
-            r.part[k][p] = s;
+            for (int j = 0; j < kRedChunk / 4; ++j) t[j] = (q[j].x + q[j].y) + (q[j].z + q[j].w);
+#pragma unroll
+            for (int w = kRedChunk / 8; w >= 1; w /= 2) {
+#pragma unroll
+                for (int j = 0; j < w; ++j) t[j] = t[j] + t[j + w];
+            }
+            r.part[k][p] = (double)t[0];
         }
     }
     __syncthreads();
@@ -509,8 +517,15 @@ __device__ inline void store_partial(const float acc[kNE], const float cmp[kNE],
             for (int p = 0; p < 8; ++p) ks.add((float)r.part[threadIdx.x][p]);
             s = (double)ks.value();
         } else {
+            double t[8];
 #pragma unroll
-            for (int p = 0; p < 8; ++p) s += r.part[threadIdx.x][p];
+            for (int p = 0; p < 8; ++p) t[p] = r.part[threadIdx.x][p];
+#pragma unroll
+            for (int w = 4; w >= 1; w /= 2) {
+#pragma unroll
+                for (int j = 0; j < w; ++j) t[j] = t[j] + t[j + w];
+            }
+            s = t[0];
         }
         if (tag && local)
             __hip_atomic_store(reinterpret_cast<unsigned long long*>(&partial[threadIdx.x]), tag_word(s, tag),
