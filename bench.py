@@ -67,9 +67,9 @@ B_ALLOC_PAIR = 16.0
 # values they had when the counters were taken.
 MEASURED_TRAFFIC = {
     "track": {
-        "bytes": 8639004,
+        "bytes": 8625789,
         "sources": {
-            "gsdf_track.hip": "ab8d2d722868127c8acba5159a6da98e0200e85a29bb3aa18a69c6d6c7e0e635",
+            "gsdf_track.hip": "50b13ae4a37fdcfe8003a474f323331b27e19dec5977a7eb731c5596f050c5c9",
             "gsdf_common.hpp": "5b726ce79643b29c9a682a0b6bcd966907429c824ecb04562facf2ef58d23989",
             "gsdf_host.hpp": "699a644f6155d591caffb7f5edc3cd6c971c32bc580d070b327d1d31c947ff6e",
             "gsdf_se3.hpp": "13c15ea94701e1129da7175cf338be9aa9cc57bf8857172577cef813f6209733"

@@ -442,11 +442,16 @@ __device__ inline void accumulate_trilinear(const MapView& M, const TrackLevel& 
 // doubles would chain ~180 dependent LDS permutes per wave.)  Each entry's
 // row is 8 chunks of kRedChunk values, kRedPad floats apart, so that the 8
 // lanes of one 16-byte read pass (the 8 chunks of an entry) fall in
-// different banks.  The plain path adds each chunk (one wave's values) by a
-// pairwise tree in float32 and the 8 chunk sums by a pairwise tree in
-// float64: the serial float64 chain it replaces (64 conversions and adds per
-// thread, then 8 more adds) was the longest dependent sequence of the sum
-// (measured: 4 us less per tracking launch at 640x480).  The precision form
+// different banks.  The plain path adds each chunk (one wave's values) four
+// at a time in float32, then those sums and the 8 chunk sums by pairwise
+// trees in float64: the serial float64 chain it replaces (64 conversions
+// and adds per thread, then 8 more adds) was the longest dependent sequence
+// of the sum (measured: 3.5 us less per tracking launch at 640x480).  A
+// float32 tree over a whole chunk is 0.6 us faster still but loses what
+// float64 keeps: where a thread holds a single pixel its sums are exact
+// products, and on an ill-conditioned system (a sphere, whose rotations
+// about its centre leave the residuals unchanged) the tracked centre moved
+// 40 times further from the float64 oracle's.  The precision form
 // (COMP) uses compensated float32 at every stage.  The storing threads are
 // lanes of wave 0, so thread 0 (which takes the arrival ticket, where there
 // is one) waits for their completion before signalling.
@@ -497,15 +502,15 @@ __device__ inline void store_partial(const float acc[kNE], const float cmp[kNE],
             }
             r.part[k][p] = (double)ks.value();
         } else {
-            float t[kRedChunk / 4];
+            double t[kRedChunk / 4];
 #pragma unroll
-            for (int j = 0; j < kRedChunk / 4; ++j) t[j] = (q[j].x + q[j].y) + (q[j].z + q[j].w);
+            for (int j = 0; j < kRedChunk / 4; ++j) t[j] = (double)((q[j].x + q[j].y) + (q[j].z + q[j].w));
 #pragma unroll
             for (int w = kRedChunk / 8; w >= 1; w /= 2) {
 #pragma unroll
                 for (int j = 0; j < w; ++j) t[j] = t[j] + t[j + w];
             }
-            r.part[k][p] = (double)t[0];
+            r.part[k][p] = t[0];
         }
     }
     __syncthreads();
