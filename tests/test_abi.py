@@ -58,6 +58,30 @@ def test_host_side_validation_without_gpu():
     assert lib.gsdf_status_string(_lib.ECAPACITY) == b"hash table or block pool full"
 
 
+def test_batched_gauss_newton_validates_without_gpu():
+    """gsdf_gn_scratch_bytes: a float64 partial of 32 words per work-group
+    and keyframe, a work-group per 4096 pixels (at least 1, at most 2048),
+    rounded up to 256 bytes; 0 for K outside 1..65535.  gsdf_gn_step_keyframes
+    refuses null buffers and bad parameters before any launch."""
+    from paper_2111_13652_amd import _lib
+    lib = _lib.load()
+    cam = _lib.Camera(525.0, 525.0, 319.5, 239.5, 640, 480, 0.4, 4.0)
+    groups = -(-640 * 480 // 4096)
+    assert lib.gsdf_gn_scratch_bytes(C.byref(cam), 30) == -(-30 * groups * 32 * 8 // 256) * 256
+    assert lib.gsdf_gn_scratch_bytes(C.byref(cam), 1) == -(-groups * 32 * 8 // 256) * 256
+    assert lib.gsdf_gn_scratch_bytes(C.byref(cam), 0) == 0
+    assert lib.gsdf_gn_scratch_bytes(C.byref(cam), 65536) == 0
+    assert lib.gsdf_gn_scratch_bytes(None, 1) == 0
+    tiny = _lib.Camera(100.0, 100.0, 3.5, 3.5, 8, 8, 0.4, 4.0)
+    assert lib.gsdf_gn_scratch_bytes(C.byref(tiny), 2) == 2 * 1 * 32 * 8
+    big = _lib.Camera(1000.0, 1000.0, 1023.5, 1023.5, 2048, 2048, 0.4, 4.0)
+    assert lib.gsdf_gn_scratch_bytes(C.byref(big), 1) == 1024 * 32 * 8
+    huge = _lib.Camera(1000.0, 1000.0, 2047.5, 2047.5, 4096, 4096, 0.4, 4.0)
+    assert lib.gsdf_gn_scratch_bytes(C.byref(huge), 1) == 2048 * 32 * 8
+    assert lib.gsdf_gn_step_keyframes(None, None, 1, C.byref(cam), None, 0.01, 1e-6, 0.1, None, 0, None,
+                                      None) == _lib.EINVAL
+
+
 def test_voxel_order_and_differentiable_calls_validate_without_gpu():
     import numpy as np
     from paper_2111_13652_amd import _lib
