@@ -376,8 +376,10 @@ __device__ inline void accumulate_trilinear(const MapView& M, const TrackLevel& 
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 all = all && cw[j][k] > 0.0f;
+                // the Taylor model's hardware reciprocal (a corner with W = 0
+                // gives inf or NaN here and is dropped below)
                 c[k] = (STORAGE == GSDF_FP32 || STORAGE == GSDF_NOGRAD_FP32)
-                           ? __uint_as_float(craw[j][k]) / cw[j][k]
+                           ? __uint_as_float(craw[j][k]) * __builtin_amdgcn_rcpf(cw[j][k])
                            : unpack16((unsigned short)craw[j][k], STORAGE) * M.truncation;
             }
             if (!all) continue;
@@ -399,7 +401,7 @@ __device__ inline void accumulate_trilinear(const MapView& M, const TrackLevel& 
             const float J[6] = {g[0], g[1], g[2], qf[j][1] * g[2] - qf[j][2] * g[1],
                                 qf[j][2] * g[0] - qf[j][0] * g[2], qf[j][0] * g[1] - qf[j][1] * g[0]};
             const float ar = fabsf(r);
-            const float w = ar <= a.delta ? 1.0f : a.delta / ar;
+            const float w = ar <= a.delta ? 1.0f : a.delta * __builtin_amdgcn_rcpf(ar);
             const float en = ar <= a.delta ? 0.5f * r * r : a.delta * (ar - 0.5f * a.delta);
             int k = 0;
 #pragma unroll
