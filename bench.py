@@ -69,7 +69,7 @@ MEASURED_TRAFFIC = {
     "track": {
         "bytes": 8625789,
         "sources": {
-            "gsdf_track.hip": "cf6f968aea870a0da9578922ebdbe8c548236945ec57c80869d9ccb513facfff",
+            "gsdf_track.hip": "7b0a13691000a5ba70cd6c2ebde83f0613147e67476830c5ff11efeacefeb93d",
             "gsdf_common.hpp": "5b726ce79643b29c9a682a0b6bcd966907429c824ecb04562facf2ef58d23989",
             "gsdf_host.hpp": "699a644f6155d591caffb7f5edc3cd6c971c32bc580d070b327d1d31c947ff6e",
             "gsdf_se3.hpp": "13c15ea94701e1129da7175cf338be9aa9cc57bf8857172577cef813f6209733"

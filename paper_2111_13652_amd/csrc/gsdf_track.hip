@@ -8,9 +8,10 @@
 // Gauss-Newton iteration of every level.  In an iteration each thread walks a strided
 // set of pixels and accumulates, in float32 registers, the 21 upper entries
 // of H = sum w J J^T, the 6 of b = sum w J r, the energy, the count of
-// pixels used and the count of valid pixels.  From there every sum is
-// float64: LDS across the waves of a work-group, then one partial per
-// work-group, then one sum per leaf, a leaf being up to 16 work-groups that
+// pixels used and the count of valid pixels.  Four threads' values are
+// added once more in float32; from there every sum is float64: LDS across
+// the waves of a work-group, then one partial per work-group, then one sum
+// per leaf, a leaf being up to 16 work-groups that
 // run on one XCD (added by the first work-group of the leaf once every
 // partial of the leaf carries the iteration's tag; the partials stay in
 // that XCD's L2).  Every work-group then reads the leaf sums the same
