@@ -8,7 +8,6 @@ away from the true sphere gradient, and distances against the analytic
 scene distance of the generator.  The last test reproduces the paper's
 finding in kind on a small noisy five-sphere stream."""
 import numpy as np
-import pytest
 
 import oracle
 from paper_2111_13652_amd import synth

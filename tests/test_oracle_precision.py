@@ -1,6 +1,5 @@
 """Oracle pins for the reduced-precision (bf16 / fp16) storage emulation."""
 import numpy as np
-import pytest
 import torch
 
 import oracle

@@ -2,7 +2,6 @@
 points lie on the plane and the selection is the brute-force set of cells
 (subcells) whose centre is within half a cell of it; on a sphere the points
 stay close to the surface with outward normals."""
-import math
 
 import numpy as np
 

@@ -2,7 +2,6 @@
 SE(3) update (Sec. 5.1), the depth pyramid, and the adjoint of the keyframe
 Huber loss.  References are textbook routines (scipy), finite differences,
 invariances and an exactly solvable rendering."""
-import math
 
 import numpy as np
 import pytest

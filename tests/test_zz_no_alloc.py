@@ -5,7 +5,6 @@ smaller image, each bit-identical to the scratch-argument call.  Needs an
 MI355X."""
 import ctypes as C
 
-import numpy as np
 import pytest
 
 from paper_2111_13652_amd import synth
