@@ -108,8 +108,9 @@ def _parse():
     ap.add_argument("--steps", type=int, default=89)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-frames", type=int, default=12,
-                    help="frames of the stream the oracle runs for the CPU baseline")
+    ap.add_argument("--cpu-frames", type=int, default=27,
+                    help="frames of the stream the oracle runs for the CPU baseline (27: about 12 s "
+                         "on a recent server core, 10-30 s on most)")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--no-h2d", action="store_true", help="skip the PCIe-inclusive pass")
     ap.add_argument("--no-full", action="store_true", help="skip the three full-stream passes")
