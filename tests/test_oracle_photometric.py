@@ -50,7 +50,7 @@ def test_mean_colour_samples_the_surface_point_of_eq18(setup):
                             st.poses[idx], xi, keys)
     p, v = _surface_points(M, keys)
     psi = M.voxels(keys)[0]
-    # the room's walls pass through voxel centres (psi ~ 0 there): judge the
+    # the room's walls pass through voxel centres (psi ~ 0 there): assess the
     # voxels whose surface point is well away from the centre
     seen = (cnt > 0) & (np.abs(psi) > VS / 8)
     # and where the fused gradient agrees with the true normal: at concave
